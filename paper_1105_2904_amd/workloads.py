@@ -1,0 +1,143 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module holds no lattice Boltzmann arithmetic: it only draws particle
+placements and random populations from a counter-free SplitMix64 stream, and
+fills in the particle records (mass and moment of inertia of a uniform disk
+or sphere of the given density ratio).  Both the GPU path and the oracle are
+fed from here; neither is called from here.
+
+Placement is random sequential addition in a periodic box: draw a centre
+uniformly, reject it if its surface comes closer than ``min_gap`` lattice
+units to an accepted particle (minimum image), up to ``max_tries`` draws per
+particle.
+"""
+import math
+
+import numpy as np
+
+_MASK = (1 << 64) - 1
+
+
+class SplitMix64:
+    """SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): 64-bit state, golden-gamma
+    increment, two xor-shift-multiply finalisation rounds."""
+
+    def __init__(self, seed):
+        self.state = seed & _MASK
+
+    def next_u64(self):
+        self.state = (self.state + 0x9E3779B97F4A7C15) & _MASK
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK
+        return z ^ (z >> 31)
+
+    def uniform(self):
+        """Double in [0, 1) from the top 53 bits."""
+        return (self.next_u64() >> 11) * (1.0 / (1 << 53))
+
+    def uniform_array(self, n):
+        return np.array([self.uniform() for _ in range(n)])
+
+    def randint(self, lo, hi):
+        """Integer in [lo, hi] (inclusive)."""
+        return lo + int(self.uniform() * (hi - lo + 1))
+
+
+def place_particles(box, radii, seed, min_gap=2.0, max_tries=10**6):
+    """Random sequential addition of particles of the given radii.
+
+    box: (nx, ny, nz) with nz == 1 for 2D.  Returns centres [n][3] (z = 0 in
+    2D), in [0, L) per axis.
+    """
+    rng = SplitMix64(seed)
+    dim = 2 if box[2] == 1 else 3
+    L = np.array(box, dtype=np.float64)
+    placed = []
+    rad = []
+    for r in radii:
+        for _ in range(max_tries):
+            c = np.zeros(3)
+            for a in range(dim):
+                c[a] = rng.uniform() * L[a]
+            ok = True
+            if placed:
+                P = np.array(placed)
+                d = P[:, :dim] - c[:dim]
+                d -= L[:dim] * np.floor(d / L[:dim] + 0.5)
+                dist = np.sqrt((d * d).sum(axis=1))
+                if np.any(dist < np.array(rad) + r + min_gap):
+                    ok = False
+            if ok:
+                placed.append(c)
+                rad.append(r)
+                break
+        else:
+            raise RuntimeError("could not place particle %d" % len(placed))
+    return np.array(placed).reshape(-1, 3)
+
+
+def solid_body(dim, radius, density_ratio, rho0=1.0):
+    """Mass and moment of inertia of a uniform disk (2D) or sphere (3D)."""
+    r = np.asarray(radius, dtype=np.float64)
+    if dim == 2:
+        m = density_ratio * rho0 * math.pi * r * r
+        inertia = 0.5 * m * r * r
+    else:
+        m = density_ratio * rho0 * (4.0 / 3.0) * math.pi * r ** 3
+        inertia = 0.4 * m * r * r
+    return m, inertia
+
+
+def random_populations(base, shape, seed, eps):
+    """Populations base[i] * (1 + eps * xi) with xi uniform in [-1, 1).
+
+    base: per-direction base values [q]; shape: (nz, ny, nx).  Returns
+    [q][nz][ny][nx] float64.
+    """
+    q = len(base)
+    n = q * int(np.prod(shape))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xi = rng.uniform(-1.0, 1.0, size=n).reshape((q,) + tuple(shape))
+    return np.asarray(base, dtype=np.float64).reshape((q, 1, 1, 1)) * (1.0 + eps * xi)
+
+
+def suspension(q, box, n, radius, density_ratio, seed, min_gap=2.0, rho0=1.0):
+    """Particle records for n equal particles at seeded random positions."""
+    dim = 2 if q == 9 else 3
+    radii = np.full(n, float(radius))
+    x = place_particles(box, radii, seed, min_gap=min_gap)
+    m, inertia = solid_body(dim, radii, density_ratio, rho0)
+    return {"x": x, "u": np.zeros((n, 3)), "omega": np.zeros((n, 3)),
+            "radius": radii, "mass": np.asarray(m, dtype=np.float64),
+            "inertia": np.asarray(inertia, dtype=np.float64)}
+
+
+def kinematic_disk_config():
+    """D2Q9, tau 0.8, 64x64 periodic, one disk of radius 8 at the centre moving
+    with imposed velocity (0.01, 0); FP64; 1000 steps."""
+    return {"name": "d2q9-64x64-kinematic-disk", "q": 9, "box": (64, 64, 1),
+            "tau": 0.8, "rho0": 1.0, "gravity": (0.0, 0.0, 0.0),
+            "zero_net_force": False, "storage": "fp64", "steps": 1000,
+            "particles": {"x": np.array([[32.0, 32.0, 0.0]]),
+                          "u": np.array([[0.01, 0.0, 0.0]]),
+                          "omega": np.zeros((1, 3)), "radius": np.array([8.0]),
+                          "mass": np.array([np.inf]), "inertia": np.array([np.inf])}}
+
+
+def disks_2d_config(seed=1):
+    """D2Q9, tau 0.7, 1024x1024 periodic, 200 disks of radius 10, density ratio
+    1.5, gravity 1e-5; FP32; 10000 steps."""
+    return {"name": "d2q9-1024x1024-200-disks", "q": 9, "box": (1024, 1024, 1),
+            "tau": 0.7, "rho0": 1.0, "gravity": (0.0, -1e-5, 0.0),
+            "zero_net_force": True, "storage": "fp32", "steps": 10000,
+            "particles": suspension(9, (1024, 1024, 1), 200, 10.0, 1.5, seed)}
+
+
+def spheres_3d_config(seed=2, storage="fp32"):
+    """D3Q19, tau 0.6, 256^3 periodic, 500 spheres of radius 6, density ratio
+    1.2, gravity 1e-6; FP32; 2000 steps."""
+    return {"name": "d3q19-256cubed-500-spheres", "q": 19, "box": (256, 256, 256),
+            "tau": 0.6, "rho0": 1.0, "gravity": (0.0, 0.0, -1e-6),
+            "zero_net_force": True, "storage": storage, "steps": 2000,
+            "particles": suspension(19, (256, 256, 256), 500, 6.0, 1.2, seed)}
