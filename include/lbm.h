@@ -1,0 +1,169 @@
+/*
+ * C ABI of the MI355X (gfx950) hot path of the site-based suspension lattice
+ * Boltzmann method of dos Santos & Philippi ("An alternative method for
+ * simulating particle suspensions using lattice Boltzmann").
+ *
+ * What one step computes (section 2, in the paper's order):
+ *   1. BGK collision at every site (eq. 1-3), plus a uniform fluid body force;
+ *   2. boundary-site (BS) substep: every BS site takes the equilibrium at the
+ *      particle's rigid-body velocity u_p + omega_p x r, and the momentum dp
+ *      and angular momentum dl this gives the fluid are summed per particle
+ *      (eq. 5-9);
+ *   3. particle acceleration by the opposite change plus the buoyancy-corrected
+ *      weight (eq. 10-11), then elastic hard-core collisions (eq. 16-19);
+ *   4. translation of the particle and its site sets (eq. 13-15);
+ *   5. internal-site (IS) substep at the new positions (eq. 12);
+ *   6. propagation (eq. 3).
+ * Where the paper is silent the library takes these readings: second-order
+ * equilibrium with c_s^2 = 1/3; D3Q19 for 3D; u = u_p + omega x r; rho kept
+ * per site in every imposition; BS/IS from the digitised ball |o - phi| <= r
+ * with the lattice's own links; nearest integer [x] = floor(x + 1/2) applied
+ * to the particle's shift; lowest particle id owns a site claimed twice;
+ * F_ext = (m - rho0 V) g with the analytic V.
+ *
+ * Conventions
+ *  - Lattice units: dx = dt = 1.  Every axis is periodic.
+ *  - Distribution layout (host buffers): f[q][nz][ny][nx], x fastest, plain f
+ *    (not deviations).  Velocity order:
+ *      D2Q9 : (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1)
+ *      D3Q19: (0,0,0) (1,0,0) (-1,0,0) (0,1,0) (0,-1,0) (0,0,1) (0,0,-1)
+ *             (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0) (1,0,1) (-1,0,-1)
+ *             (1,0,-1) (-1,0,1) (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1)
+ *  - Particle vectors are host arrays [n][3] of double.  In 2D the z
+ *    components are ignored (treated as 0) and angular velocity / torque use
+ *    component 2.
+ *  - Every call returns an int: LBM_OK (0) or a negative LBM_E* code.  No
+ *    call throws or aborts across the ABI.
+ *  - All device work is ordered on the caller's HIP stream given to
+ *    lbm_create.  lbm_step only enqueues; lbm_forces, lbm_fields,
+ *    lbm_get_distributions, lbm_site_kind, lbm_shifts and lbm_profile
+ *    synchronise that stream and report device-side anomalies.
+ *  - The library allocates no device memory: everything lives in the
+ *    caller-owned workspace, which must outlive the context.  A context is
+ *    used by one host thread at a time.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum lbm_lattice { LBM_D2Q9 = 9, LBM_D3Q19 = 19 };
+
+/* Storage precision of the distributions.  Distributions are stored as
+ * deviations f_i - w_i rho0.  FP64 computes in FP64; FP32 collides in FP32
+ * and performs the particle substeps (BS, IS), the per-particle sums and the
+ * Newton-Euler update in FP64.  FP16/BF16 are reserved. */
+enum lbm_storage { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16 = 2, LBM_BF16 = 3 };
+
+enum lbm_status {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,      /* invalid argument (checked on the host, before any HIP call) */
+  LBM_EWORKSPACE = -2,  /* workspace NULL, misaligned (256 B) or too small */
+  LBM_EHIP = -3,        /* a HIP runtime call or kernel launch failed */
+  LBM_EOVERLAP = -4,    /* new particle overlaps another particle */
+  LBM_ECAPACITY = -5,   /* more particles than max_particles */
+  LBM_ENONFINITE = -6,  /* non-finite input value */
+  LBM_EUNSUPPORTED = -7,/* storage mode not built */
+  LBM_ECOLLISION = -8   /* collision search bound exceeded: a particle speed
+                           >= 0.5 lu/step, or > 64 particles within r_i+r_j+1
+                           of one particle; results of that step are invalid */
+};
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef struct lbm_params {
+  int32_t lattice;       /* LBM_D2Q9 or LBM_D3Q19 */
+  int32_t nx, ny, nz;    /* box size; nz = 1 for D2Q9; nx*ny*nz < 2^31 */
+  double tau;            /* BGK relaxation time, > 1/2: nu = (tau - 1/2)/3 (eq. 4) */
+  double rho0;           /* initial fluid density and deviation base (> 0) */
+  double gravity[3];     /* acceleration on particles, lu/step^2 */
+  double body_force[3];  /* extra uniform force density on the fluid */
+  int32_t zero_net_force;/* 1: fluid also carries -sum_p F_ext,p / N per site */
+  int32_t storage;       /* enum lbm_storage */
+  int32_t max_particles; /* capacity (>= 0) */
+  double max_radius;     /* largest particle radius that will be added (0 < r <= 120) */
+} lbm_params;
+
+/* Bytes of device workspace lbm_create needs for these parameters. */
+int lbm_workspace_size(const lbm_params* prm, size_t* bytes);
+
+/* Create a context on a caller-owned device workspace (at least
+ * lbm_workspace_size bytes, 256-B aligned) and a caller-owned hipStream_t
+ * (NULL = the null stream).  The fluid starts at rest with density rho0:
+ * f_i = w_i rho0.  Parameters follow section 2.1 (lattice, tau) and the
+ * particle record of section 2.2. */
+int lbm_create(const lbm_params* prm, void* d_workspace, size_t bytes,
+               void* hip_stream, lbm_ctx** out);
+
+/* Append n particles (ids first_id ... first_id+n-1).  x: centres in
+ * [0, n_axis); u, omega: initial velocities (NULL = 0); radius in
+ * (0, max_radius]; mass, inertia > 0, or +INFINITY for a kinematic particle
+ * whose velocity is imposed (forces are still reported).  The particle record
+ * is that of section 2.2 (x_p, r_p, m_p, I_p, u_p, omega_p).  Rejects overlap
+ * with any particle (centre distance < r_i + r_j, minimum image).  Host
+ * arrays are read before the call returns. */
+int lbm_add_particles(lbm_ctx* ctx, int32_t n, const double* x, const double* u,
+                      const double* omega, const double* radius,
+                      const double* mass, const double* inertia,
+                      int32_t* first_id);
+
+/* Enqueue nsteps time steps (steps 1-6 above) on the context's stream. */
+int lbm_step(lbm_ctx* ctx, int32_t nsteps);
+
+/* Per particle: the last step's hydrodynamic force F = -dP and torque
+ * T = -dL (eq. 8-9; hydrodynamic only, without the weight and collisions),
+ * and the current centre x (unwrapped), velocity u and angular velocity
+ * omega.  Host arrays [n][3]; any may be NULL.  Synchronises. */
+int lbm_forces(lbm_ctx* ctx, double* F, double* T, double* x, double* u,
+               double* omega);
+
+/* Density rho[N], velocity u[N][3] (moments of the current post-propagation
+ * distributions, eq. 1-2) and the owner particle id of every BS/IS site
+ * (-1 elsewhere), N = nx*ny*nz, site index x + nx*(y + ny*z).  Any pointer
+ * may be NULL.  Synchronises. */
+int lbm_fields(lbm_ctx* ctx, double* rho, double* u, int32_t* owner);
+
+int lbm_destroy(lbm_ctx* ctx);
+const char* lbm_strerror(int code);
+
+/* ---- auxiliary calls (tests, checkpoints, measurement) ------------------ */
+
+/* Current post-propagation distributions f[q][N] (plain f). Synchronises. */
+int lbm_get_distributions(lbm_ctx* ctx, double* f);
+
+/* Replace the current post-propagation distributions by f[q][N] (plain f).
+ * Rounded to the storage precision.  Synchronises. */
+int lbm_set_distributions(lbm_ctx* ctx, const double* f);
+
+/* Site kind of the current map: 0 none, 1 BS, 2 IS (int8 [N]). Synchronises. */
+int lbm_site_kind(lbm_ctx* ctx, int8_t* kind);
+
+/* Integer shift k = [x - x0] of every particle, int32 [n][3]. Synchronises. */
+int lbm_shifts(lbm_ctx* ctx, int32_t* k);
+
+/* Particle count and template sizes (BS and IS entries) of particle p. */
+int lbm_particle_info(lbm_ctx* ctx, int32_t p, int32_t* nbs, int32_t* nis);
+
+/* Profiling: when on, lbm_step records a HIP event pair around every launch
+ * of the collide-and-stream sweep on the context's stream; lbm_profile
+ * returns the summed sweep time (ms) and launch count since profiling was
+ * switched on, and synchronises. */
+int lbm_set_profiling(lbm_ctx* ctx, int32_t on);
+int lbm_profile(lbm_ctx* ctx, double* sweep_ms, int64_t* sweeps);
+
+/* Algorithmic HBM bytes one sweep moves per site (2 q sizeof(storage)). */
+int lbm_bytes_per_site(const lbm_params* prm, int64_t* bytes);
+
+/* Plain device copy of `bytes` (multiple of 16, 16-B aligned pointers) on
+ * `hip_stream`: the bandwidth ceiling reference for the sweep. */
+int lbm_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1125 @@
+// MI355X (gfx950) hot path of the site-based suspension lattice Boltzmann
+// method of dos Santos & Philippi, behind the C ABI of include/lbm.h.
+//
+// One time step is five launches on the caller's stream:
+//   sweep      pull-stream + BGK collide (+ uniform body force) over every
+//              site, A -> B.  HBM bound: reads q and writes q populations per
+//              site, structure-of-arrays, x fastest, coalesced.            eq. 1-4
+//   boundary   one workgroup per particle: BS substep on the current map
+//              (impose f^eq(rho_B, u_p + omega x r), momentum dp and angular
+//              momentum dl per site, deterministic wave-shuffle + LDS sum per
+//              particle), clears the particle's stamps, and lists the
+//              particles close enough to collide this step.              eq. 5-9
+//   particles  one workgroup: Newton-Euler update with buoyancy-corrected
+//              weight, hard-core collisions in lexicographic pair order,
+//              translation and integer shift.               eq. 10-11, 13, 16-19
+//   stamp      rebuild the site -> particle map at the new shifts
+//              (atomicMin of the global entry index: lowest id wins).   eq. 14-15
+//   internal   IS substep at the new positions.                            eq. 12
+// The populations are stored as deviations g_i = f_i - w_i rho0 so that the
+// momentum differences behind the particle forces survive FP32 storage.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lattice.h"
+#include "lbm.h"
+
+namespace {
+
+constexpr int kEmpty = 0x7fffffff;  // map value of a site owned by no particle
+constexpr int kCandMax = 64;        // close neighbours listed per particle
+constexpr double kMargin = 1.0;     // candidate search margin (lattice units)
+constexpr int kSweepBlock = 256;
+constexpr int kBoundaryBlock = 256;
+constexpr int kParticleBlock = 1024;
+constexpr int kStatusCollision = 1;
+constexpr size_t kAlign = 256;
+
+// ---------------------------------------------------------------------------
+// Storage traits: compute type and load / streaming store of one population.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Store;
+template <>
+struct Store<double> {
+  using C = double;
+  static __device__ __forceinline__ double ld(const double* p) { return *p; }
+  static __device__ __forceinline__ void st(double* p, double v) { __builtin_nontemporal_store(v, p); }
+};
+template <>
+struct Store<float> {
+  using C = float;
+  static __device__ __forceinline__ float ld(const float* p) { return *p; }
+  static __device__ __forceinline__ void st(float* p, float v) { __builtin_nontemporal_store(v, p); }
+};
+
+struct Geo {
+  int nx, ny, nz;
+  int64_t N;
+};
+
+struct DevParticles {
+  double *x, *x0, *u, *om, *phi, *fext, *dP, *dL, *F, *T;  // [n][3]
+  double *m, *I, *rad;                                     // [n]
+  int *b0, *k;                                             // [n][3]
+  int *ent0, *nbs, *nis, *cand_n;                          // [n]
+  int *cand;                                               // [n][kCandMax]
+  int *pairs;                                              // [n*kCandMax][2]
+};
+
+struct DevEntries {
+  int* off;  // packed int8 offsets x,y,z and kind (1 BS, 2 IS) in the top byte
+  int* pid;  // owner particle
+};
+
+__host__ __device__ inline int pack_entry(int ox, int oy, int oz, int kind) {
+  return (ox & 0xff) | ((oy & 0xff) << 8) | ((oz & 0xff) << 16) | (kind << 24);
+}
+__device__ __forceinline__ int off_x(int v) { return (int)(int8_t)(v & 0xff); }
+__device__ __forceinline__ int off_y(int v) { return (int)(int8_t)((v >> 8) & 0xff); }
+__device__ __forceinline__ int off_z(int v) { return (int)(int8_t)((v >> 16) & 0xff); }
+__host__ __device__ __forceinline__ int entry_kind(int v) { return (v >> 24) & 0xff; }
+
+__device__ __forceinline__ int wrap(int v, int n) {
+  int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+// Site of a template offset at the particle's current shift b0 + k.
+__device__ __forceinline__ int entry_site(const DevParticles& P, const Geo& G, int p, int pk) {
+  const int x = wrap(P.b0[3 * p] + P.k[3 * p] + off_x(pk), G.nx);
+  const int y = wrap(P.b0[3 * p + 1] + P.k[3 * p + 1] + off_y(pk), G.ny);
+  const int z = wrap(P.b0[3 * p + 2] + P.k[3 * p + 2] + off_z(pk), G.nz);
+  return x + G.nx * (y + G.ny * z);
+}
+
+// ---------------------------------------------------------------------------
+// K1: fused pull-stream + BGK collision (eq. 1-3) over every site.
+// ---------------------------------------------------------------------------
+template <int Q, typename C>
+struct SweepArgs {
+  int nx, ny, nz, nxb;
+  int64_t N;
+  C omega;   // 1 / tau
+  C rho0;
+  C fbt[Q];  // 3 w_i c_i . f_b
+};
+
+template <int Q, typename T>
+__global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, T* __restrict__ B,
+                                                        SweepArgs<Q, typename Store<T>::C> a) {
+  using L = Lattice<Q>;
+  using C = typename Store<T>::C;
+  const int b = blockIdx.x;
+  const int row = b / a.nxb;
+  const int x = (b - row * a.nxb) * kSweepBlock + threadIdx.x;
+  if (x >= a.nx) return;
+  const int y = row % a.ny;
+  const int z = row / a.ny;
+  const int xm = x == 0 ? a.nx - 1 : x - 1, xp = x == a.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? a.ny - 1 : y - 1, yp = y == a.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? a.nz - 1 : z - 1, zp = z == a.nz - 1 ? 0 : z + 1;
+  const int s = x + a.nx * (y + a.ny * z);
+
+  C g[Q];
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    // pull: f_i(x, t+1) comes from x - c_i
+    const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
+    const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
+    const int sz = L::cz(i) > 0 ? zm : (L::cz(i) < 0 ? zp : z);
+    g[i] = Store<T>::ld(A + (size_t)i * a.N + (sx + a.nx * (sy + a.ny * sz)));
+  }
+  C drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    drho += g[i];
+    if (L::cx(i) > 0) jx += g[i];
+    if (L::cx(i) < 0) jx -= g[i];
+    if (L::cy(i) > 0) jy += g[i];
+    if (L::cy(i) < 0) jy -= g[i];
+    if (L::cz(i) > 0) jz += g[i];
+    if (L::cz(i) < 0) jz -= g[i];
+  }
+  const C rho = a.rho0 + drho;
+  const C inv = C(1) / rho;
+  const C ux = jx * inv, uy = jy * inv, uz = jz * inv;
+  const C usq = C(1.5) * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    const C cu = C(L::cx(i)) * ux + C(L::cy(i)) * uy + C(L::cz(i)) * uz;
+    const C geq = C(L::w(i)) * (drho + rho * (C(3) * cu + C(4.5) * cu * cu - usq));
+    Store<T>::st(B + (size_t)i * a.N + s, g[i] + a.omega * (geq - g[i]) + a.fbt[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic sums: butterfly within the 64-wide wave, then waves in order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// K2: BS substep (eq. 5-9), one workgroup per particle.
+// ---------------------------------------------------------------------------
+template <int Q, typename T>
+__global__ __launch_bounds__(kBoundaryBlock) void k_boundary(T* __restrict__ B, int* __restrict__ map,
+                                                              DevParticles P, DevEntries E, Geo G,
+                                                              int np, double rho0, int* status) {
+  using L = Lattice<Q>;
+  constexpr int kWaves = kBoundaryBlock / 64;
+  __shared__ double s_part[kWaves][6];
+  __shared__ int s_cnt[kWaves];
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const double phx = P.phi[3 * p], phy = P.phi[3 * p + 1], phz = P.phi[3 * p + 2];
+  const double upx = P.u[3 * p], upy = P.u[3 * p + 1], upz = P.u[3 * p + 2];
+  const double wx = P.om[3 * p], wy = P.om[3 * p + 1], wz = P.om[3 * p + 2];
+  const int e0 = P.ent0[p], nbs = P.nbs[p], nis = P.nis[p];
+
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int t = tid; t < nbs; t += kBoundaryBlock) {
+    const int e = e0 + t;
+    const int pk = E.off[e];
+    const int s = entry_site(P, G, p, pk);
+    if (map[s] != e) continue;  // owned by a lower id
+    map[s] = kEmpty;            // only the owner clears its site
+    double g[Q];
+    double drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+      g[i] = (double)B[(size_t)i * G.N + s];
+      drho += g[i];
+      jx += L::cx(i) * g[i];
+      jy += L::cy(i) * g[i];
+      jz += L::cz(i) * g[i];
+    }
+    const double rho = rho0 + drho;
+    const double ubx = jx / rho, uby = jy / rho, ubz = jz / rho;
+    // lever arm x_B - x_p = o - phi, constant while the site set translates
+    const double rx = (double)off_x(pk) - phx, ry = (double)off_y(pk) - phy,
+                 rz = (double)off_z(pk) - phz;
+    // u_B' = u_p + omega x r
+    const double vx = upx + (wy * rz - wz * ry);
+    const double vy = upy + (wz * rx - wx * rz);
+    const double vz = upz + (wx * ry - wy * rx);
+    const double dpx = rho * (vx - ubx), dpy = rho * (vy - uby), dpz = rho * (vz - ubz);
+    acc[0] += dpx;
+    acc[1] += dpy;
+    acc[2] += dpz;
+    acc[3] += ry * dpz - rz * dpy;
+    acc[4] += rz * dpx - rx * dpz;
+    acc[5] += rx * dpy - ry * dpx;
+    const double usq = 1.5 * (vx * vx + vy * vy + vz * vz);
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+      const double cu = L::cx(i) * vx + L::cy(i) * vy + L::cz(i) * vz;
+      B[(size_t)i * G.N + s] = (T)(L::w(i) * (drho + rho * (3.0 * cu + 4.5 * cu * cu - usq)));
+    }
+  }
+  for (int t = tid; t < nis; t += kBoundaryBlock) {
+    const int e = e0 + nbs + t;
+    const int s = entry_site(P, G, p, E.off[e]);
+    if (map[s] == e) map[s] = kEmpty;
+  }
+#pragma unroll
+  for (int c = 0; c < 6; c++) {
+    const double v = wave_sum(acc[c]);
+    if (lane == 0) s_part[wv][c] = v;
+  }
+  __syncthreads();
+  if (tid < 6) {
+    double v = 0;
+    for (int w = 0; w < kWaves; w++) v += s_part[w][tid];
+    if (tid < 3)
+      P.dP[3 * p + tid] = v;
+    else
+      P.dL[3 * p + tid - 3] = v;
+  }
+
+  // Close neighbours j > p (positions before translation), listed in
+  // increasing j: the only pairs that can pass the collision test this step
+  // while every speed stays below kMargin / 2 (checked in k_particles).
+  const double xpx = P.x[3 * p], xpy = P.x[3 * p + 1], xpz = P.x[3 * p + 2];
+  const double rp = P.rad[p];
+  int base = 0;
+  for (int j0 = p + 1; j0 < np; j0 += kBoundaryBlock) {
+    const int j = j0 + tid;
+    bool close = false;
+    if (j < np) {
+      double dx = P.x[3 * j] - xpx, dy = P.x[3 * j + 1] - xpy, dz = P.x[3 * j + 2] - xpz;
+      dx -= G.nx * floor(dx / G.nx + 0.5);
+      dy -= G.ny * floor(dy / G.ny + 0.5);
+      if (G.nz > 1) dz -= G.nz * floor(dz / G.nz + 0.5);
+      const double lim = rp + P.rad[j] + kMargin;
+      close = dx * dx + dy * dy + dz * dz <= lim * lim;
+    }
+    const unsigned long long bal = __ballot(close);
+    if (lane == 0) s_cnt[wv] = __popcll(bal);
+    __syncthreads();
+    int off = base;
+    int tot = 0;
+    for (int w = 0; w < kWaves; w++) {
+      if (w < wv) off += s_cnt[w];
+      tot += s_cnt[w];
+    }
+    if (close) {
+      const int idx = off + __popcll(bal & ((1ull << lane) - 1ull));
+      if (idx < kCandMax) P.cand[p * kCandMax + idx] = j;
+    }
+    base += tot;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    P.cand_n[p] = base < kCandMax ? base : kCandMax;
+    if (base > kCandMax) atomicOr(status, kStatusCollision);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K3: particle update, one workgroup (eq. 10-11, 16-19, 13).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kParticleBlock) void k_particles(DevParticles P, int np, int dim, Geo G,
+                                                              int* status) {
+  __shared__ int s_scan[kParticleBlock];
+  __shared__ double s_vmax[kParticleBlock / 64];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  double vmax = 0;
+  for (int p = tid; p < np; p += kParticleBlock) {
+    const double m = P.m[p], I = P.I[p];
+    double v2 = 0;
+    for (int a = 0; a < 3; a++) {
+      const double dp = P.dP[3 * p + a], dl = P.dL[3 * p + a];
+      P.F[3 * p + a] = -dp;
+      P.T[3 * p + a] = -dl;
+      double u = P.u[3 * p + a];
+      if (!isinf(m)) u = u + (P.fext[3 * p + a] - dp) / m;
+      P.u[3 * p + a] = u;
+      if (!isinf(I)) P.om[3 * p + a] = P.om[3 * p + a] - dl / I;
+      v2 += u * u;
+    }
+    vmax = fmax(vmax, sqrt(v2));
+  }
+  for (int o = 32; o > 0; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o));
+  if (lane == 0) s_vmax[wv] = vmax;
+
+  // lexicographic list of candidate pairs: exclusive scan of the counts
+  int total = 0;
+  for (int b = 0; b < np; b += kParticleBlock) {
+    const int p = b + tid;
+    const int c = p < np ? P.cand_n[p] : 0;
+    s_scan[tid] = c;
+    __syncthreads();
+    for (int off = 1; off < kParticleBlock; off <<= 1) {
+      const int v = tid >= off ? s_scan[tid - off] : 0;
+      __syncthreads();
+      s_scan[tid] += v;
+      __syncthreads();
+    }
+    const int excl = total + s_scan[tid] - c;
+    for (int t = 0; t < c; t++) {
+      P.pairs[2 * (excl + t)] = p;
+      P.pairs[2 * (excl + t) + 1] = P.cand[p * kCandMax + t];
+    }
+    total += s_scan[kParticleBlock - 1];
+    __syncthreads();
+  }
+
+  __syncthreads();
+  if (tid == 0) {
+    double vseen = 0;
+    for (int w = 0; w < kParticleBlock / 64; w++) vseen = fmax(vseen, s_vmax[w]);
+    const int L[3] = {G.nx, G.ny, G.nz};
+    for (int t = 0; t < total; t++) {
+      const int i = P.pairs[2 * t], j = P.pairs[2 * t + 1];
+      const bool infA = isinf(P.m[i]), infB = isinf(P.m[j]);
+      if (infA && infB) continue;
+      double d[3], dd = 0;
+      for (int a = 0; a < 3; a++) {
+        d[a] = (P.x[3 * j + a] + P.u[3 * j + a]) - (P.x[3 * i + a] + P.u[3 * i + a]);
+        if (a < dim) d[a] = d[a] - L[a] * floor(d[a] / L[a] + 0.5);
+        dd += d[a] * d[a];
+      }
+      const double dist = sqrt(dd);
+      if (dist > P.rad[i] + P.rad[j] || dist == 0.0) continue;
+      double n[3], vn = 0;
+      for (int a = 0; a < 3; a++) {
+        n[a] = d[a] / dist;
+        vn += (P.u[3 * j + a] - P.u[3 * i + a]) * n[a];
+      }
+      if (!(vn < 0.0)) continue;
+      double V[3];
+      const double mi = P.m[i], mj = P.m[j];
+      for (int a = 0; a < 3; a++) {
+        if (infA)
+          V[a] = P.u[3 * i + a];
+        else if (infB)
+          V[a] = P.u[3 * j + a];
+        else
+          V[a] = (mi * P.u[3 * i + a] + mj * P.u[3 * j + a]) / (mi + mj);
+      }
+      const int who[2] = {i, j};
+      for (int t2 = 0; t2 < 2; t2++) {
+        const int q = who[t2];
+        double wvv[3], wn = 0, v2 = 0;
+        for (int a = 0; a < 3; a++) {
+          wvv[a] = P.u[3 * q + a] - V[a];
+          wn += wvv[a] * n[a];
+        }
+        for (int a = 0; a < 3; a++) {
+          const double u = V[a] + (wvv[a] - 2.0 * wn * n[a]);
+          P.u[3 * q + a] = u;
+          v2 += u * u;
+        }
+        vseen = fmax(vseen, sqrt(v2));
+      }
+    }
+    if (2.0 * vseen >= kMargin) atomicOr(status, kStatusCollision);
+  }
+  __syncthreads();
+  for (int p = tid; p < np; p += kParticleBlock) {
+    for (int a = 0; a < dim; a++) {
+      const double x = P.x[3 * p + a] + P.u[3 * p + a];
+      P.x[3 * p + a] = x;
+      P.k[3 * p + a] = (int)floor(x - P.x0[3 * p + a] + 0.5);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K4: stamp every template entry at its particle's shift; lowest entry index
+// (hence lowest particle id) owns a site.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_stamp(int* __restrict__ map, DevParticles P, DevEntries E,
+                                                Geo G, int e_begin, int e_end) {
+  const int e = e_begin + blockIdx.x * 256 + threadIdx.x;
+  if (e >= e_end) return;
+  const int s = entry_site(P, G, E.pid[e], E.off[e]);
+  atomicMin(&map[s], e);
+}
+
+// ---------------------------------------------------------------------------
+// K5: IS substep at the new positions (eq. 12): f^eq(rho_I, u_p' + omega_p' x r).
+// ---------------------------------------------------------------------------
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_internal(T* __restrict__ B, const int* __restrict__ map,
+                                                   DevParticles P, DevEntries E, Geo G, int nent,
+                                                   double rho0) {
+  using L = Lattice<Q>;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= nent) return;
+  const int pk = E.off[e];
+  if (entry_kind(pk) != 2) return;
+  const int p = E.pid[e];
+  const int s = entry_site(P, G, p, pk);
+  if (map[s] != e) return;
+  double drho = 0;
+#pragma unroll
+  for (int i = 0; i < Q; i++) drho += (double)B[(size_t)i * G.N + s];
+  const double rho = rho0 + drho;
+  const double rx = (double)off_x(pk) - P.phi[3 * p], ry = (double)off_y(pk) - P.phi[3 * p + 1],
+               rz = (double)off_z(pk) - P.phi[3 * p + 2];
+  const double wx = P.om[3 * p], wy = P.om[3 * p + 1], wz = P.om[3 * p + 2];
+  const double vx = P.u[3 * p] + (wy * rz - wz * ry);
+  const double vy = P.u[3 * p + 1] + (wz * rx - wx * rz);
+  const double vz = P.u[3 * p + 2] + (wx * ry - wy * rx);
+  const double usq = 1.5 * (vx * vx + vy * vy + vz * vz);
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    const double cu = L::cx(i) * vx + L::cy(i) * vy + L::cz(i) * vz;
+    B[(size_t)i * G.N + s] = (T)(L::w(i) * (drho + rho * (3.0 * cu + 4.5 * cu * cu - usq)));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Read-out and set-up kernels (off the step loop).
+// ---------------------------------------------------------------------------
+template <int Q, typename T>
+__global__ void k_moments(const T* __restrict__ A, double* __restrict__ rho, double* __restrict__ u,
+                          Geo G, double rho0, int64_t s0, int64_t cnt) {
+  using L = Lattice<Q>;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= cnt) return;
+  const int64_t s = s0 + idx;
+  const int x = (int)(s % G.nx), y = (int)((s / G.nx) % G.ny), z = (int)(s / ((int64_t)G.nx * G.ny));
+  double drho = 0, j[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    const int sx = wrap(x - L::cx(i), G.nx), sy = wrap(y - L::cy(i), G.ny), sz = wrap(z - L::cz(i), G.nz);
+    const double g = (double)A[(size_t)i * G.N + sx + (int64_t)G.nx * (sy + (int64_t)G.ny * sz)];
+    drho += g;
+    j[0] += L::cx(i) * g;
+    j[1] += L::cy(i) * g;
+    j[2] += L::cz(i) * g;
+  }
+  const double r = rho0 + drho;
+  rho[idx] = r;
+  for (int a = 0; a < 3; a++) u[3 * idx + a] = j[a] / r;
+}
+
+// B_i(s) = A_i(s - dir * c_i): dir = +1 pulls (state -> post-stream f),
+// dir = -1 pushes (post-stream f -> state).
+template <int Q, typename T>
+__global__ void k_shift(const T* __restrict__ A, T* __restrict__ B, Geo G, int dir) {
+  using L = Lattice<Q>;
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= G.N) return;
+  const int x = (int)(s % G.nx), y = (int)((s / G.nx) % G.ny), z = (int)(s / ((int64_t)G.nx * G.ny));
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    const int sx = wrap(x - dir * L::cx(i), G.nx), sy = wrap(y - dir * L::cy(i), G.ny),
+              sz = wrap(z - dir * L::cz(i), G.nz);
+    B[(size_t)i * G.N + s] = A[(size_t)i * G.N + sx + (int64_t)G.nx * (sy + (int64_t)G.ny * sz)];
+  }
+}
+
+template <typename V>
+__global__ void k_fill(V* __restrict__ p, int64_t n, V v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+__global__ void k_copy16(const v4u* __restrict__ src, v4u* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    __builtin_nontemporal_store(src[i], dst + i);
+}
+
+inline unsigned blocks_for(int64_t n, int per = 256) { return (unsigned)((n + per - 1) / per); }
+
+// ---------------------------------------------------------------------------
+// Workspace layout
+// ---------------------------------------------------------------------------
+struct Layout {
+  size_t f[2], map, status;
+  size_t x, x0, u, om, phi, fext, dP, dL, F, T, m, I, rad, b0, k, ent0, nbs, nis, cand_n, cand, pairs;
+  size_t off, pid;
+  int64_t max_ent;
+  size_t total;
+};
+
+size_t store_size(int storage) { return storage == LBM_FP64 ? 8 : storage == LBM_FP32 ? 4 : 2; }
+
+int64_t entries_per_particle(int dim, double rmax) {
+  const int64_t e = 2 * (int64_t)std::ceil(rmax) + 1;
+  return dim == 2 ? e * e : e * e * e;
+}
+
+Layout make_layout(const lbm_params& p) {
+  Layout L{};
+  const int64_t N = (int64_t)p.nx * p.ny * p.nz;
+  const int dim = p.lattice == LBM_D2Q9 ? 2 : 3;
+  const int64_t np = std::max<int64_t>(p.max_particles, 1);
+  L.max_ent = np * entries_per_particle(dim, p.max_radius);
+  size_t cur = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = cur;
+    cur += (bytes + kAlign - 1) / kAlign * kAlign;
+    return at;
+  };
+  const size_t fb = (size_t)p.lattice * N * store_size(p.storage);
+  L.f[0] = take(fb);
+  L.f[1] = take(fb);
+  L.map = take(sizeof(int) * N);
+  L.status = take(64);
+  const size_t v3 = sizeof(double) * 3 * np, v1 = sizeof(double) * np;
+  L.x = take(v3); L.x0 = take(v3); L.u = take(v3); L.om = take(v3); L.phi = take(v3);
+  L.fext = take(v3); L.dP = take(v3); L.dL = take(v3); L.F = take(v3); L.T = take(v3);
+  L.m = take(v1); L.I = take(v1); L.rad = take(v1);
+  L.b0 = take(sizeof(int) * 3 * np); L.k = take(sizeof(int) * 3 * np);
+  L.ent0 = take(sizeof(int) * np); L.nbs = take(sizeof(int) * np); L.nis = take(sizeof(int) * np);
+  L.cand_n = take(sizeof(int) * np);
+  L.cand = take(sizeof(int) * np * kCandMax);
+  L.pairs = take(sizeof(int) * 2 * np * kCandMax);
+  L.off = take(sizeof(int) * L.max_ent);
+  L.pid = take(sizeof(int) * L.max_ent);
+  L.total = cur;
+  return L;
+}
+
+int check_params(const lbm_params* p) {
+  if (!p) return LBM_EINVAL;
+  if (p->lattice != LBM_D2Q9 && p->lattice != LBM_D3Q19) return LBM_EINVAL;
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return LBM_EINVAL;
+  if (p->lattice == LBM_D2Q9 && p->nz != 1) return LBM_EINVAL;
+  if ((int64_t)p->nx * p->ny * p->nz >= ((int64_t)1 << 31)) return LBM_EINVAL;
+  if (!std::isfinite(p->tau) || !std::isfinite(p->rho0) || !std::isfinite(p->max_radius)) return LBM_ENONFINITE;
+  for (int a = 0; a < 3; a++)
+    if (!std::isfinite(p->gravity[a]) || !std::isfinite(p->body_force[a])) return LBM_ENONFINITE;
+  if (!(p->tau > 0.5) || !(p->rho0 > 0)) return LBM_EINVAL;
+  if (p->max_particles < 0) return LBM_EINVAL;
+  if (!(p->max_radius > 0) || p->max_radius > 120) return LBM_EINVAL;
+  if (p->storage == LBM_FP16 || p->storage == LBM_BF16) return LBM_EUNSUPPORTED;
+  if (p->storage != LBM_FP64 && p->storage != LBM_FP32) return LBM_EINVAL;
+  return LBM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+struct lbm_ctx {
+  lbm_params prm;
+  int q, dim;
+  Geo G;
+  hipStream_t stream;
+  char* ws;
+  Layout L;
+  void* f[2];
+  int cur;  // f[cur] holds the post-collision state of the last step
+  int* map;
+  int* status;
+  DevParticles P;
+  DevEntries E;
+  int np;
+  int64_t nent;
+  std::vector<double> h_x0, h_rad, h_m, h_I, h_fext;
+  std::vector<int> h_off, h_pid, h_nbs, h_nis;
+  double fb[3];  // fluid body force density
+  bool prof;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used;
+};
+
+#define HIP_TRY(expr)                          \
+  do {                                         \
+    if ((expr) != hipSuccess) return LBM_EHIP; \
+  } while (0)
+
+namespace {
+
+template <int Q, typename T>
+int launch_step(lbm_ctx* c) {
+  using C = typename Store<T>::C;
+  using Lt = Lattice<Q>;
+  SweepArgs<Q, C> a;
+  a.nx = c->G.nx;
+  a.ny = c->G.ny;
+  a.nz = c->G.nz;
+  a.nxb = (c->G.nx + kSweepBlock - 1) / kSweepBlock;
+  a.N = c->G.N;
+  a.omega = (C)(1.0 / c->prm.tau);
+  a.rho0 = (C)c->prm.rho0;
+  for (int i = 0; i < Q; i++) {
+    const double cf = Lt::cx(i) * c->fb[0] + Lt::cy(i) * c->fb[1] + Lt::cz(i) * c->fb[2];
+    a.fbt[i] = (C)(3.0 * Lt::w(i) * cf);
+  }
+  const T* A = (const T*)c->f[c->cur];
+  T* B = (T*)c->f[1 - c->cur];
+  const unsigned nblk = (unsigned)((int64_t)a.nxb * c->G.ny * c->G.nz);
+  if (c->prof) {
+    if (c->ev_used + 2 > c->ev.size()) {
+      for (int t = 0; t < 64; t++) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        c->ev.push_back(e);
+      }
+    }
+    HIP_TRY(hipEventRecord(c->ev[c->ev_used], c->stream));
+  }
+  k_sweep<Q, T><<<nblk, kSweepBlock, 0, c->stream>>>(A, B, a);
+  if (c->prof) {
+    HIP_TRY(hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+    c->ev_used += 2;
+  }
+  HIP_TRY(hipGetLastError());
+  if (c->np > 0) {
+    k_boundary<Q, T><<<c->np, kBoundaryBlock, 0, c->stream>>>(B, c->map, c->P, c->E, c->G, c->np,
+                                                              c->prm.rho0, c->status);
+    k_particles<<<1, kParticleBlock, 0, c->stream>>>(c->P, c->np, c->dim, c->G, c->status);
+    k_stamp<<<blocks_for(c->nent), 256, 0, c->stream>>>(c->map, c->P, c->E, c->G, 0, (int)c->nent);
+    k_internal<Q, T><<<blocks_for(c->nent), 256, 0, c->stream>>>(B, c->map, c->P, c->E, c->G,
+                                                                 (int)c->nent, c->prm.rho0);
+    HIP_TRY(hipGetLastError());
+  }
+  c->cur = 1 - c->cur;
+  return LBM_OK;
+}
+
+template <int Q, typename T>
+int launch_moments(lbm_ctx* c, double* d_rho, double* d_u, int64_t s0, int64_t cnt) {
+  k_moments<Q, T><<<blocks_for(cnt), 256, 0, c->stream>>>((const T*)c->f[c->cur], d_rho, d_u, c->G,
+                                                          c->prm.rho0, s0, cnt);
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+template <int Q, typename T>
+int launch_shift(lbm_ctx* c, const void* A, void* B, int dir) {
+  k_shift<Q, T><<<blocks_for(c->G.N), 256, 0, c->stream>>>((const T*)A, (T*)B, c->G, dir);
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+#define DISPATCH(c, FN, ...)                                                        \
+  ((c)->q == 9 ? ((c)->prm.storage == LBM_FP64 ? FN<9, double>(__VA_ARGS__)        \
+                                                : FN<9, float>(__VA_ARGS__))        \
+               : ((c)->prm.storage == LBM_FP64 ? FN<19, double>(__VA_ARGS__)       \
+                                                : FN<19, float>(__VA_ARGS__)))
+
+double lattice_w(int q, int i) { return q == 9 ? Lattice<9>::w(i) : Lattice<19>::w(i); }
+
+// Template of one particle (section 2.2): digitised ball |o - phi| <= r, BS
+// = ball sites linked (any lattice velocity) to a site outside the ball, IS =
+// other ball sites linked to a BS site.  Entries: BS first, then IS, each in
+// z, y, x order.
+void build_template(int q, double r, const double phi[3], std::vector<int>& out, int* nbs, int* nis) {
+  const int dim = q == 9 ? 2 : 3;
+  const int R = (int)std::ceil(r) + 1;
+  const int h = R + 1, ext = 2 * R + 3;
+  const int ez = dim == 3 ? ext : 1, hz = dim == 3 ? h : 0, Rz = dim == 3 ? R : 0;
+  std::vector<char> in((size_t)ext * ext * ez, 0), bs(in.size(), 0), is(in.size(), 0);
+  auto gi = [&](int x, int y, int z) { return ((size_t)(z + hz) * ext + (y + h)) * ext + (x + h); };
+  int cx[19], cy[19], cz[19];
+  for (int i = 0; i < q; i++) {
+    cx[i] = q == 9 ? Lattice<9>::cx(i) : Lattice<19>::cx(i);
+    cy[i] = q == 9 ? Lattice<9>::cy(i) : Lattice<19>::cy(i);
+    cz[i] = q == 9 ? Lattice<9>::cz(i) : Lattice<19>::cz(i);
+  }
+  for (int z = -Rz; z <= Rz; z++)
+    for (int y = -R; y <= R; y++)
+      for (int x = -R; x <= R; x++) {
+        const double dx = x - phi[0], dy = y - phi[1], dz = z - phi[2];
+        in[gi(x, y, z)] = dx * dx + dy * dy + dz * dz <= r * r;
+      }
+  *nbs = *nis = 0;
+  for (int z = -Rz; z <= Rz; z++)
+    for (int y = -R; y <= R; y++)
+      for (int x = -R; x <= R; x++) {
+        if (!in[gi(x, y, z)]) continue;
+        for (int i = 1; i < q; i++)
+          if (!in[gi(x + cx[i], y + cy[i], z + cz[i])]) {
+            bs[gi(x, y, z)] = 1;
+            break;
+          }
+      }
+  for (int z = -Rz; z <= Rz; z++)
+    for (int y = -R; y <= R; y++)
+      for (int x = -R; x <= R; x++) {
+        if (!in[gi(x, y, z)] || bs[gi(x, y, z)]) continue;
+        for (int i = 1; i < q; i++)
+          if (bs[gi(x + cx[i], y + cy[i], z + cz[i])]) {
+            is[gi(x, y, z)] = 1;
+            break;
+          }
+      }
+  for (int kind = 1; kind <= 2; kind++)
+    for (int z = -Rz; z <= Rz; z++)
+      for (int y = -R; y <= R; y++)
+        for (int x = -R; x <= R; x++) {
+          if (!(kind == 1 ? bs[gi(x, y, z)] : is[gi(x, y, z)])) continue;
+          out.push_back(pack_entry(x, y, z, kind));
+          (kind == 1 ? *nbs : *nis) += 1;
+        }
+}
+
+int check_status(lbm_ctx* c) {
+  int st[4];
+  HIP_TRY(hipMemcpyAsync(st, c->status, sizeof(st), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (st[0] != 0) {
+    const int zero[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(c->status, zero, sizeof(zero), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (st[0] & kStatusCollision) return LBM_ECOLLISION;
+  }
+  return LBM_OK;
+}
+
+template <typename V>
+int upload(lbm_ctx* c, V* dst, const V* src, size_t count) {
+  if (count == 0) return LBM_OK;
+  HIP_TRY(hipMemcpyAsync(dst, src, sizeof(V) * count, hipMemcpyHostToDevice, c->stream));
+  return LBM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int lbm_workspace_size(const lbm_params* prm, size_t* bytes) {
+  const int rc = check_params(prm);
+  if (rc != LBM_OK) return rc;
+  if (!bytes) return LBM_EINVAL;
+  *bytes = make_layout(*prm).total;
+  return LBM_OK;
+}
+
+int lbm_bytes_per_site(const lbm_params* prm, int64_t* bytes) {
+  if (!prm || !bytes) return LBM_EINVAL;
+  if (prm->lattice != LBM_D2Q9 && prm->lattice != LBM_D3Q19) return LBM_EINVAL;
+  *bytes = 2 * (int64_t)prm->lattice * (int64_t)store_size(prm->storage);
+  return LBM_OK;
+}
+
+int lbm_create(const lbm_params* prm, void* d_workspace, size_t bytes, void* hip_stream, lbm_ctx** out) {
+  int rc = check_params(prm);
+  if (rc != LBM_OK) return rc;
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  const Layout L = make_layout(*prm);
+  if (!d_workspace || ((uintptr_t)d_workspace % kAlign) != 0 || bytes < L.total) return LBM_EWORKSPACE;
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return LBM_EINVAL;
+  c->prm = *prm;
+  c->q = prm->lattice;
+  c->dim = prm->lattice == LBM_D2Q9 ? 2 : 3;
+  c->G = Geo{prm->nx, prm->ny, prm->nz, (int64_t)prm->nx * prm->ny * prm->nz};
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (char*)d_workspace;
+  c->L = L;
+  c->f[0] = c->ws + L.f[0];
+  c->f[1] = c->ws + L.f[1];
+  c->cur = 0;
+  c->map = (int*)(c->ws + L.map);
+  c->status = (int*)(c->ws + L.status);
+  char* w = c->ws;
+  c->P = DevParticles{(double*)(w + L.x),    (double*)(w + L.x0),  (double*)(w + L.u),
+                      (double*)(w + L.om),   (double*)(w + L.phi), (double*)(w + L.fext),
+                      (double*)(w + L.dP),   (double*)(w + L.dL),  (double*)(w + L.F),
+                      (double*)(w + L.T),    (double*)(w + L.m),   (double*)(w + L.I),
+                      (double*)(w + L.rad),  (int*)(w + L.b0),     (int*)(w + L.k),
+                      (int*)(w + L.ent0),    (int*)(w + L.nbs),    (int*)(w + L.nis),
+                      (int*)(w + L.cand_n),  (int*)(w + L.cand),   (int*)(w + L.pairs)};
+  c->E = DevEntries{(int*)(w + L.off), (int*)(w + L.pid)};
+  c->np = 0;
+  c->nent = 0;
+  for (int a = 0; a < 3; a++) c->fb[a] = prm->body_force[a];
+  c->prof = false;
+  c->ev_used = 0;
+  // fluid at rest: every deviation zero; empty map; clear status
+  const size_t fbytes = (size_t)c->q * c->G.N * store_size(prm->storage);
+  const int64_t nwords = (int64_t)(fbytes / 4);
+  k_fill<uint32_t><<<blocks_for(nwords), 256, 0, c->stream>>>((uint32_t*)c->f[0], nwords, 0u);
+  k_fill<int><<<blocks_for(c->G.N), 256, 0, c->stream>>>(c->map, c->G.N, kEmpty);
+  k_fill<int><<<1, 256, 0, c->stream>>>(c->status, 16, 0);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+    delete c;
+    return LBM_EHIP;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+int lbm_destroy(lbm_ctx* c) {
+  if (!c) return LBM_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+  return LBM_OK;
+}
+
+int lbm_add_particles(lbm_ctx* c, int32_t n, const double* x, const double* u, const double* omega,
+                      const double* radius, const double* mass, const double* inertia, int32_t* first_id) {
+  if (!c || n < 0) return LBM_EINVAL;
+  if (n == 0) {
+    if (first_id) *first_id = c->np;
+    return LBM_OK;
+  }
+  if (!x || !radius || !mass || !inertia) return LBM_EINVAL;
+  if (c->np + (int64_t)n > c->prm.max_particles) return LBM_ECAPACITY;
+  const int dim = c->dim;
+  const int box[3] = {c->G.nx, c->G.ny, c->G.nz};
+  for (int j = 0; j < n; j++) {
+    for (int a = 0; a < 3; a++) {
+      if (a < dim && !std::isfinite(x[3 * j + a])) return LBM_ENONFINITE;
+      if (u && a < dim && !std::isfinite(u[3 * j + a])) return LBM_ENONFINITE;
+      if (omega && !std::isfinite(omega[3 * j + a])) return LBM_ENONFINITE;
+      if (a < dim && (x[3 * j + a] < 0 || x[3 * j + a] >= box[a])) return LBM_EINVAL;
+    }
+    const double r = radius[j];
+    if (!std::isfinite(r) || std::isnan(mass[j]) || std::isnan(inertia[j])) return LBM_ENONFINITE;
+    if (!(r > 0) || r > c->prm.max_radius) return LBM_EINVAL;
+    if (!(mass[j] > 0) || !(inertia[j] > 0)) return LBM_EINVAL;
+    for (int a = 0; a < dim; a++)
+      if (2 * (int)std::ceil(r) + 3 > box[a]) return LBM_EINVAL;
+  }
+  // positions of the particles already in the box
+  std::vector<double> cur((size_t)3 * c->np);
+  if (c->np > 0) {
+    HIP_TRY(hipMemcpyAsync(cur.data(), c->P.x, sizeof(double) * 3 * c->np, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  auto dist2 = [&](const double* A, const double* B) {
+    double s = 0;
+    for (int a = 0; a < dim; a++) {
+      double d = B[a] - A[a];
+      d -= box[a] * std::floor(d / box[a] + 0.5);
+      s += d * d;
+    }
+    return s;
+  };
+  for (int j = 0; j < n; j++) {
+    for (int p = 0; p < c->np; p++) {
+      const double lim = radius[j] + c->h_rad[p];
+      if (dist2(&cur[3 * p], &x[3 * j]) < lim * lim) return LBM_EOVERLAP;
+    }
+    for (int i = 0; i < j; i++) {
+      const double lim = radius[j] + radius[i];
+      if (dist2(&x[3 * i], &x[3 * j]) < lim * lim) return LBM_EOVERLAP;
+    }
+  }
+  // templates and particle records (host), then upload
+  std::vector<double> hx(3 * n), hu(3 * n, 0.0), hom(3 * n, 0.0), hphi(3 * n), hfext(3 * n);
+  std::vector<int> hb0(3 * n), hk(3 * n, 0), hent0(n), hnbs(n), hnis(n), hoff, hpid;
+  for (int j = 0; j < n; j++) {
+    const double r = radius[j];
+    const double V = dim == 2 ? M_PI * r * r : 4.0 / 3.0 * M_PI * r * r * r;
+    for (int a = 0; a < 3; a++) {
+      hx[3 * j + a] = a < dim ? x[3 * j + a] : 0.0;
+      if (u && a < dim) hu[3 * j + a] = u[3 * j + a];
+      if (omega && (dim == 3 || a == 2)) hom[3 * j + a] = omega[3 * j + a];
+      hb0[3 * j + a] = (int)std::floor(hx[3 * j + a] + 0.5);
+      hphi[3 * j + a] = hx[3 * j + a] - (double)hb0[3 * j + a];
+      hfext[3 * j + a] = std::isinf(mass[j]) ? 0.0 : (mass[j] - c->prm.rho0 * V) * c->prm.gravity[a];
+    }
+    int nb = 0, ni = 0;
+    const size_t before = hoff.size();
+    build_template(c->q, r, &hphi[3 * j], hoff, &nb, &ni);
+    hent0[j] = (int)(c->nent + before);
+    hnbs[j] = nb;
+    hnis[j] = ni;
+    hpid.insert(hpid.end(), (size_t)(nb + ni), c->np + j);
+  }
+  if (c->nent + (int64_t)hoff.size() > c->L.max_ent) return LBM_ECAPACITY;
+  const int p0 = c->np;
+  int rc;
+#define UP(dst, src, cnt) \
+  if ((rc = upload(c, dst, src, cnt)) != LBM_OK) return rc
+  UP(c->P.x + 3 * p0, hx.data(), 3 * (size_t)n);
+  UP(c->P.x0 + 3 * p0, hx.data(), 3 * (size_t)n);
+  UP(c->P.u + 3 * p0, hu.data(), 3 * (size_t)n);
+  UP(c->P.om + 3 * p0, hom.data(), 3 * (size_t)n);
+  UP(c->P.phi + 3 * p0, hphi.data(), 3 * (size_t)n);
+  UP(c->P.fext + 3 * p0, hfext.data(), 3 * (size_t)n);
+  UP(c->P.m + p0, mass, (size_t)n);
+  UP(c->P.I + p0, inertia, (size_t)n);
+  UP(c->P.rad + p0, radius, (size_t)n);
+  UP(c->P.b0 + 3 * p0, hb0.data(), 3 * (size_t)n);
+  UP(c->P.k + 3 * p0, hk.data(), 3 * (size_t)n);
+  UP(c->P.ent0 + p0, hent0.data(), (size_t)n);
+  UP(c->P.nbs + p0, hnbs.data(), (size_t)n);
+  UP(c->P.nis + p0, hnis.data(), (size_t)n);
+  UP(c->E.off + c->nent, hoff.data(), hoff.size());
+  UP(c->E.pid + c->nent, hpid.data(), hpid.size());
+#undef UP
+  std::vector<double> zero(3 * (size_t)n, 0.0);
+  HIP_TRY(hipMemcpyAsync(c->P.F + 3 * p0, zero.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->P.T + 3 * p0, zero.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
+  // stamp the new entries into the current map (existing owners have lower ids)
+  const int64_t e0 = c->nent, e1 = c->nent + (int64_t)hoff.size();
+  k_stamp<<<blocks_for(e1 - e0), 256, 0, c->stream>>>(c->map, c->P, c->E, c->G, (int)e0, (int)e1);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int j = 0; j < n; j++) {
+    c->h_x0.insert(c->h_x0.end(), &hx[3 * j], &hx[3 * j] + 3);
+    c->h_rad.push_back(radius[j]);
+    c->h_m.push_back(mass[j]);
+    c->h_I.push_back(inertia[j]);
+    c->h_fext.insert(c->h_fext.end(), &hfext[3 * j], &hfext[3 * j] + 3);
+    c->h_nbs.push_back(hnbs[j]);
+    c->h_nis.push_back(hnis[j]);
+  }
+  c->h_off.insert(c->h_off.end(), hoff.begin(), hoff.end());
+  c->h_pid.insert(c->h_pid.end(), hpid.begin(), hpid.end());
+  c->nent = e1;
+  c->np += n;
+  // fluid body force: user value, plus the opposite of the particles' total
+  // external force spread over every site in a zero-net-force box
+  double tot[3] = {0, 0, 0};
+  for (int p = 0; p < c->np; p++)
+    for (int a = 0; a < 3; a++) tot[a] += c->h_fext[3 * p + a];
+  for (int a = 0; a < 3; a++)
+    c->fb[a] = c->prm.body_force[a] - (c->prm.zero_net_force ? tot[a] / (double)c->G.N : 0.0);
+  if (first_id) *first_id = p0;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int32_t nsteps) {
+  if (!c || nsteps < 0) return LBM_EINVAL;
+  for (int t = 0; t < nsteps; t++) {
+    const int rc = DISPATCH(c, launch_step, c);
+    if (rc != LBM_OK) return rc;
+  }
+  return LBM_OK;
+}
+
+int lbm_forces(lbm_ctx* c, double* F, double* T, double* x, double* u, double* omega) {
+  if (!c) return LBM_EINVAL;
+  const size_t b = sizeof(double) * 3 * c->np;
+  if (c->np > 0) {
+    if (F) HIP_TRY(hipMemcpyAsync(F, c->P.F, b, hipMemcpyDeviceToHost, c->stream));
+    if (T) HIP_TRY(hipMemcpyAsync(T, c->P.T, b, hipMemcpyDeviceToHost, c->stream));
+    if (x) HIP_TRY(hipMemcpyAsync(x, c->P.x, b, hipMemcpyDeviceToHost, c->stream));
+    if (u) HIP_TRY(hipMemcpyAsync(u, c->P.u, b, hipMemcpyDeviceToHost, c->stream));
+    if (omega) HIP_TRY(hipMemcpyAsync(omega, c->P.om, b, hipMemcpyDeviceToHost, c->stream));
+  }
+  return check_status(c);
+}
+
+int lbm_fields(lbm_ctx* c, double* rho, double* u, int32_t* owner) {
+  if (!c) return LBM_EINVAL;
+  if (rho || u) {
+    // the other population buffer is free between steps: stage moments there
+    const size_t stage = (size_t)c->q * c->G.N * store_size(c->prm.storage);
+    const int64_t chunk = (int64_t)(stage / (4 * sizeof(double)));
+    double* d_rho = (double*)c->f[1 - c->cur];
+    double* d_u = d_rho + chunk;
+    std::vector<double> hr, hu;
+    for (int64_t s0 = 0; s0 < c->G.N; s0 += chunk) {
+      const int64_t cnt = std::min<int64_t>(chunk, c->G.N - s0);
+      const int rc = DISPATCH(c, launch_moments, c, d_rho, d_u, s0, cnt);
+      if (rc != LBM_OK) return rc;
+      if (rho) HIP_TRY(hipMemcpyAsync(rho + s0, d_rho, sizeof(double) * cnt, hipMemcpyDeviceToHost, c->stream));
+      if (u) HIP_TRY(hipMemcpyAsync(u + 3 * s0, d_u, sizeof(double) * 3 * cnt, hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+  }
+  if (owner) {
+    std::vector<int> m(c->G.N);
+    HIP_TRY(hipMemcpyAsync(m.data(), c->map, sizeof(int) * c->G.N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int64_t s = 0; s < c->G.N; s++) owner[s] = m[s] == kEmpty ? -1 : c->h_pid[m[s]];
+  }
+  return check_status(c);
+}
+
+int lbm_site_kind(lbm_ctx* c, int8_t* kind) {
+  if (!c || !kind) return LBM_EINVAL;
+  std::vector<int> m(c->G.N);
+  HIP_TRY(hipMemcpyAsync(m.data(), c->map, sizeof(int) * c->G.N, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int64_t s = 0; s < c->G.N; s++) kind[s] = m[s] == kEmpty ? 0 : (int8_t)entry_kind(c->h_off[m[s]]);
+  return check_status(c);
+}
+
+int lbm_shifts(lbm_ctx* c, int32_t* k) {
+  if (!c || !k) return LBM_EINVAL;
+  if (c->np > 0) HIP_TRY(hipMemcpyAsync(k, c->P.k, sizeof(int) * 3 * c->np, hipMemcpyDeviceToHost, c->stream));
+  return check_status(c);
+}
+
+int lbm_particle_info(lbm_ctx* c, int32_t p, int32_t* nbs, int32_t* nis) {
+  if (!c || p < 0 || p >= c->np) return LBM_EINVAL;
+  if (nbs) *nbs = c->h_nbs[p];
+  if (nis) *nis = c->h_nis[p];
+  return LBM_OK;
+}
+
+int lbm_get_distributions(lbm_ctx* c, double* f) {
+  if (!c || !f) return LBM_EINVAL;
+  void* stage = c->f[1 - c->cur];
+  int rc = DISPATCH(c, launch_shift, c, c->f[c->cur], stage, 1);
+  if (rc != LBM_OK) return rc;
+  const int64_t n = (int64_t)c->q * c->G.N;
+  if (c->prm.storage == LBM_FP64) {
+    HIP_TRY(hipMemcpyAsync(f, stage, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  } else {
+    std::vector<float> h(n);
+    HIP_TRY(hipMemcpyAsync(h.data(), stage, sizeof(float) * n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int64_t i = 0; i < n; i++) f[i] = (double)h[i];
+  }
+  for (int i = 0; i < c->q; i++) {
+    const double base = lattice_w(c->q, i) * c->prm.rho0;
+    double* fi = f + (int64_t)i * c->G.N;
+    for (int64_t s = 0; s < c->G.N; s++) fi[s] += base;
+  }
+  return check_status(c);
+}
+
+int lbm_set_distributions(lbm_ctx* c, const double* f) {
+  if (!c || !f) return LBM_EINVAL;
+  const int64_t n = (int64_t)c->q * c->G.N;
+  for (int64_t i = 0; i < n; i++)
+    if (!std::isfinite(f[i])) return LBM_ENONFINITE;
+  void* stage = c->f[1 - c->cur];
+  if (c->prm.storage == LBM_FP64) {
+    std::vector<double> h(n);
+    for (int i = 0; i < c->q; i++) {
+      const double base = lattice_w(c->q, i) * c->prm.rho0;
+      for (int64_t s = 0; s < c->G.N; s++) h[(int64_t)i * c->G.N + s] = f[(int64_t)i * c->G.N + s] - base;
+    }
+    HIP_TRY(hipMemcpyAsync(stage, h.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  } else {
+    std::vector<float> h(n);
+    for (int i = 0; i < c->q; i++) {
+      const double base = lattice_w(c->q, i) * c->prm.rho0;
+      for (int64_t s = 0; s < c->G.N; s++)
+        h[(int64_t)i * c->G.N + s] = (float)(f[(int64_t)i * c->G.N + s] - base);
+    }
+    HIP_TRY(hipMemcpyAsync(stage, h.data(), sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  int rc = DISPATCH(c, launch_shift, c, stage, c->f[c->cur], -1);
+  if (rc != LBM_OK) return rc;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int lbm_set_profiling(lbm_ctx* c, int32_t on) {
+  if (!c) return LBM_EINVAL;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->prof = on != 0;
+  c->ev_used = 0;
+  return LBM_OK;
+}
+
+int lbm_profile(lbm_ctx* c, double* sweep_ms, int64_t* sweeps) {
+  if (!c) return LBM_EINVAL;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  double tot = 0;
+  for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+    tot += ms;
+  }
+  if (sweep_ms) *sweep_ms = tot;
+  if (sweeps) *sweeps = (int64_t)(c->ev_used / 2);
+  c->ev_used = 0;
+  return LBM_OK;
+}
+
+int lbm_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
+  if (!dst || !src || bytes % 16 || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16)) return LBM_EINVAL;
+  const int64_t n = (int64_t)(bytes / 16);
+  const unsigned nb = (unsigned)std::min<int64_t>(blocks_for(n), 256 * 64);
+  k_copy16<<<nb, 256, 0, (hipStream_t)hip_stream>>>((const v4u*)src, (v4u*)dst, n);
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+const char* lbm_strerror(int code) {
+  switch (code) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_EWORKSPACE: return "workspace missing, misaligned or too small";
+    case LBM_EHIP: return "HIP runtime error";
+    case LBM_EOVERLAP: return "particles overlap";
+    case LBM_ECAPACITY: return "capacity exceeded";
+    case LBM_ENONFINITE: return "non-finite value";
+    case LBM_EUNSUPPORTED: return "storage mode not supported";
+    case LBM_ECOLLISION: return "collision search bound exceeded";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,229 @@
+"""Thin ctypes binding of the C ABI in include/lbm.h.
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``liblbm.so``.  PyTorch provides the device workspace and the stream.
+The module-level ``lbm_*`` functions mirror the C entry points one to one;
+``Simulation`` bundles a context with its workspace tensor.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+LBM_D2Q9, LBM_D3Q19 = 9, 19
+LBM_FP64, LBM_FP32, LBM_FP16, LBM_BF16 = 0, 1, 2, 3
+STORAGE = {"fp64": LBM_FP64, "fp32": LBM_FP32, "fp16": LBM_FP16, "bf16": LBM_BF16}
+LBM_OK = 0
+LBM_EINVAL, LBM_EWORKSPACE, LBM_EHIP, LBM_EOVERLAP = -1, -2, -3, -4
+LBM_ECAPACITY, LBM_ENONFINITE, LBM_EUNSUPPORTED, LBM_ECOLLISION = -5, -6, -7, -8
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__("%s failed: %s (%d)" % (what, lbm_strerror(code), code))
+        self.code = code
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("gravity", ctypes.c_double * 3), ("body_force", ctypes.c_double * 3),
+                ("zero_net_force", ctypes.c_int32), ("storage", ctypes.c_int32),
+                ("max_particles", ctypes.c_int32), ("max_radius", ctypes.c_double)]
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+_lib = None
+
+
+def lib():
+    """Load liblbm.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("HIP library %s is not built; run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER(lbm_params)
+        vp = ctypes.c_void_p
+        sig = {
+            "lbm_workspace_size": [P, ctypes.POINTER(ctypes.c_size_t)],
+            "lbm_create": [P, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)],
+            "lbm_add_particles": [vp, ctypes.c_int32, _dp, _dp, _dp, _dp, _dp, _dp, _ip],
+            "lbm_step": [vp, ctypes.c_int32],
+            "lbm_forces": [vp, _dp, _dp, _dp, _dp, _dp],
+            "lbm_fields": [vp, _dp, _dp, _ip],
+            "lbm_destroy": [vp],
+            "lbm_get_distributions": [vp, _dp],
+            "lbm_set_distributions": [vp, _dp],
+            "lbm_site_kind": [vp, ctypes.POINTER(ctypes.c_int8)],
+            "lbm_shifts": [vp, _ip],
+            "lbm_particle_info": [vp, ctypes.c_int32, _ip, _ip],
+            "lbm_set_profiling": [vp, ctypes.c_int32],
+            "lbm_profile": [vp, _dp, ctypes.POINTER(ctypes.c_int64)],
+            "lbm_bytes_per_site": [P, ctypes.POINTER(ctypes.c_int64)],
+            "lbm_device_copy": [vp, vp, ctypes.c_size_t, vp],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.lbm_strerror.argtypes = [ctypes.c_int]
+        L.lbm_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def lbm_strerror(code):
+    return lib().lbm_strerror(int(code)).decode()
+
+
+def _check(code, what):
+    if code != LBM_OK:
+        raise LbmError(code, what)
+
+
+def _d(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def make_params(lattice, nx, ny, nz=1, tau=1.0, rho0=1.0, gravity=(0, 0, 0), body_force=(0, 0, 0),
+                zero_net_force=False, storage="fp32", max_particles=0, max_radius=1.0):
+    p = lbm_params()
+    p.lattice, p.nx, p.ny, p.nz = int(lattice), int(nx), int(ny), int(nz)
+    p.tau, p.rho0 = float(tau), float(rho0)
+    for a in range(3):
+        p.gravity[a] = float(gravity[a])
+        p.body_force[a] = float(body_force[a])
+    p.zero_net_force = int(bool(zero_net_force))
+    p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    p.max_particles = int(max_particles)
+    p.max_radius = float(max_radius)
+    return p
+
+
+def lbm_workspace_size(params):
+    n = ctypes.c_size_t(0)
+    _check(lib().lbm_workspace_size(ctypes.byref(params), ctypes.byref(n)), "lbm_workspace_size")
+    return n.value
+
+
+def lbm_bytes_per_site(params):
+    n = ctypes.c_int64(0)
+    _check(lib().lbm_bytes_per_site(ctypes.byref(params), ctypes.byref(n)), "lbm_bytes_per_site")
+    return n.value
+
+
+def lbm_create(params, workspace_ptr, workspace_bytes, stream_handle):
+    ctx = ctypes.c_void_p()
+    _check(lib().lbm_create(ctypes.byref(params), ctypes.c_void_p(workspace_ptr), workspace_bytes,
+                            ctypes.c_void_p(stream_handle), ctypes.byref(ctx)), "lbm_create")
+    return ctx
+
+
+def lbm_device_copy(dst_ptr, src_ptr, nbytes, stream_handle):
+    _check(lib().lbm_device_copy(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr), nbytes,
+                                 ctypes.c_void_p(stream_handle)), "lbm_device_copy")
+
+
+def _vec3(a, n):
+    if a is None:
+        return np.zeros((n, 3))
+    return np.ascontiguousarray(a, dtype=np.float64).reshape(n, 3)
+
+
+def _vec1(a, n):
+    return np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), (n,)))
+
+
+class Simulation:
+    """A context plus the torch workspace tensor it lives in."""
+
+    def __init__(self, lattice, nx, ny, nz=1, tau=1.0, rho0=1.0, gravity=(0, 0, 0),
+                 body_force=(0, 0, 0), zero_net_force=False, storage="fp32", max_particles=0,
+                 max_radius=1.0, device="cuda", stream=None):
+        import torch
+        self.params = make_params(lattice, nx, ny, nz, tau, rho0, gravity, body_force,
+                                  zero_net_force, storage, max_particles, max_radius)
+        self.q, self.nx, self.ny, self.nz = int(lattice), int(nx), int(ny), int(nz)
+        self.N = self.nx * self.ny * self.nz
+        self.nbytes = lbm_workspace_size(self.params)
+        self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        self.ctx = lbm_create(self.params, self.workspace.data_ptr(), self.nbytes, self.stream.cuda_stream)
+        self.n_particles = 0
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_particles(self, x, u=None, omega=None, radius=None, mass=None, inertia=None):
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
+        n = x.shape[0]
+        first = ctypes.c_int32(-1)
+        _check(lib().lbm_add_particles(self.ctx, n, _d(x), _d(_vec3(u, n)), _d(_vec3(omega, n)),
+                                       _d(_vec1(radius, n)), _d(_vec1(mass, n)), _d(_vec1(inertia, n)),
+                                       ctypes.byref(first)), "lbm_add_particles")
+        self.n_particles += n
+        return first.value
+
+    def step(self, n=1):
+        _check(lib().lbm_step(self.ctx, int(n)), "lbm_step")
+
+    def forces(self):
+        n = self.n_particles
+        F, T, x, u, om = (np.zeros((n, 3)) for _ in range(5))
+        _check(lib().lbm_forces(self.ctx, _d(F), _d(T), _d(x), _d(u), _d(om)), "lbm_forces")
+        return F, T, x, u, om
+
+    def fields(self):
+        rho = np.zeros(self.N)
+        u = np.zeros((self.N, 3))
+        own = np.zeros(self.N, dtype=np.int32)
+        _check(lib().lbm_fields(self.ctx, _d(rho), _d(u), own.ctypes.data_as(_ip)), "lbm_fields")
+        shp = (self.nz, self.ny, self.nx)
+        return rho.reshape(shp), u.reshape(shp + (3,)), own.reshape(shp)
+
+    def get_distributions(self):
+        f = np.zeros((self.q, self.N))
+        _check(lib().lbm_get_distributions(self.ctx, _d(f)), "lbm_get_distributions")
+        return f.reshape(self.q, self.nz, self.ny, self.nx)
+
+    def set_distributions(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(self.q, self.N)
+        _check(lib().lbm_set_distributions(self.ctx, _d(f)), "lbm_set_distributions")
+
+    def site_kind(self):
+        k = np.zeros(self.N, dtype=np.int8)
+        _check(lib().lbm_site_kind(self.ctx, k.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))),
+               "lbm_site_kind")
+        return k.reshape(self.nz, self.ny, self.nx)
+
+    def shifts(self):
+        k = np.zeros((self.n_particles, 3), dtype=np.int32)
+        _check(lib().lbm_shifts(self.ctx, k.ctypes.data_as(_ip)), "lbm_shifts")
+        return k
+
+    def particle_info(self, p):
+        nbs, nis = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().lbm_particle_info(self.ctx, int(p), ctypes.byref(nbs), ctypes.byref(nis)),
+               "lbm_particle_info")
+        return nbs.value, nis.value
+
+    def set_profiling(self, on):
+        _check(lib().lbm_set_profiling(self.ctx, int(bool(on))), "lbm_set_profiling")
+
+    def profile(self):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().lbm_profile(self.ctx, ctypes.byref(ms), ctypes.byref(n)), "lbm_profile")
+        return ms.value, n.value

@@ -1,0 +1,291 @@
+"""GPU (HIP, through the C ABI) against the FP64 oracle on the same seeded inputs.
+
+Gates, after the stated number of steps:
+  e_f = max|f_gpu - f_ora| / max|f_ora|          <= 1e-12 (FP64), 1e-5 (FP32)
+  e_F = max_p |F_gpu - F_ora| / S_F               <= 1e-12 (FP64), 1e-4 (FP32)
+  e_T = max_p |T_gpu - T_ora| / max(S_T, r_max S_F)
+  where S_F, S_T are the force and torque scales of the run so far (largest
+  |F_ora|, |T_ora| over the particles and the steps checked): a force that
+  passes through zero makes a per-step ratio meaningless (the FP64 oracle
+  itself moves by 1e-11 relative at such steps when its state is perturbed
+  by one ulp), and a torque that vanishes by symmetry is measured against
+  r |F|.  Positions agree to the same relative tolerance times the
+  displacement, and the integer shifts k, the owner map and the site kinds are
+  bit-exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1105_2904_amd import lbm
+from paper_1105_2904_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": (1e-12, 1e-12), "fp32": (1e-5, 1e-4)}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    lbm.lib()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def make_pair(q, box, tau, storage, particles=None, gravity=(0, 0, 0), body_force=(0, 0, 0),
+              znf=False, f0=None, max_particles=None, max_radius=None):
+    n = 0 if particles is None else len(particles["radius"])
+    rmax = max_radius or (float(np.max(particles["radius"])) if n else 1.0)
+    sim = lbm.Simulation(q, *box, tau=tau, gravity=gravity, body_force=body_force, zero_net_force=znf,
+                         storage=storage, max_particles=max_particles or n, max_radius=rmax)
+    ora = oracle.Oracle(q, *box, tau, gravity=gravity, body_force=body_force, zero_net_force=znf)
+    if f0 is not None:
+        sim.set_distributions(f0)
+        ora.set_f(f0)
+    if n:
+        kw = dict(u=particles.get("u"), omega=particles.get("omega"), radius=particles["radius"],
+                  mass=particles["mass"], inertia=particles["inertia"])
+        sim.add_particles(particles["x"], **kw)
+        ora.add_particles(particles["x"], **kw)
+    sim.r_max = rmax
+    sim.scale = [0.0, 0.0]
+    sim.x_init = None if not n else np.array(particles["x"], dtype=np.float64).reshape(-1, 3)
+    return sim, ora
+
+
+def err_f(sim, ora):
+    fg, fo = sim.get_distributions(), ora.get_f()
+    return np.abs(fg - fo).max() / np.abs(fo).max()
+
+
+def err_vec(a, b, scale=0.0):
+    den = max(np.linalg.norm(b, axis=1).max(), scale)
+    return np.linalg.norm(a - b, axis=1).max() / den if den > 0 else np.abs(a - b).max()
+
+
+def compare_particles(sim, ora, tol_F, label=""):
+    Fg, Tg, xg, ug, wg = sim.forces()
+    Fo, To, xo, uo, wo = ora.forces()
+    sim.scale[0] = max(sim.scale[0], np.linalg.norm(Fo, axis=1).max())
+    sim.scale[1] = max(sim.scale[1], np.linalg.norm(To, axis=1).max())
+    eF = err_vec(Fg, Fo, sim.scale[0])
+    eT = err_vec(Tg, To, max(sim.scale[1], sim.r_max * sim.scale[0]))
+    assert eF <= tol_F, (label, "F", eF)
+    assert eT <= tol_F, (label, "T", eT)
+    assert np.array_equal(sim.shifts(), ora.shifts()), label
+    x0 = sim.x_init if sim.x_init is not None and len(sim.x_init) == len(xo) else xo
+    disp = max(np.abs(xo - x0).max(), 1e-6)
+    assert np.abs(xg - xo).max() <= tol_F * disp + 1e-13, (label, np.abs(xg - xo).max(), disp)
+    return eF, eT
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("q", [9, 19])
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_initial_state_is_exact(q, storage):
+    box = (33, 17, 1) if q == 9 else (19, 11, 7)
+    sim, ora = make_pair(q, box, 0.8, storage)
+    _say("initial state", q, storage, box)
+    assert np.array_equal(sim.get_distributions(), ora.get_f())
+    rho, u, own = sim.fields()
+    assert np.all(rho == 1.0) and np.all(u == 0.0) and np.all(own == -1)
+    assert np.all(sim.site_kind() == 0)
+
+
+@pytest.mark.parametrize("q", [9, 19])
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_lbgk_random_populations(q, storage):
+    """Plain collide + stream with a body force from random populations, on
+    boxes spanning several 256-wide sweep tiles with a ragged tail."""
+    box = (600, 9, 1) if q == 9 else (260, 6, 5)
+    fb = (1e-5, -2e-5, 0.0) if q == 9 else (1e-5, -2e-5, 1.5e-5)
+    _, w = oracle.lattice(q)
+    f0 = wl.random_populations(w, box[::-1], seed=21 + q, eps=0.05)
+    sim, ora = make_pair(q, box, 0.7, storage, body_force=fb, f0=f0)
+    _say("lbgk random", q, storage, box)
+    assert err_f(sim, ora) <= TOL[storage][0]
+    sim.step(25)
+    ora.step(25)
+    e = err_f(sim, ora)
+    _say("  e_f", e)
+    assert e <= TOL[storage][0]
+    rg, ug, _ = sim.fields()
+    ro, uo, _ = ora.fields()
+    assert np.abs(rg - ro).max() <= 10 * TOL[storage][0]
+    assert np.abs(ug - uo).max() <= 10 * TOL[storage][0]
+
+
+def test_kinematic_disk_fp64_1000_steps():
+    """D2Q9 tau 0.8, 64x64, one disk r = 8 at the centre with imposed velocity
+    (0.01, 0), FP64, 1000 steps: forces every step for the first 120 steps,
+    the shift sequence k(t), and all populations at the end."""
+    cfg = wl.kinematic_disk_config()
+    sim, ora = make_pair(9, cfg["box"], cfg["tau"], "fp64", particles=cfg["particles"])
+    _say("kinematic disk fp64")
+    assert sim.particle_info(0) == (60, 48)
+    for t in range(120):
+        sim.step(1)
+        ora.step(1)
+        compare_particles(sim, ora, 1e-12, "step %d" % t)
+    for t in range(120, 1000, 40):
+        sim.step(40)
+        ora.step(40)
+        compare_particles(sim, ora, 1e-12, "step %d" % t)
+    assert tuple(sim.shifts()[0]) == (10, 0, 0)
+    e = err_f(sim, ora)
+    _say("  e_f", e)
+    assert e <= 1e-12
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_suspension_2d(storage):
+    """Settling, rotating D2Q9 disks with a zero-net-force frame."""
+    box = (96, 80, 1)
+    p = wl.suspension(9, box, 6, 6.0, 1.5, seed=31)
+    p["omega"][:, 2] = np.linspace(-2e-3, 2e-3, 6)
+    p["u"][:, 0] = np.linspace(-0.01, 0.01, 6)
+    sim, ora = make_pair(9, box, 0.7, storage, particles=p, gravity=(0, -2e-4, 0), znf=True)
+    _say("suspension 2d", storage)
+    for chunk in range(10):
+        sim.step(20)
+        ora.step(20)
+        compare_particles(sim, ora, TOL[storage][1], "step %d" % (20 * chunk + 20))
+    e = err_f(sim, ora)
+    _say("  e_f", e)
+    assert e <= TOL[storage][0]
+    _, _, own_g = sim.fields()
+    _, _, own_o = ora.fields()
+    assert np.array_equal(own_g, own_o)
+    assert np.array_equal(sim.site_kind(), ora.site_kind())
+    assert np.abs(sim.shifts()).max() >= 1
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_suspension_3d(storage):
+    box = (40, 36, 32)
+    p = wl.suspension(19, box, 4, 4.5, 1.2, seed=32)
+    p["omega"][:, 1] = 1e-3
+    sim, ora = make_pair(19, box, 0.6, storage, particles=p, gravity=(0, 0, -3e-4), znf=True)
+    _say("suspension 3d", storage)
+    for chunk in range(6):
+        sim.step(10)
+        ora.step(10)
+        compare_particles(sim, ora, TOL[storage][1], "step %d" % (10 * chunk + 10))
+    e = err_f(sim, ora)
+    _say("  e_f", e)
+    assert e <= TOL[storage][0]
+    assert np.array_equal(sim.site_kind(), ora.site_kind())
+
+
+def test_hard_core_collisions():
+    """Many heavy disks with random velocities in a small periodic box: the
+    collision sequence (lexicographic pairs, minimum image, kinematic
+    partners) must reproduce the oracle's trajectories."""
+    rng = np.random.default_rng(41)
+    box = (48, 48, 1)
+    n = 14
+    x = wl.place_particles(box, np.full(n, 3.0), seed=41, min_gap=0.2)
+    u = np.zeros((n, 3))
+    u[:, :2] = rng.uniform(-0.08, 0.08, (n, 2))
+    m = np.full(n, 1e30)
+    m[0] = np.inf
+    p = {"x": x, "u": u, "omega": np.zeros((n, 3)), "radius": np.full(n, 3.0), "mass": m,
+         "inertia": np.full(n, 1e33)}
+    sim, ora = make_pair(9, box, 0.8, "fp64", particles=p)
+    _say("hard-core collisions")
+    for t in range(150):
+        sim.step(1)
+        ora.step(1)
+        _, _, xg, ug, _ = sim.forces()
+        _, _, xo, uo, _ = ora.forces()
+        assert np.abs(ug - uo).max() <= 1e-14, t
+        assert np.abs(xg - xo).max() <= 1e-12, t
+        assert np.array_equal(sim.shifts(), ora.shifts()), t
+    _, _, _, u_end, _ = ora.forces()
+    assert np.abs(u_end - u).max() > 0.01  # collisions happened
+
+
+def test_particles_added_in_two_batches():
+    box = (64, 48, 1)
+    p = wl.suspension(9, box, 5, 5.0, 1.5, seed=51)
+    first = {k: v[:3] for k, v in p.items()}
+    second = {k: v[3:] for k, v in p.items()}
+    sim, ora = make_pair(9, box, 0.75, "fp64", particles=first, gravity=(0, -1e-4, 0), znf=True,
+                         max_particles=5, max_radius=5.0)
+    _say("two batches")
+    sim.step(15)
+    ora.step(15)
+    kw = dict(u=second["u"], omega=second["omega"], radius=second["radius"], mass=second["mass"],
+              inertia=second["inertia"])
+    assert sim.add_particles(second["x"], **kw) == 3
+    ora.add_particles(second["x"], **kw)
+    sim.step(25)
+    ora.step(25)
+    compare_particles(sim, ora, 1e-12)
+    assert err_f(sim, ora) <= 1e-12
+
+
+def test_argument_errors():
+    box = (48, 48, 1)
+    sim = lbm.Simulation(9, *box, tau=0.8, storage="fp64", max_particles=2, max_radius=5.0)
+    with pytest.raises(lbm.LbmError) as e:
+        sim.add_particles([[10, 10, 0], [18, 10, 0]], radius=5.0, mass=10.0, inertia=10.0)
+    assert e.value.code == lbm.LBM_EOVERLAP
+    with pytest.raises(lbm.LbmError) as e:
+        sim.add_particles([[10, 10, 0], [30, 10, 0], [10, 30, 0]], radius=3.0, mass=1.0, inertia=1.0)
+    assert e.value.code == lbm.LBM_ECAPACITY
+    with pytest.raises(lbm.LbmError) as e:
+        sim.add_particles([[60, 10, 0]], radius=3.0, mass=1.0, inertia=1.0)
+    assert e.value.code == lbm.LBM_EINVAL
+    with pytest.raises(lbm.LbmError) as e:
+        sim.add_particles([[10, 10, 0]], radius=6.0, mass=1.0, inertia=1.0)
+    assert e.value.code == lbm.LBM_EINVAL
+    assert sim.add_particles([[3, 10, 0]], radius=5.0, mass=1.0, inertia=1.0) == 0
+    with pytest.raises(lbm.LbmError) as e:
+        sim.add_particles([[44, 10, 0]], radius=5.0, mass=1.0, inertia=1.0)  # overlaps through x = 0
+    assert e.value.code == lbm.LBM_EOVERLAP
+    sim.step(3)
+    sim.forces()
+
+
+def test_runs_are_bitwise_deterministic():
+    box = (40, 36, 32)
+    p = wl.suspension(19, box, 4, 4.5, 1.2, seed=61)
+    out = []
+    for _ in range(2):
+        sim = lbm.Simulation(19, *box, tau=0.6, gravity=(0, 0, -3e-4), zero_net_force=True,
+                             storage="fp32", max_particles=4, max_radius=4.5)
+        sim.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
+        sim.step(30)
+        out.append((sim.get_distributions(), sim.forces()))
+        sim.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    for a, b in zip(out[0][1], out[1][1]):
+        assert np.array_equal(a, b)
+
+
+def test_spheres_256cubed_500_full_size_fp32():
+    """The D3Q19 256^3 box with 500 spheres (r = 6, density ratio 1.2, gravity
+    1e-6) in FP32, in the configuration the benchmark times: per-particle
+    forces and torques of all 500 spheres, the shifts, and the populations at
+    20000 sampled sites after 3 steps."""
+    cfg = wl.spheres_3d_config()
+    sim, ora = make_pair(19, cfg["box"], cfg["tau"], "fp32", particles=cfg["particles"],
+                         gravity=cfg["gravity"], znf=True)
+    _say("full size 256^3, 500 spheres, fp32")
+    steps = 3
+    sim.step(steps)
+    ora.step(steps)
+    eF, eT = compare_particles(sim, ora, 1e-4)
+    _say("  e_F %.2e e_T %.2e" % (eF, eT))
+    fg, fo = sim.get_distributions(), ora.get_f()
+    idx = np.random.default_rng(3).integers(0, fg[0].size, 20000)
+    fg, fo = fg.reshape(19, -1)[:, idx], fo.reshape(19, -1)[:, idx]
+    e = np.abs(fg - fo).max() / np.abs(fo).max()
+    _say("  e_f(sampled) %.2e" % e)
+    assert e <= 1e-5
