@@ -2,20 +2,34 @@
 // method of dos Santos & Philippi, behind the C ABI of include/lbm.h.
 //
 // One time step is five launches on the caller's stream:
-//   sweep      pull-stream + BGK collide (+ uniform body force) over every
-//              site, A -> B.  HBM bound: reads q and writes q populations per
-//              site, structure-of-arrays, x fastest, coalesced.            eq. 1-4
-//   boundary   one workgroup per particle: BS substep on the current map
-//              (impose f^eq(rho_B, u_p + omega x r), momentum dp and angular
-//              momentum dl per site, deterministic wave-shuffle + LDS sum per
-//              particle), clears the particle's stamps, and lists the
-//              particles close enough to collide this step.              eq. 5-9
+//   sweep      one streaming pass over every site, A -> B (HBM bound; SoA,
+//              x fastest, coalesced): pull-propagation of the previous step
+//              with its pending IS substep folded into the pull, BGK collision
+//              with body force, and the BS substep at owned BS sites (the
+//              site's post-collision moments go to the entry's slot).
+//                                                          eq. 1-5, 12, 3 (left)
+//   reduce     one workgroup per particle: momentum dp and angular momentum dl
+//              of every owned BS site from its slot, deterministic
+//              wave-shuffle + LDS sums, release of the particle's stamps, and
+//              the list of particles close enough to collide.         eq. 6-9
 //   particles  one workgroup: Newton-Euler update with buoyancy-corrected
 //              weight, hard-core collisions in lexicographic pair order,
 //              translation and integer shift.               eq. 10-11, 13, 16-19
-//   stamp      rebuild the site -> particle map at the new shifts
-//              (atomicMin of the global entry index: lowest id wins).   eq. 14-15
-//   internal   IS substep at the new positions.                            eq. 12
+//   stamp      rebuild the maps at the new shifts: the owner map (lowest BS/IS
+//              entry index, hence lowest particle id) and the ball map (lowest
+//              entry of any kind: one representative entry per ball site).
+//                                                                    eq. 14-15
+//   prepare    one thread per ball site: the record the next sweep needs there
+//              -- which incoming populations leave a pending IS site, their
+//              values f^eq_i(rho_I, u_p' + omega_p' x r) (IS substep at the new
+//              positions, eq. 12), and for an owned BS site its rigid-body
+//              velocity u_p + omega x r (eq. 5).
+// The IS substep of step t acts on the post-collision populations of IS sites
+// just before they propagate, so the sweep of step t+1 applies it while
+// pulling.  Every link of an IS site stays inside its particle's ball, so only
+// ball sites receive such populations; everywhere else the sweep reads one
+// map word and nothing more.  Read-outs first write the pending values into
+// the state (k_materialize).
 // The populations are stored as deviations g_i = f_i - w_i rho0 so that the
 // momentum differences behind the particle forces survive FP32 storage.
 #include <hip/hip_runtime.h>
@@ -32,11 +46,11 @@
 
 namespace {
 
-constexpr int kEmpty = 0x7fffffff;  // map value of a site owned by no particle
+constexpr int kEmpty = 0x7fffffff;  // map value of a site no entry claims
 constexpr int kCandMax = 64;        // close neighbours listed per particle
 constexpr double kMargin = 1.0;     // candidate search margin (lattice units)
 constexpr int kSweepBlock = 256;
-constexpr int kBoundaryBlock = 256;
+constexpr int kBoundaryBlock = 256;  // reduce workgroup
 constexpr int kParticleBlock = 1024;
 constexpr int kStatusCollision = 1;
 constexpr size_t kAlign = 256;
@@ -68,13 +82,13 @@ struct DevParticles {
   double *x, *x0, *u, *om, *phi, *fext, *dP, *dL, *F, *T;  // [n][3]
   double *m, *I, *rad;                                     // [n]
   int *b0, *k;                                             // [n][3]
-  int *ent0, *nbs, *nis, *cand_n;                          // [n]
+  int *ent0, *nbs, *nis, *nin, *cand_n, *jump;             // [n]
   int *cand;                                               // [n][kCandMax]
   int *pairs;                                              // [n*kCandMax][2]
 };
 
 struct DevEntries {
-  int* off;  // packed int8 offsets x,y,z and kind (1 BS, 2 IS) in the top byte
+  int* off;  // packed int8 offsets x,y,z and kind (1 BS, 2 IS, 3 interior) in the top byte
   int* pid;  // owner particle
 };
 
@@ -100,7 +114,48 @@ __device__ __forceinline__ int entry_site(const DevParticles& P, const Geo& G, i
 }
 
 // ---------------------------------------------------------------------------
-// K1: fused pull-stream + BGK collision (eq. 1-3) over every site.
+// Ball-site records.  ball[s] holds the lowest entry index of any kind stamped
+// at s (kEmpty outside every ball); the record of that representative entry
+// b describes site s for the next sweep:
+//   hdr[b] = {mask, bs}: bit i of mask set if population i arrives from a
+//            pending IS site, its value being sub[b*q + i]; bs = the BS entry
+//            that owns s (-1 if none), whose rigid-body velocity is vel[b].
+// ---------------------------------------------------------------------------
+template <typename T>
+struct SiteArgs {
+  const int* ball;
+  const int2* hdr;
+  const typename Store<T>::C* vel;  // [entry][4]
+  const T* sub;                     // [entry][q]
+  double* slot;                     // [entry][4]: post-collision drho, j of an owned BS site
+  typename Store<T>::C* drho;       // density deviation of every site (this sweep)
+};
+
+// Deviation f^eq_i(rho, u) - w_i rho0 at the velocity u_p + omega_p x r of
+// entry e: the IS imposition (eq. 12, fourth substep) when e is an IS entry.
+template <int Q>
+__device__ __forceinline__ double rigid_feq(int i, int e, double drho, const DevParticles& P,
+                                            const DevEntries& E, double rho0) {
+  using L = Lattice<Q>;
+  const int p = E.pid[e];
+  const int pk = E.off[e];
+  const double rx = (double)off_x(pk) - P.phi[3 * p], ry = (double)off_y(pk) - P.phi[3 * p + 1],
+               rz = (double)off_z(pk) - P.phi[3 * p + 2];
+  const double wx = P.om[3 * p], wy = P.om[3 * p + 1], wz = P.om[3 * p + 2];
+  const double vx = P.u[3 * p] + (wy * rz - wz * ry);
+  const double vy = P.u[3 * p + 1] + (wz * rx - wx * rz);
+  const double vz = P.u[3 * p + 2] + (wx * ry - wy * rx);
+  const double rho = rho0 + drho;
+  const double usq = 1.5 * (vx * vx + vy * vy + vz * vz);
+  const double cu = L::cx(i) * vx + L::cy(i) * vy + L::cz(i) * vz;
+  return L::w(i) * (drho + rho * (3.0 * cu + 4.5 * cu * cu - usq));
+}
+
+// ---------------------------------------------------------------------------
+// K1: one pass over every site = propagation of the previous step (pull), the
+// pending IS substep of the previous step folded into that pull, BGK
+// collision with body force (eq. 1-3), and the BS substep at owned BS sites
+// (eq. 5-7) with dp, dl written to the entry's slot.
 // ---------------------------------------------------------------------------
 template <int Q, typename C>
 struct SweepArgs {
@@ -111,14 +166,14 @@ struct SweepArgs {
   C fbt[Q];  // 3 w_i c_i . f_b
 };
 
-template <int Q, typename T>
+template <int Q, typename T, bool PART>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, T* __restrict__ B,
-                                                        SweepArgs<Q, typename Store<T>::C> a) {
+                                                        SweepArgs<Q, typename Store<T>::C> a, SiteArgs<T> sa) {
   using L = Lattice<Q>;
   using C = typename Store<T>::C;
-  const int b = blockIdx.x;
-  const int row = b / a.nxb;
-  const int x = (b - row * a.nxb) * kSweepBlock + threadIdx.x;
+  const int blk = blockIdx.x;
+  const int row = blk / a.nxb;
+  const int x = (blk - row * a.nxb) * kSweepBlock + threadIdx.x;
   if (x >= a.nx) return;
   const int y = row % a.ny;
   const int z = row / a.ny;
@@ -135,6 +190,21 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, 
     const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
     const int sz = L::cz(i) > 0 ? zm : (L::cz(i) < 0 ? zp : z);
     g[i] = Store<T>::ld(A + (size_t)i * a.N + (sx + a.nx * (sy + a.ny * sz)));
+  }
+  const int b = PART ? sa.ball[s] : kEmpty;
+  int bs = -1;
+  if (PART && b != kEmpty) {
+    // a ball site: populations arriving from a pending internal site left it
+    // as the imposed equilibrium
+    const int2 h = sa.hdr[b];
+    bs = h.y;
+    const unsigned mask = (unsigned)h.x;
+    if (mask) {
+      const T* sub = sa.sub + (size_t)b * Q;
+#pragma unroll
+      for (int i = 0; i < Q; i++)
+        if (mask & (1u << i)) g[i] = Store<T>::ld(sub + i);
+    }
   }
   C drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
@@ -155,8 +225,41 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, 
   for (int i = 0; i < Q; i++) {
     const C cu = C(L::cx(i)) * ux + C(L::cy(i)) * uy + C(L::cz(i)) * uz;
     const C geq = C(L::w(i)) * (drho + rho * (C(3) * cu + C(4.5) * cu * cu - usq));
-    Store<T>::st(B + (size_t)i * a.N + s, g[i] + a.omega * (geq - g[i]) + a.fbt[i]);
+    g[i] = g[i] + a.omega * (geq - g[i]) + a.fbt[i];
   }
+  if (PART && b != kEmpty) {
+    sa.drho[s] = drho;
+    if (bs >= 0) {
+      // BS substep at a site entry bs owns: its post-collision moments go to
+      // the slot (FP64 sums), and the populations become f^eq(rho_B, u_B')
+      // with the rigid-body velocity u_B' = u_p + omega x r of the site
+      double dr = 0, bx = 0, by = 0, bz = 0;
+#pragma unroll
+      for (int i = 0; i < Q; i++) {
+        const double v = (double)g[i];
+        dr += v;
+        bx += L::cx(i) * v;
+        by += L::cy(i) * v;
+        bz += L::cz(i) * v;
+      }
+      double* sl = sa.slot + 4 * (size_t)bs;
+      sl[0] = dr;
+      sl[1] = bx;
+      sl[2] = by;
+      sl[3] = bz;
+      const C vx = sa.vel[4 * (size_t)b], vy = sa.vel[4 * (size_t)b + 1], vz = sa.vel[4 * (size_t)b + 2];
+      const C drB = (C)dr;
+      const C rhoB = a.rho0 + drB;
+      const C usqB = C(1.5) * (vx * vx + vy * vy + vz * vz);
+#pragma unroll
+      for (int i = 0; i < Q; i++) {
+        const C cu = C(L::cx(i)) * vx + C(L::cy(i)) * vy + C(L::cz(i)) * vz;
+        g[i] = C(L::w(i)) * (drB + rhoB * (C(3) * cu + C(4.5) * cu * cu - usqB));
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < Q; i++) Store<T>::st(B + (size_t)i * a.N + s, g[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -169,68 +272,54 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// K2: BS substep (eq. 5-9), one workgroup per particle.
+// K2: per-particle sums of the BS slots (eq. 8-9) in a fixed order, release
+// of the particle's stamps, and the list of particles close enough to collide
+// this step.  One workgroup per particle.
 // ---------------------------------------------------------------------------
-template <int Q, typename T>
-__global__ __launch_bounds__(kBoundaryBlock) void k_boundary(T* __restrict__ B, int* __restrict__ map,
-                                                              DevParticles P, DevEntries E, Geo G,
-                                                              int np, double rho0, int* status) {
-  using L = Lattice<Q>;
+__global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own, int* __restrict__ ball,
+                                                            const double* __restrict__ slot,
+                                                            DevParticles P, DevEntries E, Geo G, int np,
+                                                            double rho0, int* status) {
   constexpr int kWaves = kBoundaryBlock / 64;
   __shared__ double s_part[kWaves][6];
   __shared__ int s_cnt[kWaves];
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
+  const int e0 = P.ent0[p], nbs = P.nbs[p], nis = P.nis[p], nin = P.nin[p];
   const double phx = P.phi[3 * p], phy = P.phi[3 * p + 1], phz = P.phi[3 * p + 2];
   const double upx = P.u[3 * p], upy = P.u[3 * p + 1], upz = P.u[3 * p + 2];
   const double wx = P.om[3 * p], wy = P.om[3 * p + 1], wz = P.om[3 * p + 2];
-  const int e0 = P.ent0[p], nbs = P.nbs[p], nis = P.nis[p];
 
   double acc[6] = {0, 0, 0, 0, 0, 0};
   for (int t = tid; t < nbs; t += kBoundaryBlock) {
     const int e = e0 + t;
     const int pk = E.off[e];
     const int s = entry_site(P, G, p, pk);
-    if (map[s] != e) continue;  // owned by a lower id
-    map[s] = kEmpty;            // only the owner clears its site
-    double g[Q];
-    double drho = 0, jx = 0, jy = 0, jz = 0;
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-      g[i] = (double)B[(size_t)i * G.N + s];
-      drho += g[i];
-      jx += L::cx(i) * g[i];
-      jy += L::cy(i) * g[i];
-      jz += L::cz(i) * g[i];
-    }
-    const double rho = rho0 + drho;
-    const double ubx = jx / rho, uby = jy / rho, ubz = jz / rho;
-    // lever arm x_B - x_p = o - phi, constant while the site set translates
-    const double rx = (double)off_x(pk) - phx, ry = (double)off_y(pk) - phy,
-                 rz = (double)off_z(pk) - phz;
-    // u_B' = u_p + omega x r
+    ball[s] = kEmpty;
+    if (own[s] != e) continue;  // owned by a lower id: not imposed
+    own[s] = kEmpty;            // only the owner clears its site
+    // dp = rho_B (u_B' - u_B), dl = r x dp with the post-collision moments
+    const double rhoB = rho0 + slot[4 * (size_t)e];
+    const double ubx = slot[4 * (size_t)e + 1] / rhoB, uby = slot[4 * (size_t)e + 2] / rhoB,
+                 ubz = slot[4 * (size_t)e + 3] / rhoB;
+    const double rx = (double)off_x(pk) - phx, ry = (double)off_y(pk) - phy, rz = (double)off_z(pk) - phz;
     const double vx = upx + (wy * rz - wz * ry);
     const double vy = upy + (wz * rx - wx * rz);
     const double vz = upz + (wx * ry - wy * rx);
-    const double dpx = rho * (vx - ubx), dpy = rho * (vy - uby), dpz = rho * (vz - ubz);
+    const double dpx = rhoB * (vx - ubx), dpy = rhoB * (vy - uby), dpz = rhoB * (vz - ubz);
     acc[0] += dpx;
     acc[1] += dpy;
     acc[2] += dpz;
     acc[3] += ry * dpz - rz * dpy;
     acc[4] += rz * dpx - rx * dpz;
     acc[5] += rx * dpy - ry * dpx;
-    const double usq = 1.5 * (vx * vx + vy * vy + vz * vz);
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-      const double cu = L::cx(i) * vx + L::cy(i) * vy + L::cz(i) * vz;
-      B[(size_t)i * G.N + s] = (T)(L::w(i) * (drho + rho * (3.0 * cu + 4.5 * cu * cu - usq)));
-    }
   }
-  for (int t = tid; t < nis; t += kBoundaryBlock) {
+  for (int t = tid; t < nis + nin; t += kBoundaryBlock) {
     const int e = e0 + nbs + t;
     const int s = entry_site(P, G, p, E.off[e]);
-    if (map[s] == e) map[s] = kEmpty;
+    ball[s] = kEmpty;
+    if (t < nis && own[s] == e) own[s] = kEmpty;
   }
 #pragma unroll
   for (int c = 0; c < 6; c++) {
@@ -389,57 +478,145 @@ __global__ __launch_bounds__(kParticleBlock) void k_particles(DevParticles P, in
   }
   __syncthreads();
   for (int p = tid; p < np; p += kParticleBlock) {
+    int moved = 0;
     for (int a = 0; a < dim; a++) {
       const double x = P.x[3 * p + a] + P.u[3 * p + a];
       P.x[3 * p + a] = x;
-      P.k[3 * p + a] = (int)floor(x - P.x0[3 * p + a] + 0.5);
+      const int k = (int)floor(x - P.x0[3 * p + a] + 0.5);
+      moved += k != P.k[3 * p + a];
+      P.k[3 * p + a] = k;
     }
+    // a shift along all three axes at once (not a D3Q19 link) can take an IS
+    // site outside the ball the sweep kept densities for
+    P.jump[p] = moved == 3;
   }
 }
 
 // ---------------------------------------------------------------------------
-// K4: stamp every template entry at its particle's shift; lowest entry index
-// (hence lowest particle id) owns a site.
+// K4: stamp every template entry at its particle's shift.  BS/IS entries
+// claim the owner map (lowest index, hence lowest particle id, wins); every
+// entry claims the ball map, whose lowest entry represents the site.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_stamp(int* __restrict__ map, DevParticles P, DevEntries E,
-                                                Geo G, int e_begin, int e_end) {
+__global__ __launch_bounds__(256) void k_stamp(int* __restrict__ own, int* __restrict__ ball, DevParticles P,
+                                                DevEntries E, Geo G, int e_begin, int e_end) {
   const int e = e_begin + blockIdx.x * 256 + threadIdx.x;
   if (e >= e_end) return;
-  const int s = entry_site(P, G, E.pid[e], E.off[e]);
-  atomicMin(&map[s], e);
+  const int pk = E.off[e];
+  const int s = entry_site(P, G, E.pid[e], pk);
+  atomicMin(&ball[s], e);
+  if (entry_kind(pk) != 3) atomicMin(&own[s], e);
 }
 
 // ---------------------------------------------------------------------------
-// K5: IS substep at the new positions (eq. 12): f^eq(rho_I, u_p' + omega_p' x r).
+// K5: IS substep at the new positions (eq. 12), computed once per owned IS
+// site: the q populations f^eq(rho_I, u_p' + omega_p' x r), rho_I being the
+// site's post-collision density (kept by this step's sweep for ball sites;
+// summed from the populations after a diagonal jump).
 // ---------------------------------------------------------------------------
 template <int Q, typename T>
-__global__ __launch_bounds__(256) void k_internal(T* __restrict__ B, const int* __restrict__ map,
-                                                   DevParticles P, DevEntries E, Geo G, int nent,
-                                                   double rho0) {
-  using L = Lattice<Q>;
+__global__ __launch_bounds__(256) void k_isval(const int* __restrict__ own, T* __restrict__ isval,
+                                                const typename Store<T>::C* __restrict__ drho,
+                                                const T* __restrict__ B, DevParticles P, DevEntries E, Geo G,
+                                                int nent, double rho0) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= nent) return;
   const int pk = E.off[e];
   if (entry_kind(pk) != 2) return;
   const int p = E.pid[e];
   const int s = entry_site(P, G, p, pk);
-  if (map[s] != e) return;
-  double drho = 0;
+  if (own[s] != e) return;
+  double dr = 0;
+  if (P.jump[p]) {
 #pragma unroll
-  for (int i = 0; i < Q; i++) drho += (double)B[(size_t)i * G.N + s];
-  const double rho = rho0 + drho;
-  const double rx = (double)off_x(pk) - P.phi[3 * p], ry = (double)off_y(pk) - P.phi[3 * p + 1],
-               rz = (double)off_z(pk) - P.phi[3 * p + 2];
-  const double wx = P.om[3 * p], wy = P.om[3 * p + 1], wz = P.om[3 * p + 2];
-  const double vx = P.u[3 * p] + (wy * rz - wz * ry);
-  const double vy = P.u[3 * p + 1] + (wz * rx - wx * rz);
-  const double vz = P.u[3 * p + 2] + (wx * ry - wy * rx);
-  const double usq = 1.5 * (vx * vx + vy * vy + vz * vz);
-#pragma unroll
-  for (int i = 0; i < Q; i++) {
-    const double cu = L::cx(i) * vx + L::cy(i) * vy + L::cz(i) * vz;
-    B[(size_t)i * G.N + s] = (T)(L::w(i) * (drho + rho * (3.0 * cu + 4.5 * cu * cu - usq)));
+    for (int i = 0; i < Q; i++) dr += (double)B[(size_t)i * G.N + s];
+  } else {
+    dr = (double)drho[s];
   }
+#pragma unroll
+  for (int i = 0; i < Q; i++) isval[(size_t)e * Q + i] = (T)rigid_feq<Q>(i, e, dr, P, E, rho0);
+}
+
+// ---------------------------------------------------------------------------
+// K6: record of every ball site for the next sweep.  With pending = 1,
+// population i of site s arrives from s - c_i, and if that site is an owned
+// IS site it arrives as the value K5 prepared.  For an owned BS site the
+// rigid-body velocity of the next BS substep is stored (eq. 5).
+// ---------------------------------------------------------------------------
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own, const int* __restrict__ ball,
+                                                  int2* __restrict__ hdr, typename Store<T>::C* __restrict__ vel,
+                                                  T* __restrict__ sub, const T* __restrict__ isval,
+                                                  DevParticles P, DevEntries E, Geo G, int nent, int pending) {
+  using L = Lattice<Q>;
+  using C = typename Store<T>::C;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= nent) return;
+  const int p = E.pid[e];
+  const int pk = E.off[e];
+  const int x = wrap(P.b0[3 * p] + P.k[3 * p] + off_x(pk), G.nx);
+  const int y = wrap(P.b0[3 * p + 1] + P.k[3 * p + 1] + off_y(pk), G.ny);
+  const int z = wrap(P.b0[3 * p + 2] + P.k[3 * p + 2] + off_z(pk), G.nz);
+  const int s = x + G.nx * (y + G.ny * z);
+  if (ball[s] != e) return;  // another entry represents this site
+  unsigned mask = 0;
+  if (pending) {
+    int o[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++)
+      o[i] = own[wrap(x - L::cx(i), G.nx) + G.nx * (wrap(y - L::cy(i), G.ny) + G.ny * wrap(z - L::cz(i), G.nz))];
+#pragma unroll
+    for (int i = 0; i < Q; i++)
+      if (o[i] != kEmpty && entry_kind(E.off[o[i]]) == 2) {
+        mask |= 1u << i;
+        sub[(size_t)e * Q + i] = isval[(size_t)o[i] * Q + i];
+      }
+  }
+  int bs = -1;
+  const int o = own[s];
+  if (o != kEmpty && entry_kind(E.off[o]) == 1) {
+    bs = o;
+    const int q = E.pid[o];
+    const int ok = E.off[o];
+    const double rx = (double)off_x(ok) - P.phi[3 * q], ry = (double)off_y(ok) - P.phi[3 * q + 1],
+                 rz = (double)off_z(ok) - P.phi[3 * q + 2];
+    const double wx = P.om[3 * q], wy = P.om[3 * q + 1], wz = P.om[3 * q + 2];
+    vel[4 * (size_t)e] = (C)(P.u[3 * q] + (wy * rz - wz * ry));
+    vel[4 * (size_t)e + 1] = (C)(P.u[3 * q + 1] + (wz * rx - wx * rz));
+    vel[4 * (size_t)e + 2] = (C)(P.u[3 * q + 2] + (wx * ry - wy * rx));
+  }
+  hdr[e] = make_int2((int)mask, bs);
+}
+
+// Read-outs and overwrites: retire the pending IS substep.  write = 1 puts the
+// prepared populations into the state in place (exactly what the next sweep
+// would have pulled); write = 0 drops them (the state was replaced).
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_materialize(T* __restrict__ S, const int* __restrict__ ball,
+                                                      int2* __restrict__ hdr, const T* __restrict__ sub,
+                                                      DevParticles P, DevEntries E, Geo G, int nent, int write) {
+  using L = Lattice<Q>;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= nent) return;
+  const int p = E.pid[e];
+  const int pk = E.off[e];
+  const int x = wrap(P.b0[3 * p] + P.k[3 * p] + off_x(pk), G.nx);
+  const int y = wrap(P.b0[3 * p + 1] + P.k[3 * p + 1] + off_y(pk), G.ny);
+  const int z = wrap(P.b0[3 * p + 2] + P.k[3 * p + 2] + off_z(pk), G.nz);
+  const int s = x + G.nx * (y + G.ny * z);
+  if (ball[s] != e) return;
+  int2 h = hdr[e];
+  if (h.x == 0) return;
+  if (write) {
+    // the pulled population i of s is the state's population i at s - c_i
+#pragma unroll
+    for (int i = 0; i < Q; i++)
+      if (h.x & (1 << i)) {
+        const int src = wrap(x - L::cx(i), G.nx) + G.nx * (wrap(y - L::cy(i), G.ny) + G.ny * wrap(z - L::cz(i), G.nz));
+        S[(size_t)i * G.N + src] = sub[(size_t)e * Q + i];
+      }
+  }
+  h.x = 0;
+  hdr[e] = h;
 }
 
 // ---------------------------------------------------------------------------
@@ -492,9 +669,10 @@ __global__ void k_fill(V* __restrict__ p, int64_t n, V v) {
 
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
-__global__ void k_copy16(const v4u* __restrict__ src, v4u* __restrict__ dst, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    __builtin_nontemporal_store(src[i], dst + i);
+// one 16-byte vector per thread, streaming store
+__global__ __launch_bounds__(256) void k_copy16(const v4u* __restrict__ src, v4u* __restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) __builtin_nontemporal_store(src[i], dst + i);
 }
 
 inline unsigned blocks_for(int64_t n, int per = 256) { return (unsigned)((n + per - 1) / per); }
@@ -503,9 +681,9 @@ inline unsigned blocks_for(int64_t n, int per = 256) { return (unsigned)((n + pe
 // Workspace layout
 // ---------------------------------------------------------------------------
 struct Layout {
-  size_t f[2], map, status;
-  size_t x, x0, u, om, phi, fext, dP, dL, F, T, m, I, rad, b0, k, ent0, nbs, nis, cand_n, cand, pairs;
-  size_t off, pid;
+  size_t f[2], drho, own, ball, status;
+  size_t x, x0, u, om, phi, fext, dP, dL, F, T, m, I, rad, b0, k, ent0, nbs, nis, nin, jump, cand_n, cand, pairs;
+  size_t off, pid, slot, hdr, vel, sub, isval;
   int64_t max_ent;
   size_t total;
 };
@@ -532,7 +710,9 @@ Layout make_layout(const lbm_params& p) {
   const size_t fb = (size_t)p.lattice * N * store_size(p.storage);
   L.f[0] = take(fb);
   L.f[1] = take(fb);
-  L.map = take(sizeof(int) * N);
+  L.drho = take((size_t)N * (p.storage == LBM_FP64 ? 8 : 4));
+  L.own = take(sizeof(int) * N);
+  L.ball = take(sizeof(int) * N);
   L.status = take(64);
   const size_t v3 = sizeof(double) * 3 * np, v1 = sizeof(double) * np;
   L.x = take(v3); L.x0 = take(v3); L.u = take(v3); L.om = take(v3); L.phi = take(v3);
@@ -540,11 +720,18 @@ Layout make_layout(const lbm_params& p) {
   L.m = take(v1); L.I = take(v1); L.rad = take(v1);
   L.b0 = take(sizeof(int) * 3 * np); L.k = take(sizeof(int) * 3 * np);
   L.ent0 = take(sizeof(int) * np); L.nbs = take(sizeof(int) * np); L.nis = take(sizeof(int) * np);
+  L.nin = take(sizeof(int) * np);
+  L.jump = take(sizeof(int) * np);
   L.cand_n = take(sizeof(int) * np);
   L.cand = take(sizeof(int) * np * kCandMax);
   L.pairs = take(sizeof(int) * 2 * np * kCandMax);
   L.off = take(sizeof(int) * L.max_ent);
   L.pid = take(sizeof(int) * L.max_ent);
+  L.slot = take(sizeof(double) * 4 * L.max_ent);
+  L.hdr = take(sizeof(int) * 2 * L.max_ent);
+  L.vel = take((p.storage == LBM_FP64 ? 8 : 4) * 4 * L.max_ent);
+  L.sub = take((size_t)p.lattice * store_size(p.storage) * L.max_ent);
+  L.isval = take((size_t)p.lattice * store_size(p.storage) * L.max_ent);
   L.total = cur;
   return L;
 }
@@ -580,14 +767,21 @@ struct lbm_ctx {
   Layout L;
   void* f[2];
   int cur;  // f[cur] holds the post-collision state of the last step
-  int* map;
+  void* drho;
+  double* slot;
+  int2* hdr;
+  void* vel;
+  void* sub;
+  void* isval;
+  int* own;   // owner map: lowest BS/IS entry per site
+  int* ball;  // ball map: lowest entry of any kind per site
   int* status;
   DevParticles P;
   DevEntries E;
   int np;
   int64_t nent;
   std::vector<double> h_x0, h_rad, h_m, h_I, h_fext;
-  std::vector<int> h_off, h_pid, h_nbs, h_nis;
+  std::vector<int> h_off, h_pid, h_nbs, h_nis, h_nin;
   double fb[3];  // fluid body force density
   bool prof;
   std::vector<hipEvent_t> ev;
@@ -600,6 +794,35 @@ struct lbm_ctx {
   } while (0)
 
 namespace {
+
+template <int Q, typename T>
+SiteArgs<T> site_args(lbm_ctx* c) {
+  SiteArgs<T> sa;
+  sa.ball = c->ball;
+  sa.hdr = c->hdr;
+  sa.vel = (const typename Store<T>::C*)c->vel;
+  sa.sub = (const T*)c->sub;
+  sa.slot = c->slot;
+  sa.drho = (typename Store<T>::C*)c->drho;
+  return sa;
+}
+
+// Records of every ball site for the next sweep; with pending = 1 the IS
+// substep of the step that just ran is prepared first.
+template <int Q, typename T>
+int launch_prepare(lbm_ctx* c, int pending) {
+  if (c->nent > 0) {
+    if (pending)
+      k_isval<Q, T><<<blocks_for(c->nent), 256, 0, c->stream>>>(
+          c->own, (T*)c->isval, (const typename Store<T>::C*)c->drho, (const T*)c->f[c->cur], c->P, c->E, c->G,
+          (int)c->nent, c->prm.rho0);
+    k_prepare<Q, T><<<blocks_for(c->nent), 256, 0, c->stream>>>(
+        c->own, c->ball, c->hdr, (typename Store<T>::C*)c->vel, (T*)c->sub, (const T*)c->isval, c->P, c->E,
+        c->G, (int)c->nent, pending);
+    HIP_TRY(hipGetLastError());
+  }
+  return LBM_OK;
+}
 
 template <int Q, typename T>
 int launch_step(lbm_ctx* c) {
@@ -619,6 +842,7 @@ int launch_step(lbm_ctx* c) {
   }
   const T* A = (const T*)c->f[c->cur];
   T* B = (T*)c->f[1 - c->cur];
+  const SiteArgs<T> sa = site_args<Q, T>(c);
   const unsigned nblk = (unsigned)((int64_t)a.nxb * c->G.ny * c->G.nz);
   if (c->prof) {
     if (c->ev_used + 2 > c->ev.size()) {
@@ -630,22 +854,36 @@ int launch_step(lbm_ctx* c) {
     }
     HIP_TRY(hipEventRecord(c->ev[c->ev_used], c->stream));
   }
-  k_sweep<Q, T><<<nblk, kSweepBlock, 0, c->stream>>>(A, B, a);
+  if (c->np > 0)
+    k_sweep<Q, T, true><<<nblk, kSweepBlock, 0, c->stream>>>(A, B, a, sa);
+  else
+    k_sweep<Q, T, false><<<nblk, kSweepBlock, 0, c->stream>>>(A, B, a, sa);
   if (c->prof) {
     HIP_TRY(hipEventRecord(c->ev[c->ev_used + 1], c->stream));
     c->ev_used += 2;
   }
   HIP_TRY(hipGetLastError());
   if (c->np > 0) {
-    k_boundary<Q, T><<<c->np, kBoundaryBlock, 0, c->stream>>>(B, c->map, c->P, c->E, c->G, c->np,
-                                                              c->prm.rho0, c->status);
+    k_reduce<<<c->np, kBoundaryBlock, 0, c->stream>>>(c->own, c->ball, c->slot, c->P, c->E, c->G, c->np,
+                                                      c->prm.rho0, c->status);
     k_particles<<<1, kParticleBlock, 0, c->stream>>>(c->P, c->np, c->dim, c->G, c->status);
-    k_stamp<<<blocks_for(c->nent), 256, 0, c->stream>>>(c->map, c->P, c->E, c->G, 0, (int)c->nent);
-    k_internal<Q, T><<<blocks_for(c->nent), 256, 0, c->stream>>>(B, c->map, c->P, c->E, c->G,
-                                                                 (int)c->nent, c->prm.rho0);
+    k_stamp<<<blocks_for(c->nent), 256, 0, c->stream>>>(c->own, c->ball, c->P, c->E, c->G, 0, (int)c->nent);
     HIP_TRY(hipGetLastError());
   }
-  c->cur = 1 - c->cur;
+  c->cur = 1 - c->cur;  // f[cur] now holds this step's post-collision state
+  if (c->np > 0) return launch_prepare<Q, T>(c, 1);
+  return LBM_OK;
+}
+
+// Retire the pending IS substep: write = 1 puts it into the current state
+// (read-outs), write = 0 drops it (the state is being replaced).
+template <int Q, typename T>
+int launch_materialize(lbm_ctx* c, int write) {
+  if (c->nent > 0) {
+    k_materialize<Q, T><<<blocks_for(c->nent), 256, 0, c->stream>>>(
+        (T*)c->f[c->cur], c->ball, c->hdr, (const T*)c->sub, c->P, c->E, c->G, (int)c->nent, write);
+    HIP_TRY(hipGetLastError());
+  }
   return LBM_OK;
 }
 
@@ -674,9 +912,9 @@ double lattice_w(int q, int i) { return q == 9 ? Lattice<9>::w(i) : Lattice<19>:
 
 // Template of one particle (section 2.2): digitised ball |o - phi| <= r, BS
 // = ball sites linked (any lattice velocity) to a site outside the ball, IS =
-// other ball sites linked to a BS site.  Entries: BS first, then IS, each in
-// z, y, x order.
-void build_template(int q, double r, const double phi[3], std::vector<int>& out, int* nbs, int* nis) {
+// other ball sites linked to a BS site, interior = the remaining ball sites.
+// Entries: BS, then IS, then interior, each in z, y, x order.
+void build_template(int q, double r, const double phi[3], std::vector<int>& out, int* nbs, int* nis, int* nin) {
   const int dim = q == 9 ? 2 : 3;
   const int R = (int)std::ceil(r) + 1;
   const int h = R + 1, ext = 2 * R + 3;
@@ -695,7 +933,7 @@ void build_template(int q, double r, const double phi[3], std::vector<int>& out,
         const double dx = x - phi[0], dy = y - phi[1], dz = z - phi[2];
         in[gi(x, y, z)] = dx * dx + dy * dy + dz * dz <= r * r;
       }
-  *nbs = *nis = 0;
+  *nbs = *nis = *nin = 0;
   for (int z = -Rz; z <= Rz; z++)
     for (int y = -R; y <= R; y++)
       for (int x = -R; x <= R; x++) {
@@ -716,13 +954,15 @@ void build_template(int q, double r, const double phi[3], std::vector<int>& out,
             break;
           }
       }
-  for (int kind = 1; kind <= 2; kind++)
+  for (int kind = 1; kind <= 3; kind++)
     for (int z = -Rz; z <= Rz; z++)
       for (int y = -R; y <= R; y++)
         for (int x = -R; x <= R; x++) {
-          if (!(kind == 1 ? bs[gi(x, y, z)] : is[gi(x, y, z)])) continue;
+          const size_t g = gi(x, y, z);
+          const bool take = kind == 1 ? bs[g] : kind == 2 ? is[g] : (in[g] && !bs[g] && !is[g]);
+          if (!take) continue;
           out.push_back(pack_entry(x, y, z, kind));
-          (kind == 1 ? *nbs : *nis) += 1;
+          (kind == 1 ? *nbs : kind == 2 ? *nis : *nin) += 1;
         }
 }
 
@@ -787,7 +1027,14 @@ int lbm_create(const lbm_params* prm, void* d_workspace, size_t bytes, void* hip
   c->f[0] = c->ws + L.f[0];
   c->f[1] = c->ws + L.f[1];
   c->cur = 0;
-  c->map = (int*)(c->ws + L.map);
+  c->drho = c->ws + L.drho;
+  c->slot = (double*)(c->ws + L.slot);
+  c->hdr = (int2*)(c->ws + L.hdr);
+  c->vel = c->ws + L.vel;
+  c->sub = c->ws + L.sub;
+  c->isval = c->ws + L.isval;
+  c->own = (int*)(c->ws + L.own);
+  c->ball = (int*)(c->ws + L.ball);
   c->status = (int*)(c->ws + L.status);
   char* w = c->ws;
   c->P = DevParticles{(double*)(w + L.x),    (double*)(w + L.x0),  (double*)(w + L.u),
@@ -796,7 +1043,8 @@ int lbm_create(const lbm_params* prm, void* d_workspace, size_t bytes, void* hip
                       (double*)(w + L.T),    (double*)(w + L.m),   (double*)(w + L.I),
                       (double*)(w + L.rad),  (int*)(w + L.b0),     (int*)(w + L.k),
                       (int*)(w + L.ent0),    (int*)(w + L.nbs),    (int*)(w + L.nis),
-                      (int*)(w + L.cand_n),  (int*)(w + L.cand),   (int*)(w + L.pairs)};
+                      (int*)(w + L.nin),     (int*)(w + L.cand_n), (int*)(w + L.jump),
+                      (int*)(w + L.cand),    (int*)(w + L.pairs)};
   c->E = DevEntries{(int*)(w + L.off), (int*)(w + L.pid)};
   c->np = 0;
   c->nent = 0;
@@ -807,7 +1055,8 @@ int lbm_create(const lbm_params* prm, void* d_workspace, size_t bytes, void* hip
   const size_t fbytes = (size_t)c->q * c->G.N * store_size(prm->storage);
   const int64_t nwords = (int64_t)(fbytes / 4);
   k_fill<uint32_t><<<blocks_for(nwords), 256, 0, c->stream>>>((uint32_t*)c->f[0], nwords, 0u);
-  k_fill<int><<<blocks_for(c->G.N), 256, 0, c->stream>>>(c->map, c->G.N, kEmpty);
+  k_fill<int><<<blocks_for(c->G.N), 256, 0, c->stream>>>(c->own, c->G.N, kEmpty);
+  k_fill<int><<<blocks_for(c->G.N), 256, 0, c->stream>>>(c->ball, c->G.N, kEmpty);
   k_fill<int><<<1, 256, 0, c->stream>>>(c->status, 16, 0);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
     delete c;
@@ -877,7 +1126,7 @@ int lbm_add_particles(lbm_ctx* c, int32_t n, const double* x, const double* u, c
   }
   // templates and particle records (host), then upload
   std::vector<double> hx(3 * n), hu(3 * n, 0.0), hom(3 * n, 0.0), hphi(3 * n), hfext(3 * n);
-  std::vector<int> hb0(3 * n), hk(3 * n, 0), hent0(n), hnbs(n), hnis(n), hoff, hpid;
+  std::vector<int> hb0(3 * n), hk(3 * n, 0), hent0(n), hnbs(n), hnis(n), hnin(n), hoff, hpid;
   for (int j = 0; j < n; j++) {
     const double r = radius[j];
     const double V = dim == 2 ? M_PI * r * r : 4.0 / 3.0 * M_PI * r * r * r;
@@ -889,15 +1138,19 @@ int lbm_add_particles(lbm_ctx* c, int32_t n, const double* x, const double* u, c
       hphi[3 * j + a] = hx[3 * j + a] - (double)hb0[3 * j + a];
       hfext[3 * j + a] = std::isinf(mass[j]) ? 0.0 : (mass[j] - c->prm.rho0 * V) * c->prm.gravity[a];
     }
-    int nb = 0, ni = 0;
+    int nb = 0, ni = 0, nn = 0;
     const size_t before = hoff.size();
-    build_template(c->q, r, &hphi[3 * j], hoff, &nb, &ni);
+    build_template(c->q, r, &hphi[3 * j], hoff, &nb, &ni, &nn);
     hent0[j] = (int)(c->nent + before);
     hnbs[j] = nb;
     hnis[j] = ni;
-    hpid.insert(hpid.end(), (size_t)(nb + ni), c->np + j);
+    hnin[j] = nn;
+    hpid.insert(hpid.end(), (size_t)(nb + ni + nn), c->np + j);
   }
   if (c->nent + (int64_t)hoff.size() > c->L.max_ent) return LBM_ECAPACITY;
+  // the pending IS substep of the particles already present goes into the state
+  const int mrc = DISPATCH(c, launch_materialize, c, 1);
+  if (mrc != LBM_OK) return mrc;
   const int p0 = c->np;
   int rc;
 #define UP(dst, src, cnt) \
@@ -916,6 +1169,7 @@ int lbm_add_particles(lbm_ctx* c, int32_t n, const double* x, const double* u, c
   UP(c->P.ent0 + p0, hent0.data(), (size_t)n);
   UP(c->P.nbs + p0, hnbs.data(), (size_t)n);
   UP(c->P.nis + p0, hnis.data(), (size_t)n);
+  UP(c->P.nin + p0, hnin.data(), (size_t)n);
   UP(c->E.off + c->nent, hoff.data(), hoff.size());
   UP(c->E.pid + c->nent, hpid.data(), hpid.size());
 #undef UP
@@ -924,8 +1178,13 @@ int lbm_add_particles(lbm_ctx* c, int32_t n, const double* x, const double* u, c
   HIP_TRY(hipMemcpyAsync(c->P.T + 3 * p0, zero.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
   // stamp the new entries into the current map (existing owners have lower ids)
   const int64_t e0 = c->nent, e1 = c->nent + (int64_t)hoff.size();
-  k_stamp<<<blocks_for(e1 - e0), 256, 0, c->stream>>>(c->map, c->P, c->E, c->G, (int)e0, (int)e1);
+  k_stamp<<<blocks_for(e1 - e0), 256, 0, c->stream>>>(c->own, c->ball, c->P, c->E, c->G, (int)e0, (int)e1);
   HIP_TRY(hipGetLastError());
+  c->nent = e1;
+  c->np += n;
+  // records of every ball site, with nothing pending (written into the state above)
+  const int prc = DISPATCH(c, launch_prepare, c, 0);
+  if (prc != LBM_OK) return prc;
   HIP_TRY(hipStreamSynchronize(c->stream));
   for (int j = 0; j < n; j++) {
     c->h_x0.insert(c->h_x0.end(), &hx[3 * j], &hx[3 * j] + 3);
@@ -935,11 +1194,10 @@ int lbm_add_particles(lbm_ctx* c, int32_t n, const double* x, const double* u, c
     c->h_fext.insert(c->h_fext.end(), &hfext[3 * j], &hfext[3 * j] + 3);
     c->h_nbs.push_back(hnbs[j]);
     c->h_nis.push_back(hnis[j]);
+    c->h_nin.push_back(hnin[j]);
   }
   c->h_off.insert(c->h_off.end(), hoff.begin(), hoff.end());
   c->h_pid.insert(c->h_pid.end(), hpid.begin(), hpid.end());
-  c->nent = e1;
-  c->np += n;
   // fluid body force: user value, plus the opposite of the particles' total
   // external force spread over every site in a zero-net-force box
   double tot[3] = {0, 0, 0};
@@ -976,6 +1234,8 @@ int lbm_forces(lbm_ctx* c, double* F, double* T, double* x, double* u, double* o
 int lbm_fields(lbm_ctx* c, double* rho, double* u, int32_t* owner) {
   if (!c) return LBM_EINVAL;
   if (rho || u) {
+    const int mrc = DISPATCH(c, launch_materialize, c, 1);
+    if (mrc != LBM_OK) return mrc;
     // the other population buffer is free between steps: stage moments there
     const size_t stage = (size_t)c->q * c->G.N * store_size(c->prm.storage);
     const int64_t chunk = (int64_t)(stage / (4 * sizeof(double)));
@@ -993,7 +1253,7 @@ int lbm_fields(lbm_ctx* c, double* rho, double* u, int32_t* owner) {
   }
   if (owner) {
     std::vector<int> m(c->G.N);
-    HIP_TRY(hipMemcpyAsync(m.data(), c->map, sizeof(int) * c->G.N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(m.data(), c->own, sizeof(int) * c->G.N, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     for (int64_t s = 0; s < c->G.N; s++) owner[s] = m[s] == kEmpty ? -1 : c->h_pid[m[s]];
   }
@@ -1003,7 +1263,7 @@ int lbm_fields(lbm_ctx* c, double* rho, double* u, int32_t* owner) {
 int lbm_site_kind(lbm_ctx* c, int8_t* kind) {
   if (!c || !kind) return LBM_EINVAL;
   std::vector<int> m(c->G.N);
-  HIP_TRY(hipMemcpyAsync(m.data(), c->map, sizeof(int) * c->G.N, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(m.data(), c->own, sizeof(int) * c->G.N, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   for (int64_t s = 0; s < c->G.N; s++) kind[s] = m[s] == kEmpty ? 0 : (int8_t)entry_kind(c->h_off[m[s]]);
   return check_status(c);
@@ -1025,7 +1285,9 @@ int lbm_particle_info(lbm_ctx* c, int32_t p, int32_t* nbs, int32_t* nis) {
 int lbm_get_distributions(lbm_ctx* c, double* f) {
   if (!c || !f) return LBM_EINVAL;
   void* stage = c->f[1 - c->cur];
-  int rc = DISPATCH(c, launch_shift, c, c->f[c->cur], stage, 1);
+  int rc = DISPATCH(c, launch_materialize, c, 1);
+  if (rc != LBM_OK) return rc;
+  rc = DISPATCH(c, launch_shift, c, c->f[c->cur], stage, 1);
   if (rc != LBM_OK) return rc;
   const int64_t n = (int64_t)c->q * c->G.N;
   if (c->prm.storage == LBM_FP64) {
@@ -1071,6 +1333,9 @@ int lbm_set_distributions(lbm_ctx* c, const double* f) {
   }
   int rc = DISPATCH(c, launch_shift, c, stage, c->f[c->cur], -1);
   if (rc != LBM_OK) return rc;
+  // the given populations are the complete post-propagation state
+  rc = DISPATCH(c, launch_materialize, c, 0);
+  if (rc != LBM_OK) return rc;
   HIP_TRY(hipStreamSynchronize(c->stream));
   return LBM_OK;
 }
@@ -1101,8 +1366,9 @@ int lbm_profile(lbm_ctx* c, double* sweep_ms, int64_t* sweeps) {
 int lbm_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
   if (!dst || !src || bytes % 16 || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16)) return LBM_EINVAL;
   const int64_t n = (int64_t)(bytes / 16);
-  const unsigned nb = (unsigned)std::min<int64_t>(blocks_for(n), 256 * 64);
-  k_copy16<<<nb, 256, 0, (hipStream_t)hip_stream>>>((const v4u*)src, (v4u*)dst, n);
+  if (n == 0) return LBM_OK;
+  if (blocks_for(n) > 0x7fffffff) return LBM_EINVAL;
+  k_copy16<<<blocks_for(n), 256, 0, (hipStream_t)hip_stream>>>((const v4u*)src, (v4u*)dst, n);
   HIP_TRY(hipGetLastError());
   return LBM_OK;
 }
