@@ -61,24 +61,35 @@ def main():
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--particles", type=int, default=-1,
+                    help="particles in the box (default: the workload's; fewer only to measure overheads)")
+    ap.add_argument("--workload", default="spheres-3d", choices=["spheres-3d", "disks-2d"],
+                    help="spheres-3d: D3Q19 256^3, 500 spheres (the headline); "
+                         "disks-2d: D2Q9 1024^2, 200 disks")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the slab decomposition across GPUs is a design, not code)", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     from paper_1105_2904_amd import lbm
     from paper_1105_2904_amd import workloads as wl
 
     torch.cuda.set_device(0)
-    cfg = wl.spheres_3d_config(storage=args.storage)
-    p = cfg["particles"]
+    cfg = wl.spheres_3d_config(storage=args.storage) if args.workload == "spheres-3d" else wl.disks_2d_config()
+    q = cfg["q"]
+    if args.particles < 0:
+        args.particles = len(cfg["particles"]["radius"])
+    p = {k: v[:args.particles] for k, v in cfg["particles"].items()}
     nx, ny, nz = cfg["box"]
     N = nx * ny * nz
-    sim = lbm.Simulation(19, nx, ny, nz, tau=cfg["tau"], gravity=cfg["gravity"], zero_net_force=True,
-                         storage=args.storage, max_particles=len(p["radius"]), max_radius=6.0)
-    sim.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
+    sim = lbm.Simulation(q, nx, ny, nz, tau=cfg["tau"], gravity=cfg["gravity"], zero_net_force=True,
+                         storage=args.storage, max_particles=max(len(p["radius"]), 1),
+                         max_radius=float(np.max(cfg["particles"]["radius"])))
+    if args.particles:
+        sim.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
     bps = lbm.lbm_bytes_per_site(sim.params)
     stream = sim.stream
 
@@ -98,7 +109,7 @@ def main():
     sweep_ms, sweeps = sim.profile()
     sim.set_profiling(False)
     F = sim.forces()[0]
-    assert F.shape == (500, 3)
+    assert F.shape == (args.particles, 3) and np.isfinite(F).all()
 
     ms_step = ms_total / args.steps
     mlups = N / (ms_step * 1e-3) / 1e6
@@ -118,17 +129,19 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.storage == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": cfg["name"], "lattice": "D3Q19", "box": [nx, ny, nz], "tau": cfg["tau"],
-                   "particles": 500, "radius": 6.0, "density_ratio": 1.2, "gravity": 1e-6,
+        "config": {"workload": cfg["name"], "lattice": "D3Q19" if q == 19 else "D2Q9", "box": [nx, ny, nz],
+                   "tau": cfg["tau"], "particles": args.particles,
+                   "radius": float(np.max(cfg["particles"]["radius"])),
+                   "density_ratio": 1.2 if q == 19 else 1.5, "gravity": float(-min(cfg["gravity"])),
                    "storage": args.storage, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None,
-                     "kernel": "k_sweep<19,%s>" % ("float" if args.storage == "fp32" else "double"),
+                     "kernel": "k_sweep<%d,%s>" % (q, "float" if args.storage == "fp32" else "double"),
                      "kernel_avg_ms": round(sweep_avg_ms, 4), "bytes_per_site": bps},
         "step_roofline_frac": round(bps * mlups * 1e6 / 1e9 / PEAK_HBM_GBPS, 4),
         "copy_ceiling_GBps": round(ceiling, 1),
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "spheres-3d":
         print("cpu baseline: %d oracle steps" % args.cpu_steps, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
     print(json.dumps(out), flush=True)

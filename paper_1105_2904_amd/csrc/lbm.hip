@@ -16,8 +16,9 @@
 //              weight, hard-core collisions in lexicographic pair order,
 //              translation and integer shift.               eq. 10-11, 13, 16-19
 //   stamp      rebuild the maps at the new shifts: the owner map (lowest BS/IS
-//              entry index, hence lowest particle id) and the ball map (lowest
-//              entry of any kind: one representative entry per ball site).
+//              entry index, hence lowest particle id; stored as 2e + [IS]) and
+//              the ball map (lowest entry of any kind: one representative
+//              entry per ball site).
 //                                                                    eq. 14-15
 //   prepare    one thread per ball site: the record the next sweep needs there
 //              -- which incoming populations leave a pending IS site, their
@@ -47,6 +48,7 @@
 namespace {
 
 constexpr int kEmpty = 0x7fffffff;  // map value of a site no entry claims
+constexpr int64_t kMaxEntries = (int64_t)1 << 29;  // owner map stores 2e + 1 < kEmpty
 constexpr int kCandMax = 64;        // close neighbours listed per particle
 constexpr double kMargin = 1.0;     // candidate search margin (lattice units)
 constexpr int kSweepBlock = 256;
@@ -81,7 +83,7 @@ struct Geo {
 struct DevParticles {
   double *x, *x0, *u, *om, *phi, *fext, *dP, *dL, *F, *T;  // [n][3]
   double *m, *I, *rad;                                     // [n]
-  int *b0, *k;                                             // [n][3]
+  int *b0, *k, *org;                                       // [n][3]; org = b0 + k wrapped into the box
   int *ent0, *nbs, *nis, *nin, *cand_n, *jump;             // [n]
   int *cand;                                               // [n][kCandMax]
   int *pairs;                                              // [n*kCandMax][2]
@@ -105,11 +107,21 @@ __device__ __forceinline__ int wrap(int v, int n) {
   return r < 0 ? r + n : r;
 }
 
-// Site of a template offset at the particle's current shift b0 + k.
+// v in (-n, 2n) back into [0, n)
+__device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Coordinates of a template offset at the particle's current shift b0 + k
+// (offsets are shorter than the box, so one wrap suffices).
+__device__ __forceinline__ void entry_xyz(const DevParticles& P, const Geo& G, int p, int pk, int& x, int& y,
+                                          int& z) {
+  x = wrap1(P.org[3 * p] + off_x(pk), G.nx);
+  y = wrap1(P.org[3 * p + 1] + off_y(pk), G.ny);
+  z = wrap1(P.org[3 * p + 2] + off_z(pk), G.nz);
+}
+
 __device__ __forceinline__ int entry_site(const DevParticles& P, const Geo& G, int p, int pk) {
-  const int x = wrap(P.b0[3 * p] + P.k[3 * p] + off_x(pk), G.nx);
-  const int y = wrap(P.b0[3 * p + 1] + P.k[3 * p + 1] + off_y(pk), G.ny);
-  const int z = wrap(P.b0[3 * p + 2] + P.k[3 * p + 2] + off_z(pk), G.nz);
+  int x, y, z;
+  entry_xyz(P, G, p, pk, x, y, z);
   return x + G.nx * (y + G.ny * z);
 }
 
@@ -118,15 +130,17 @@ __device__ __forceinline__ int entry_site(const DevParticles& P, const Geo& G, i
 // at s (kEmpty outside every ball); the record of that representative entry
 // b describes site s for the next sweep:
 //   hdr[b] = {mask, bs}: bit i of mask set if population i arrives from a
-//            pending IS site, its value being sub[b*q + i]; bs = the BS entry
-//            that owns s (-1 if none), whose rigid-body velocity is vel[b].
+//            pending IS site, its value being sub[i*stride + b]; bs = the BS
+//            entry that owns s (-1 if none), whose rigid-body velocity is
+//            vel[b].
 // ---------------------------------------------------------------------------
 template <typename T>
 struct SiteArgs {
   const int* ball;
   const int2* hdr;
   const typename Store<T>::C* vel;  // [entry][4]
-  const T* sub;                     // [entry][q]
+  const T* sub;                     // [q][stride]
+  int64_t stride;                   // entries per direction plane of sub
   double* slot;                     // [entry][4]: post-collision drho, j of an owned BS site
   typename Store<T>::C* drho;       // density deviation of every site (this sweep)
 };
@@ -182,6 +196,10 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, 
   const int zm = z == 0 ? a.nz - 1 : z - 1, zp = z == a.nz - 1 ? 0 : z + 1;
   const int s = x + a.nx * (y + a.ny * z);
 
+  // ball sites first: their record is needed before the collision
+  const int b = PART ? sa.ball[s] : kEmpty;
+  int2 h = make_int2(0, -1);
+  if (PART && b != kEmpty) h = sa.hdr[b];
   C g[Q];
 #pragma unroll
   for (int i = 0; i < Q; i++) {
@@ -191,20 +209,14 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, 
     const int sz = L::cz(i) > 0 ? zm : (L::cz(i) < 0 ? zp : z);
     g[i] = Store<T>::ld(A + (size_t)i * a.N + (sx + a.nx * (sy + a.ny * sz)));
   }
-  const int b = PART ? sa.ball[s] : kEmpty;
-  int bs = -1;
-  if (PART && b != kEmpty) {
-    // a ball site: populations arriving from a pending internal site left it
-    // as the imposed equilibrium
-    const int2 h = sa.hdr[b];
-    bs = h.y;
+  const int bs = h.y;
+  if (PART && h.x) {
+    // populations arriving from a pending internal site left it as the
+    // imposed equilibrium
     const unsigned mask = (unsigned)h.x;
-    if (mask) {
-      const T* sub = sa.sub + (size_t)b * Q;
 #pragma unroll
-      for (int i = 0; i < Q; i++)
-        if (mask & (1u << i)) g[i] = Store<T>::ld(sub + i);
-    }
+    for (int i = 0; i < Q; i++)
+      if (mask & (1u << i)) g[i] = Store<T>::ld(sa.sub + (size_t)i * sa.stride + b);
   }
   C drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
@@ -292,34 +304,50 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
   const double wx = P.om[3 * p], wy = P.om[3 * p + 1], wz = P.om[3 * p + 2];
 
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int t = tid; t < nbs; t += kBoundaryBlock) {
-    const int e = e0 + t;
-    const int pk = E.off[e];
-    const int s = entry_site(P, G, p, pk);
-    ball[s] = kEmpty;
-    if (own[s] != e) continue;  // owned by a lower id: not imposed
-    own[s] = kEmpty;            // only the owner clears its site
-    // dp = rho_B (u_B' - u_B), dl = r x dp with the post-collision moments
-    const double rhoB = rho0 + slot[4 * (size_t)e];
-    const double ubx = slot[4 * (size_t)e + 1] / rhoB, uby = slot[4 * (size_t)e + 2] / rhoB,
-                 ubz = slot[4 * (size_t)e + 3] / rhoB;
-    const double rx = (double)off_x(pk) - phx, ry = (double)off_y(pk) - phy, rz = (double)off_z(pk) - phz;
-    const double vx = upx + (wy * rz - wz * ry);
-    const double vy = upy + (wz * rx - wx * rz);
-    const double vz = upz + (wx * ry - wy * rx);
-    const double dpx = rhoB * (vx - ubx), dpy = rhoB * (vy - uby), dpz = rhoB * (vz - ubz);
-    acc[0] += dpx;
-    acc[1] += dpy;
-    acc[2] += dpz;
-    acc[3] += ry * dpz - rz * dpy;
-    acc[4] += rz * dpx - rx * dpz;
-    acc[5] += rx * dpy - ry * dpx;
-  }
-  for (int t = tid; t < nis + nin; t += kBoundaryBlock) {
-    const int e = e0 + nbs + t;
-    const int s = entry_site(P, G, p, E.off[e]);
-    ball[s] = kEmpty;
-    if (t < nis && own[s] == e) own[s] = kEmpty;
+  const int ne = nbs + nis + nin;
+  constexpr int kEnt = 4;  // entries per thread whose loads are issued together
+  for (int tb = 0; tb < ne; tb += kBoundaryBlock * kEnt) {
+    int pkv[kEnt], sv[kEnt], ov[kEnt];
+    double4 mv[kEnt];
+#pragma unroll
+    for (int j = 0; j < kEnt; j++) {
+      const int t = tb + j * kBoundaryBlock + tid;
+      if (t < ne) {
+        const int e = e0 + t;
+        pkv[j] = E.off[e];
+        sv[j] = entry_site(P, G, p, pkv[j]);
+        ov[j] = own[sv[j]];
+        // the slot is only meaningful for an owned BS site; read it anyway
+        mv[j] = entry_kind(pkv[j]) == 1 ? *(const double4*)(slot + 4 * (size_t)e) : make_double4(0, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kEnt; j++) {
+      const int t = tb + j * kBoundaryBlock + tid;
+      if (t >= ne) continue;
+      const int e = e0 + t;
+      const int pk = pkv[j];
+      const int kind = entry_kind(pk);
+      const int s = sv[j];
+      ball[s] = kEmpty;
+      if (kind == 2 && ov[j] == 2 * e + 1) own[s] = kEmpty;
+      if (kind != 1 || ov[j] != 2 * e) continue;  // BS sites owned by this entry only
+      own[s] = kEmpty;                             // only the owner clears its site
+      // dp = rho_B (u_B' - u_B), dl = r x dp with the post-collision moments
+      const double rhoB = rho0 + mv[j].x;
+      const double ubx = mv[j].y / rhoB, uby = mv[j].z / rhoB, ubz = mv[j].w / rhoB;
+      const double rx = (double)off_x(pk) - phx, ry = (double)off_y(pk) - phy, rz = (double)off_z(pk) - phz;
+      const double vx = upx + (wy * rz - wz * ry);
+      const double vy = upy + (wz * rx - wx * rz);
+      const double vz = upz + (wx * ry - wy * rx);
+      const double dpx = rhoB * (vx - ubx), dpy = rhoB * (vy - uby), dpz = rhoB * (vz - ubz);
+      acc[0] += dpx;
+      acc[1] += dpy;
+      acc[2] += dpz;
+      acc[3] += ry * dpz - rz * dpy;
+      acc[4] += rz * dpx - rx * dpz;
+      acc[5] += rx * dpy - ry * dpx;
+    }
   }
 #pragma unroll
   for (int c = 0; c < 6; c++) {
@@ -408,6 +436,7 @@ __global__ __launch_bounds__(kParticleBlock) void k_particles(DevParticles P, in
   for (int b = 0; b < np; b += kParticleBlock) {
     const int p = b + tid;
     const int c = p < np ? P.cand_n[p] : 0;
+    if (!__syncthreads_or(c)) continue;  // no close pair in this chunk
     s_scan[tid] = c;
     __syncthreads();
     for (int off = 1; off < kParticleBlock; off <<= 1) {
@@ -477,6 +506,7 @@ __global__ __launch_bounds__(kParticleBlock) void k_particles(DevParticles P, in
     if (2.0 * vseen >= kMargin) atomicOr(status, kStatusCollision);
   }
   __syncthreads();
+  const int L[3] = {G.nx, G.ny, G.nz};
   for (int p = tid; p < np; p += kParticleBlock) {
     int moved = 0;
     for (int a = 0; a < dim; a++) {
@@ -485,6 +515,7 @@ __global__ __launch_bounds__(kParticleBlock) void k_particles(DevParticles P, in
       const int k = (int)floor(x - P.x0[3 * p + a] + 0.5);
       moved += k != P.k[3 * p + a];
       P.k[3 * p + a] = k;
+      P.org[3 * p + a] = wrap(P.b0[3 * p + a] + k, L[a]);
     }
     // a shift along all three axes at once (not a D3Q19 link) can take an IS
     // site outside the ball the sweep kept densities for
@@ -495,7 +526,9 @@ __global__ __launch_bounds__(kParticleBlock) void k_particles(DevParticles P, in
 // ---------------------------------------------------------------------------
 // K4: stamp every template entry at its particle's shift.  BS/IS entries
 // claim the owner map (lowest index, hence lowest particle id, wins); every
-// entry claims the ball map, whose lowest entry represents the site.
+// entry writes the ball map, and whichever entry lands there last represents
+// the site (a record describes the site, not the entry, so any choice gives
+// the same results).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_stamp(int* __restrict__ own, int* __restrict__ ball, DevParticles P,
                                                 DevEntries E, Geo G, int e_begin, int e_end) {
@@ -503,80 +536,66 @@ __global__ __launch_bounds__(256) void k_stamp(int* __restrict__ own, int* __res
   if (e >= e_end) return;
   const int pk = E.off[e];
   const int s = entry_site(P, G, E.pid[e], pk);
-  atomicMin(&ball[s], e);
-  if (entry_kind(pk) != 3) atomicMin(&own[s], e);
+  ball[s] = e;
+  const int kind = entry_kind(pk);
+  if (kind != 3) atomicMin(&own[s], 2 * e + (kind == 2));
 }
 
 // ---------------------------------------------------------------------------
-// K5: IS substep at the new positions (eq. 12), computed once per owned IS
-// site: the q populations f^eq(rho_I, u_p' + omega_p' x r), rho_I being the
-// site's post-collision density (kept by this step's sweep for ball sites;
-// summed from the populations after a diagonal jump).
-// ---------------------------------------------------------------------------
-template <int Q, typename T>
-__global__ __launch_bounds__(256) void k_isval(const int* __restrict__ own, T* __restrict__ isval,
-                                                const typename Store<T>::C* __restrict__ drho,
-                                                const T* __restrict__ B, DevParticles P, DevEntries E, Geo G,
-                                                int nent, double rho0) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= nent) return;
-  const int pk = E.off[e];
-  if (entry_kind(pk) != 2) return;
-  const int p = E.pid[e];
-  const int s = entry_site(P, G, p, pk);
-  if (own[s] != e) return;
-  double dr = 0;
-  if (P.jump[p]) {
-#pragma unroll
-    for (int i = 0; i < Q; i++) dr += (double)B[(size_t)i * G.N + s];
-  } else {
-    dr = (double)drho[s];
-  }
-#pragma unroll
-  for (int i = 0; i < Q; i++) isval[(size_t)e * Q + i] = (T)rigid_feq<Q>(i, e, dr, P, E, rho0);
-}
-
-// ---------------------------------------------------------------------------
-// K6: record of every ball site for the next sweep.  With pending = 1,
-// population i of site s arrives from s - c_i, and if that site is an owned
-// IS site it arrives as the value K5 prepared.  For an owned BS site the
+// K5: record of every ball site for the next sweep.  With pending = 1 the IS
+// substep at the new positions (eq. 12) is prepared: population i of site s
+// arrives from s - c_i, and if that site is an owned IS site it arrives as
+// f^eq_i(rho_I, u_p' + omega_p' x r), with rho_I the density this step's
+// sweep found there (ball sites), or the sum of its populations when its
+// particle jumped along all three axes at once (the site may then lie outside
+// the ball the sweep kept densities for).  For an owned BS site the
 // rigid-body velocity of the next BS substep is stored (eq. 5).
 // ---------------------------------------------------------------------------
 template <int Q, typename T>
 __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own, const int* __restrict__ ball,
                                                   int2* __restrict__ hdr, typename Store<T>::C* __restrict__ vel,
-                                                  T* __restrict__ sub, const T* __restrict__ isval,
-                                                  DevParticles P, DevEntries E, Geo G, int nent, int pending) {
+                                                  T* __restrict__ sub, const typename Store<T>::C* __restrict__ drho,
+                                                  const T* __restrict__ B, DevParticles P, DevEntries E, Geo G,
+                                                  int nent, int64_t stride, double rho0, int pending) {
   using L = Lattice<Q>;
   using C = typename Store<T>::C;
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= nent) return;
-  const int p = E.pid[e];
-  const int pk = E.off[e];
-  const int x = wrap(P.b0[3 * p] + P.k[3 * p] + off_x(pk), G.nx);
-  const int y = wrap(P.b0[3 * p + 1] + P.k[3 * p + 1] + off_y(pk), G.ny);
-  const int z = wrap(P.b0[3 * p + 2] + P.k[3 * p + 2] + off_z(pk), G.nz);
+  int x, y, z;
+  entry_xyz(P, G, E.pid[e], E.off[e], x, y, z);
   const int s = x + G.nx * (y + G.ny * z);
   if (ball[s] != e) return;  // another entry represents this site
   unsigned mask = 0;
   if (pending) {
-    int o[Q];
+    const int xm = x == 0 ? G.nx - 1 : x - 1, xp = x == G.nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? G.ny - 1 : y - 1, yp = y == G.ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? G.nz - 1 : z - 1, zp = z == G.nz - 1 ? 0 : z + 1;
 #pragma unroll
-    for (int i = 0; i < Q; i++)
-      o[i] = own[wrap(x - L::cx(i), G.nx) + G.nx * (wrap(y - L::cy(i), G.ny) + G.ny * wrap(z - L::cz(i), G.nz))];
-#pragma unroll
-    for (int i = 0; i < Q; i++)
-      if (o[i] != kEmpty && entry_kind(E.off[o[i]]) == 2) {
-        mask |= 1u << i;
-        sub[(size_t)e * Q + i] = isval[(size_t)o[i] * Q + i];
+    for (int i = 0; i < Q; i++) {
+      const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
+      const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
+      const int sz = L::cz(i) > 0 ? zm : (L::cz(i) < 0 ? zp : z);
+      const int src = sx + G.nx * (sy + G.ny * sz);
+      const int o = own[src];
+      if (o == kEmpty || !(o & 1)) continue;  // not an owned IS site
+      const int ie = o >> 1;
+      double dr;
+      if (P.jump[E.pid[ie]]) {
+        dr = 0;
+        for (int j = 0; j < Q; j++) dr += (double)B[(size_t)j * G.N + src];
+      } else {
+        dr = (double)drho[src];
       }
+      mask |= 1u << i;
+      sub[(size_t)i * stride + e] = (T)rigid_feq<Q>(i, ie, dr, P, E, rho0);
+    }
   }
   int bs = -1;
   const int o = own[s];
-  if (o != kEmpty && entry_kind(E.off[o]) == 1) {
-    bs = o;
-    const int q = E.pid[o];
-    const int ok = E.off[o];
+  if (o != kEmpty && !(o & 1)) {  // an owned BS site
+    bs = o >> 1;
+    const int q = E.pid[bs];
+    const int ok = E.off[bs];
     const double rx = (double)off_x(ok) - P.phi[3 * q], ry = (double)off_y(ok) - P.phi[3 * q + 1],
                  rz = (double)off_z(ok) - P.phi[3 * q + 2];
     const double wx = P.om[3 * q], wy = P.om[3 * q + 1], wz = P.om[3 * q + 2];
@@ -587,21 +606,169 @@ __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own, co
   hdr[e] = make_int2((int)mask, bs);
 }
 
+// The same records built per particle (one workgroup each) from a window of
+// the owner map and densities around the ball, staged in LDS: row-coalesced
+// loads instead of scattered neighbour lookups.  The window has half-width
+// hw = floor(r + 1/2) + 1 (ball offsets plus one link).  Sites claimed by
+// another particle fall back to global lookups.
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ own, const int* __restrict__ ball,
+                                                        int2* __restrict__ hdr, typename Store<T>::C* __restrict__ vel,
+                                                        T* __restrict__ sub, const typename Store<T>::C* __restrict__ drho,
+                                                        const T* __restrict__ B, DevParticles P, DevEntries E, Geo G,
+                                                        int64_t stride, double rho0, int pending, int dim) {
+  using L = Lattice<Q>;
+  using C = typename Store<T>::C;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int hw = (int)floor(P.rad[p] + 0.5) + 1;
+  const int W = 2 * hw + 1, Wz = dim == 3 ? W : 1, hz = dim == 3 ? hw : 0;
+  const int nW = W * W * Wz;
+  int* s_own = (int*)smem;
+  C* s_drho = (C*)(smem + ((sizeof(int) * nW + 15) / 16) * 16);
+  const int ox0 = P.org[3 * p], oy0 = P.org[3 * p + 1], oz0 = P.org[3 * p + 2];
+  // window loads issued in batches of kBatch per thread so that their
+  // latencies overlap
+  constexpr int kBatch = 8;
+  for (int base = 0; base < nW; base += 256 * kBatch) {
+    int vo[kBatch];
+    C vd[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; j++) {
+      const int idx = base + j * 256 + tid;
+      if (idx < nW) {
+        const int wx = idx % W, wy = (idx / W) % W, wz = idx / (W * W);
+        const int x = wrap1(ox0 + wx - hw, G.nx), y = wrap1(oy0 + wy - hw, G.ny), z = wrap1(oz0 + wz - hz, G.nz);
+        const int site = x + G.nx * (y + G.ny * z);
+        vo[j] = own[site];
+        vd[j] = pending ? drho[site] : C(0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kBatch; j++) {
+      const int idx = base + j * 256 + tid;
+      if (idx < nW) {
+        s_own[idx] = vo[j];
+        s_drho[idx] = vd[j];
+      }
+    }
+  }
+  __syncthreads();
+  const double phx = P.phi[3 * p], phy = P.phi[3 * p + 1], phz = P.phi[3 * p + 2];
+  const double upx = P.u[3 * p], upy = P.u[3 * p + 1], upz = P.u[3 * p + 2];
+  const double wx = P.om[3 * p], wy = P.om[3 * p + 1], wz = P.om[3 * p + 2];
+  const int e0 = P.ent0[p], ne = P.nbs[p] + P.nis[p] + P.nin[p];
+  const bool jump = P.jump[p] != 0;
+  constexpr int kEnt = 4;
+  for (int tb = 0; tb < ne; tb += 256 * kEnt) {
+  int rep[kEnt], pkv[kEnt];
+#pragma unroll
+  for (int j = 0; j < kEnt; j++) {
+    const int t = tb + j * 256 + tid;
+    rep[j] = -1;
+    if (t < ne) {
+      pkv[j] = E.off[e0 + t];
+      const int x = wrap1(ox0 + off_x(pkv[j]), G.nx), y = wrap1(oy0 + off_y(pkv[j]), G.ny),
+                z = wrap1(oz0 + off_z(pkv[j]), G.nz);
+      rep[j] = ball[x + G.nx * (y + G.ny * z)];
+    }
+  }
+#pragma unroll 1
+  for (int j = 0; j < kEnt; j++) {
+    const int t = tb + j * 256 + tid;
+    const int e = e0 + t;
+    if (t >= ne || rep[j] != e) continue;  // another entry represents this site
+    const int pk = pkv[j];
+    const int ox = off_x(pk), oy = off_y(pk), oz = off_z(pk);
+    const int x = wrap1(ox0 + ox, G.nx), y = wrap1(oy0 + oy, G.ny), z = wrap1(oz0 + oz, G.nz);
+    const int w = (ox + hw) + W * ((oy + hw) + W * (oz + hz));
+    unsigned mask = 0;
+    if (pending) {
+#pragma unroll
+      for (int i = 0; i < Q; i++) {
+        const int wn = w - (L::cx(i) + W * (L::cy(i) + W * L::cz(i)));  // site s - c_i
+        const int o = s_own[wn];
+        if (o == kEmpty || !(o & 1)) continue;  // not an owned IS site
+        const int ie = o >> 1;
+        double val;
+        if (ie >= e0 && ie < e0 + ne) {
+          // an IS site of this particle: lever arm (o - c_i) - phi
+          double dr;
+          if (jump) {
+            const int src = wrap1(x - L::cx(i), G.nx) + G.nx * (wrap1(y - L::cy(i), G.ny) + G.ny * wrap1(z - L::cz(i), G.nz));
+            dr = 0;
+            for (int j = 0; j < Q; j++) dr += (double)B[(size_t)j * G.N + src];
+          } else {
+            dr = (double)s_drho[wn];
+          }
+          const double rx = (double)(ox - L::cx(i)) - phx, ry = (double)(oy - L::cy(i)) - phy,
+                       rz = (double)(oz - L::cz(i)) - phz;
+          const double vx = upx + (wy * rz - wz * ry);
+          const double vy = upy + (wz * rx - wx * rz);
+          const double vz = upz + (wx * ry - wy * rx);
+          const double rho = rho0 + dr;
+          const double usq = 1.5 * (vx * vx + vy * vy + vz * vz);
+          const double cu = L::cx(i) * vx + L::cy(i) * vy + L::cz(i) * vz;
+          val = L::w(i) * (dr + rho * (3.0 * cu + 4.5 * cu * cu - usq));
+        } else {
+          // an IS site of another particle (balls overlap)
+          const int src = wrap1(x - L::cx(i), G.nx) + G.nx * (wrap1(y - L::cy(i), G.ny) + G.ny * wrap1(z - L::cz(i), G.nz));
+          double dr;
+          if (P.jump[E.pid[ie]]) {
+            dr = 0;
+            for (int j = 0; j < Q; j++) dr += (double)B[(size_t)j * G.N + src];
+          } else {
+            dr = (double)drho[src];
+          }
+          val = rigid_feq<Q>(i, ie, dr, P, E, rho0);
+        }
+        mask |= 1u << i;
+        sub[(size_t)i * stride + e] = (T)val;
+      }
+    }
+    int bs = -1;
+    const int o = s_own[w];
+    if (o != kEmpty && !(o & 1)) {  // an owned BS site
+      bs = o >> 1;
+      double vx, vy, vz;
+      if (bs == e) {
+        const double rx = (double)ox - phx, ry = (double)oy - phy, rz = (double)oz - phz;
+        vx = upx + (wy * rz - wz * ry);
+        vy = upy + (wz * rx - wx * rz);
+        vz = upz + (wx * ry - wy * rx);
+      } else {
+        const int q = E.pid[bs];
+        const int ok = E.off[bs];
+        const double rx = (double)off_x(ok) - P.phi[3 * q], ry = (double)off_y(ok) - P.phi[3 * q + 1],
+                     rz = (double)off_z(ok) - P.phi[3 * q + 2];
+        const double ax = P.om[3 * q], ay = P.om[3 * q + 1], az = P.om[3 * q + 2];
+        vx = P.u[3 * q] + (ay * rz - az * ry);
+        vy = P.u[3 * q + 1] + (az * rx - ax * rz);
+        vz = P.u[3 * q + 2] + (ax * ry - ay * rx);
+      }
+      vel[4 * (size_t)e] = (C)vx;
+      vel[4 * (size_t)e + 1] = (C)vy;
+      vel[4 * (size_t)e + 2] = (C)vz;
+    }
+    hdr[e] = make_int2((int)mask, bs);
+  }
+  }
+}
+
 // Read-outs and overwrites: retire the pending IS substep.  write = 1 puts the
 // prepared populations into the state in place (exactly what the next sweep
 // would have pulled); write = 0 drops them (the state was replaced).
 template <int Q, typename T>
 __global__ __launch_bounds__(256) void k_materialize(T* __restrict__ S, const int* __restrict__ ball,
                                                       int2* __restrict__ hdr, const T* __restrict__ sub,
-                                                      DevParticles P, DevEntries E, Geo G, int nent, int write) {
+                                                      DevParticles P, DevEntries E, Geo G, int nent, int64_t stride,
+                                                      int write) {
   using L = Lattice<Q>;
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= nent) return;
-  const int p = E.pid[e];
-  const int pk = E.off[e];
-  const int x = wrap(P.b0[3 * p] + P.k[3 * p] + off_x(pk), G.nx);
-  const int y = wrap(P.b0[3 * p + 1] + P.k[3 * p + 1] + off_y(pk), G.ny);
-  const int z = wrap(P.b0[3 * p + 2] + P.k[3 * p + 2] + off_z(pk), G.nz);
+  int x, y, z;
+  entry_xyz(P, G, E.pid[e], E.off[e], x, y, z);
   const int s = x + G.nx * (y + G.ny * z);
   if (ball[s] != e) return;
   int2 h = hdr[e];
@@ -611,8 +778,8 @@ __global__ __launch_bounds__(256) void k_materialize(T* __restrict__ S, const in
 #pragma unroll
     for (int i = 0; i < Q; i++)
       if (h.x & (1 << i)) {
-        const int src = wrap(x - L::cx(i), G.nx) + G.nx * (wrap(y - L::cy(i), G.ny) + G.ny * wrap(z - L::cz(i), G.nz));
-        S[(size_t)i * G.N + src] = sub[(size_t)e * Q + i];
+        const int src = wrap1(x - L::cx(i), G.nx) + G.nx * (wrap1(y - L::cy(i), G.ny) + G.ny * wrap1(z - L::cz(i), G.nz));
+        S[(size_t)i * G.N + src] = sub[(size_t)i * stride + e];
       }
   }
   h.x = 0;
@@ -669,10 +836,10 @@ __global__ void k_fill(V* __restrict__ p, int64_t n, V v) {
 
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
-// one 16-byte vector per thread, streaming store
+// one 16-byte vector per thread, streaming load and store
 __global__ __launch_bounds__(256) void k_copy16(const v4u* __restrict__ src, v4u* __restrict__ dst, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) __builtin_nontemporal_store(src[i], dst + i);
+  if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 inline unsigned blocks_for(int64_t n, int per = 256) { return (unsigned)((n + per - 1) / per); }
@@ -682,8 +849,8 @@ inline unsigned blocks_for(int64_t n, int per = 256) { return (unsigned)((n + pe
 // ---------------------------------------------------------------------------
 struct Layout {
   size_t f[2], drho, own, ball, status;
-  size_t x, x0, u, om, phi, fext, dP, dL, F, T, m, I, rad, b0, k, ent0, nbs, nis, nin, jump, cand_n, cand, pairs;
-  size_t off, pid, slot, hdr, vel, sub, isval;
+  size_t x, x0, u, om, phi, fext, dP, dL, F, T, m, I, rad, b0, k, org, ent0, nbs, nis, nin, jump, cand_n, cand, pairs;
+  size_t off, pid, slot, hdr, vel, sub;
   int64_t max_ent;
   size_t total;
 };
@@ -718,7 +885,7 @@ Layout make_layout(const lbm_params& p) {
   L.x = take(v3); L.x0 = take(v3); L.u = take(v3); L.om = take(v3); L.phi = take(v3);
   L.fext = take(v3); L.dP = take(v3); L.dL = take(v3); L.F = take(v3); L.T = take(v3);
   L.m = take(v1); L.I = take(v1); L.rad = take(v1);
-  L.b0 = take(sizeof(int) * 3 * np); L.k = take(sizeof(int) * 3 * np);
+  L.b0 = take(sizeof(int) * 3 * np); L.k = take(sizeof(int) * 3 * np); L.org = take(sizeof(int) * 3 * np);
   L.ent0 = take(sizeof(int) * np); L.nbs = take(sizeof(int) * np); L.nis = take(sizeof(int) * np);
   L.nin = take(sizeof(int) * np);
   L.jump = take(sizeof(int) * np);
@@ -731,7 +898,6 @@ Layout make_layout(const lbm_params& p) {
   L.hdr = take(sizeof(int) * 2 * L.max_ent);
   L.vel = take((p.storage == LBM_FP64 ? 8 : 4) * 4 * L.max_ent);
   L.sub = take((size_t)p.lattice * store_size(p.storage) * L.max_ent);
-  L.isval = take((size_t)p.lattice * store_size(p.storage) * L.max_ent);
   L.total = cur;
   return L;
 }
@@ -748,6 +914,9 @@ int check_params(const lbm_params* p) {
   if (!(p->tau > 0.5) || !(p->rho0 > 0)) return LBM_EINVAL;
   if (p->max_particles < 0) return LBM_EINVAL;
   if (!(p->max_radius > 0) || p->max_radius > 120) return LBM_EINVAL;
+  const int dim = p->lattice == LBM_D2Q9 ? 2 : 3;
+  if (std::max<int64_t>(p->max_particles, 1) * entries_per_particle(dim, p->max_radius) > kMaxEntries)
+    return LBM_ECAPACITY;
   if (p->storage == LBM_FP16 || p->storage == LBM_BF16) return LBM_EUNSUPPORTED;
   if (p->storage != LBM_FP64 && p->storage != LBM_FP32) return LBM_EINVAL;
   return LBM_OK;
@@ -772,7 +941,6 @@ struct lbm_ctx {
   int2* hdr;
   void* vel;
   void* sub;
-  void* isval;
   int* own;   // owner map: lowest BS/IS entry per site
   int* ball;  // ball map: lowest entry of any kind per site
   int* status;
@@ -783,6 +951,7 @@ struct lbm_ctx {
   std::vector<double> h_x0, h_rad, h_m, h_I, h_fext;
   std::vector<int> h_off, h_pid, h_nbs, h_nis, h_nin;
   double fb[3];  // fluid body force density
+  size_t lds_window;  // LDS bytes of the per-particle record window (0: not used)
   bool prof;
   std::vector<hipEvent_t> ev;
   size_t ev_used;
@@ -802,25 +971,29 @@ SiteArgs<T> site_args(lbm_ctx* c) {
   sa.hdr = c->hdr;
   sa.vel = (const typename Store<T>::C*)c->vel;
   sa.sub = (const T*)c->sub;
+  sa.stride = c->L.max_ent;
   sa.slot = c->slot;
   sa.drho = (typename Store<T>::C*)c->drho;
   return sa;
 }
 
 // Records of every ball site for the next sweep; with pending = 1 the IS
-// substep of the step that just ran is prepared first.
+// substep of the step that just ran is prepared.  Per-particle LDS windows
+// when they fit, one thread per entry otherwise.
 template <int Q, typename T>
 int launch_prepare(lbm_ctx* c, int pending) {
-  if (c->nent > 0) {
-    if (pending)
-      k_isval<Q, T><<<blocks_for(c->nent), 256, 0, c->stream>>>(
-          c->own, (T*)c->isval, (const typename Store<T>::C*)c->drho, (const T*)c->f[c->cur], c->P, c->E, c->G,
-          (int)c->nent, c->prm.rho0);
+  if (c->nent == 0) return LBM_OK;
+  using C = typename Store<T>::C;
+  if (c->lds_window > 0) {
+    k_prepare_local<Q, T><<<c->np, 256, c->lds_window, c->stream>>>(
+        c->own, c->ball, c->hdr, (C*)c->vel, (T*)c->sub, (const C*)c->drho, (const T*)c->f[c->cur], c->P, c->E, c->G,
+        c->L.max_ent, c->prm.rho0, pending, c->dim);
+  } else {
     k_prepare<Q, T><<<blocks_for(c->nent), 256, 0, c->stream>>>(
-        c->own, c->ball, c->hdr, (typename Store<T>::C*)c->vel, (T*)c->sub, (const T*)c->isval, c->P, c->E,
-        c->G, (int)c->nent, pending);
-    HIP_TRY(hipGetLastError());
+        c->own, c->ball, c->hdr, (C*)c->vel, (T*)c->sub, (const C*)c->drho, (const T*)c->f[c->cur], c->P, c->E, c->G,
+        (int)c->nent, c->L.max_ent, c->prm.rho0, pending);
   }
+  HIP_TRY(hipGetLastError());
   return LBM_OK;
 }
 
@@ -881,7 +1054,7 @@ template <int Q, typename T>
 int launch_materialize(lbm_ctx* c, int write) {
   if (c->nent > 0) {
     k_materialize<Q, T><<<blocks_for(c->nent), 256, 0, c->stream>>>(
-        (T*)c->f[c->cur], c->ball, c->hdr, (const T*)c->sub, c->P, c->E, c->G, (int)c->nent, write);
+        (T*)c->f[c->cur], c->ball, c->hdr, (const T*)c->sub, c->P, c->E, c->G, (int)c->nent, c->L.max_ent, write);
     HIP_TRY(hipGetLastError());
   }
   return LBM_OK;
@@ -913,7 +1086,8 @@ double lattice_w(int q, int i) { return q == 9 ? Lattice<9>::w(i) : Lattice<19>:
 // Template of one particle (section 2.2): digitised ball |o - phi| <= r, BS
 // = ball sites linked (any lattice velocity) to a site outside the ball, IS =
 // other ball sites linked to a BS site, interior = the remaining ball sites.
-// Entries: BS, then IS, then interior, each in z, y, x order.
+// Entries follow the ball in z, y, x order so that neighbouring threads of
+// the sparse kernels touch neighbouring sites.
 void build_template(int q, double r, const double phi[3], std::vector<int>& out, int* nbs, int* nis, int* nin) {
   const int dim = q == 9 ? 2 : 3;
   const int R = (int)std::ceil(r) + 1;
@@ -954,16 +1128,15 @@ void build_template(int q, double r, const double phi[3], std::vector<int>& out,
             break;
           }
       }
-  for (int kind = 1; kind <= 3; kind++)
-    for (int z = -Rz; z <= Rz; z++)
-      for (int y = -R; y <= R; y++)
-        for (int x = -R; x <= R; x++) {
-          const size_t g = gi(x, y, z);
-          const bool take = kind == 1 ? bs[g] : kind == 2 ? is[g] : (in[g] && !bs[g] && !is[g]);
-          if (!take) continue;
-          out.push_back(pack_entry(x, y, z, kind));
-          (kind == 1 ? *nbs : kind == 2 ? *nis : *nin) += 1;
-        }
+  for (int z = -Rz; z <= Rz; z++)
+    for (int y = -R; y <= R; y++)
+      for (int x = -R; x <= R; x++) {
+        const size_t g = gi(x, y, z);
+        if (!in[g]) continue;
+        const int kind = bs[g] ? 1 : (is[g] ? 2 : 3);
+        out.push_back(pack_entry(x, y, z, kind));
+        (kind == 1 ? *nbs : kind == 2 ? *nis : *nin) += 1;
+      }
 }
 
 int check_status(lbm_ctx* c) {
@@ -1032,7 +1205,6 @@ int lbm_create(const lbm_params* prm, void* d_workspace, size_t bytes, void* hip
   c->hdr = (int2*)(c->ws + L.hdr);
   c->vel = c->ws + L.vel;
   c->sub = c->ws + L.sub;
-  c->isval = c->ws + L.isval;
   c->own = (int*)(c->ws + L.own);
   c->ball = (int*)(c->ws + L.ball);
   c->status = (int*)(c->ws + L.status);
@@ -1042,6 +1214,7 @@ int lbm_create(const lbm_params* prm, void* d_workspace, size_t bytes, void* hip
                       (double*)(w + L.dP),   (double*)(w + L.dL),  (double*)(w + L.F),
                       (double*)(w + L.T),    (double*)(w + L.m),   (double*)(w + L.I),
                       (double*)(w + L.rad),  (int*)(w + L.b0),     (int*)(w + L.k),
+                      (int*)(w + L.org),
                       (int*)(w + L.ent0),    (int*)(w + L.nbs),    (int*)(w + L.nis),
                       (int*)(w + L.nin),     (int*)(w + L.cand_n), (int*)(w + L.jump),
                       (int*)(w + L.cand),    (int*)(w + L.pairs)};
@@ -1051,6 +1224,13 @@ int lbm_create(const lbm_params* prm, void* d_workspace, size_t bytes, void* hip
   for (int a = 0; a < 3; a++) c->fb[a] = prm->body_force[a];
   c->prof = false;
   c->ev_used = 0;
+  {
+    // window of the largest particle: (2 hw + 1)^d sites, hw = floor(r + 1/2) + 1
+    const int64_t W = 2 * ((int64_t)std::floor(prm->max_radius + 0.5) + 1) + 1;
+    const int64_t nW = c->dim == 3 ? W * W * W : W * W;
+    const size_t bytes = (size_t)((4 * nW + 15) / 16 * 16) + (size_t)nW * (prm->storage == LBM_FP64 ? 8 : 4);
+    c->lds_window = bytes <= 65536 ? bytes : 0;
+  }
   // fluid at rest: every deviation zero; empty map; clear status
   const size_t fbytes = (size_t)c->q * c->G.N * store_size(prm->storage);
   const int64_t nwords = (int64_t)(fbytes / 4);
@@ -1166,6 +1346,10 @@ int lbm_add_particles(lbm_ctx* c, int32_t n, const double* x, const double* u, c
   UP(c->P.rad + p0, radius, (size_t)n);
   UP(c->P.b0 + 3 * p0, hb0.data(), 3 * (size_t)n);
   UP(c->P.k + 3 * p0, hk.data(), 3 * (size_t)n);
+  std::vector<int> horg(3 * n);
+  for (int j = 0; j < n; j++)
+    for (int a = 0; a < 3; a++) horg[3 * j + a] = ((hb0[3 * j + a] % box[a]) + box[a]) % box[a];
+  UP(c->P.org + 3 * p0, horg.data(), 3 * (size_t)n);
   UP(c->P.ent0 + p0, hent0.data(), (size_t)n);
   UP(c->P.nbs + p0, hnbs.data(), (size_t)n);
   UP(c->P.nis + p0, hnis.data(), (size_t)n);
@@ -1255,7 +1439,7 @@ int lbm_fields(lbm_ctx* c, double* rho, double* u, int32_t* owner) {
     std::vector<int> m(c->G.N);
     HIP_TRY(hipMemcpyAsync(m.data(), c->own, sizeof(int) * c->G.N, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    for (int64_t s = 0; s < c->G.N; s++) owner[s] = m[s] == kEmpty ? -1 : c->h_pid[m[s]];
+    for (int64_t s = 0; s < c->G.N; s++) owner[s] = m[s] == kEmpty ? -1 : c->h_pid[m[s] >> 1];
   }
   return check_status(c);
 }
@@ -1265,7 +1449,7 @@ int lbm_site_kind(lbm_ctx* c, int8_t* kind) {
   std::vector<int> m(c->G.N);
   HIP_TRY(hipMemcpyAsync(m.data(), c->own, sizeof(int) * c->G.N, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  for (int64_t s = 0; s < c->G.N; s++) kind[s] = m[s] == kEmpty ? 0 : (int8_t)entry_kind(c->h_off[m[s]]);
+  for (int64_t s = 0; s < c->G.N; s++) kind[s] = m[s] == kEmpty ? 0 : (int8_t)(1 + (m[s] & 1));
   return check_status(c);
 }
 

@@ -182,6 +182,26 @@ def test_suspension_3d(storage):
     assert np.array_equal(sim.site_kind(), ora.site_kind())
 
 
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_large_sphere(storage):
+    """A sphere of radius 10 (its per-particle record window no longer fits in
+    LDS, so the records are built one thread per entry), sinking and
+    spinning next to a small one."""
+    box = (40, 36, 44)
+    p = {"x": np.array([[20.3, 17.6, 22.1], [6.0, 5.5, 6.2]]), "u": np.array([[0.0, 0.004, -0.006], [0.0, 0.0, 0.0]]),
+         "omega": np.array([[0.0, 0.0, 1e-3], [0.0, 0.0, 0.0]]), "radius": np.array([10.0, 3.0])}
+    p["mass"], p["inertia"] = wl.solid_body(3, p["radius"], 1.3)
+    sim, ora = make_pair(19, box, 0.7, storage, particles=p, gravity=(0, 0, -2e-4), znf=True)
+    _say("large sphere", storage)
+    assert sim.particle_info(0)[0] > 1000
+    for chunk in range(4):
+        sim.step(10)
+        ora.step(10)
+        compare_particles(sim, ora, TOL[storage][1], "step %d" % (10 * chunk + 10))
+    assert err_f(sim, ora) <= TOL[storage][0]
+    assert np.array_equal(sim.site_kind(), ora.site_kind())
+
+
 def test_hard_core_collisions():
     """Many heavy disks with random velocities in a small periodic box: the
     collision sequence (lexicographic pairs, minimum image, kinematic
