@@ -58,7 +58,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp64", "fp16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--particles", type=int, default=-1,
@@ -127,7 +127,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.storage == "fp32" else "f64",
+        "dtype": {"fp32": "f32", "fp64": "f64", "fp16": "f16-store/f32", "bf16": "bf16-store/f32"}[args.storage],
         "data": "synthetic",
         "config": {"workload": cfg["name"], "lattice": "D3Q19" if q == 19 else "D2Q9", "box": [nx, ny, nz],
                    "tau": cfg["tau"], "particles": args.particles,
@@ -136,7 +136,8 @@ def main():
                    "storage": args.storage, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None,
-                     "kernel": "k_sweep<%d,%s>" % (q, "float" if args.storage == "fp32" else "double"),
+                     "kernel": "k_sweep<%d,%s>" % (q, {"fp32": "float", "fp64": "double", "fp16": "_Float16",
+                                                      "bf16": "bf16s"}[args.storage]),
                      "kernel_avg_ms": round(sweep_avg_ms, 4), "bytes_per_site": bps},
         "step_roofline_frac": round(bps * mlups * 1e6 / 1e9 / PEAK_HBM_GBPS, 4),
         "copy_ceiling_GBps": round(ceiling, 1),

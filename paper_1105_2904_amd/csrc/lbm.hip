@@ -40,6 +40,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "lattice.h"
@@ -74,6 +75,67 @@ struct Store<float> {
   static __device__ __forceinline__ float ld(const float* p) { return *p; }
   static __device__ __forceinline__ void st(float* p, float v) { __builtin_nontemporal_store(v, p); }
 };
+// Half precision: the stored number is g_i / (w_i 2^-10), i.e. the deviation
+// normalised by its weight (so that every direction spans the same range of
+// O(u) values) and scaled by 2^10 to keep small deviations normal.
+template <>
+struct Store<_Float16> {
+  using C = float;
+  static __device__ __forceinline__ float ld(const _Float16* p) { return (float)*p; }
+  static __device__ __forceinline__ void st(_Float16* p, float v) { __builtin_nontemporal_store((_Float16)v, p); }
+};
+// bfloat16: the top half of an FP32 number, rounded to nearest even; stores
+// g_i / w_i (FP32's exponent range needs no scaling).
+struct bf16s {
+  uint16_t v;
+};
+__host__ __device__ inline uint16_t f32_to_bf16_bits(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float bf16_bits_to_f32(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+template <>
+struct Store<bf16s> {
+  using C = float;
+  static __device__ __forceinline__ float ld(const bf16s* p) { return bf16_bits_to_f32(p->v); }
+  static __device__ __forceinline__ void st(bf16s* p, float v) {
+    __builtin_nontemporal_store(f32_to_bf16_bits(v), (uint16_t*)p);
+  }
+};
+
+// Multiplier from the stored number to the deviation g_i (1 for FP64/FP32).
+template <typename T>
+__host__ __device__ constexpr double pop_unit(double w) {
+  return std::is_same<T, _Float16>::value ? w * (1.0 / 1024.0) : (std::is_same<T, bf16s>::value ? w : 1.0);
+}
+
+// Load / store population i (deviation g_i in the compute type).
+template <int Q, typename T>
+__device__ __forceinline__ typename Store<T>::C pop_ld(const T* p, int i) {
+  using C = typename Store<T>::C;
+  return Store<T>::ld(p) * (C)pop_unit<T>(Lattice<Q>::w(i));
+}
+template <int Q, typename T>
+__device__ __forceinline__ void pop_st(T* p, int i, typename Store<T>::C v) {
+  using C = typename Store<T>::C;
+  Store<T>::st(p, v * (C)(1.0 / pop_unit<T>(Lattice<Q>::w(i))));
+}
+// Encoded value for a plain (not streaming) store of an FP64 result.
+template <int Q, typename T>
+__device__ __forceinline__ T pop_enc(int i, double v) {
+  const double x = v / pop_unit<T>(Lattice<Q>::w(i));
+  if constexpr (std::is_same<T, bf16s>::value)
+    return bf16s{f32_to_bf16_bits((float)x)};
+  else
+    return (T)x;
+}
 
 struct Geo {
   int nx, ny, nz;
@@ -207,7 +269,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, 
     const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
     const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
     const int sz = L::cz(i) > 0 ? zm : (L::cz(i) < 0 ? zp : z);
-    g[i] = Store<T>::ld(A + (size_t)i * a.N + (sx + a.nx * (sy + a.ny * sz)));
+    g[i] = pop_ld<Q, T>(A + (size_t)i * a.N + (sx + a.nx * (sy + a.ny * sz)), i);
   }
   const int bs = h.y;
   if (PART && h.x) {
@@ -216,7 +278,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, 
     const unsigned mask = (unsigned)h.x;
 #pragma unroll
     for (int i = 0; i < Q; i++)
-      if (mask & (1u << i)) g[i] = Store<T>::ld(sa.sub + (size_t)i * sa.stride + b);
+      if (mask & (1u << i)) g[i] = pop_ld<Q, T>(sa.sub + (size_t)i * sa.stride + b, i);
   }
   C drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
@@ -271,7 +333,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, 
     }
   }
 #pragma unroll
-  for (int i = 0; i < Q; i++) Store<T>::st(B + (size_t)i * a.N + s, g[i]);
+  for (int i = 0; i < Q; i++) pop_st<Q, T>(B + (size_t)i * a.N + s, i, g[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -582,12 +644,12 @@ __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own, co
       double dr;
       if (P.jump[E.pid[ie]]) {
         dr = 0;
-        for (int j = 0; j < Q; j++) dr += (double)B[(size_t)j * G.N + src];
+        for (int j = 0; j < Q; j++) dr += (double)pop_ld<Q, T>(B + (size_t)j * G.N + src, j);
       } else {
         dr = (double)drho[src];
       }
       mask |= 1u << i;
-      sub[(size_t)i * stride + e] = (T)rigid_feq<Q>(i, ie, dr, P, E, rho0);
+      sub[(size_t)i * stride + e] = pop_enc<Q, T>(i, rigid_feq<Q>(i, ie, dr, P, E, rho0));
     }
   }
   int bs = -1;
@@ -698,7 +760,7 @@ __global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ o
           if (jump) {
             const int src = wrap1(x - L::cx(i), G.nx) + G.nx * (wrap1(y - L::cy(i), G.ny) + G.ny * wrap1(z - L::cz(i), G.nz));
             dr = 0;
-            for (int j = 0; j < Q; j++) dr += (double)B[(size_t)j * G.N + src];
+            for (int j = 0; j < Q; j++) dr += (double)pop_ld<Q, T>(B + (size_t)j * G.N + src, j);
           } else {
             dr = (double)s_drho[wn];
           }
@@ -717,14 +779,14 @@ __global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ o
           double dr;
           if (P.jump[E.pid[ie]]) {
             dr = 0;
-            for (int j = 0; j < Q; j++) dr += (double)B[(size_t)j * G.N + src];
+            for (int j = 0; j < Q; j++) dr += (double)pop_ld<Q, T>(B + (size_t)j * G.N + src, j);
           } else {
             dr = (double)drho[src];
           }
           val = rigid_feq<Q>(i, ie, dr, P, E, rho0);
         }
         mask |= 1u << i;
-        sub[(size_t)i * stride + e] = (T)val;
+        sub[(size_t)i * stride + e] = pop_enc<Q, T>(i, val);
       }
     }
     int bs = -1;
@@ -801,7 +863,7 @@ __global__ void k_moments(const T* __restrict__ A, double* __restrict__ rho, dou
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     const int sx = wrap(x - L::cx(i), G.nx), sy = wrap(y - L::cy(i), G.ny), sz = wrap(z - L::cz(i), G.nz);
-    const double g = (double)A[(size_t)i * G.N + sx + (int64_t)G.nx * (sy + (int64_t)G.ny * sz)];
+    const double g = (double)pop_ld<Q, T>(A + (size_t)i * G.N + sx + (int64_t)G.nx * (sy + (int64_t)G.ny * sz), i);
     drho += g;
     j[0] += L::cx(i) * g;
     j[1] += L::cy(i) * g;
@@ -917,8 +979,7 @@ int check_params(const lbm_params* p) {
   const int dim = p->lattice == LBM_D2Q9 ? 2 : 3;
   if (std::max<int64_t>(p->max_particles, 1) * entries_per_particle(dim, p->max_radius) > kMaxEntries)
     return LBM_ECAPACITY;
-  if (p->storage == LBM_FP16 || p->storage == LBM_BF16) return LBM_EUNSUPPORTED;
-  if (p->storage != LBM_FP64 && p->storage != LBM_FP32) return LBM_EINVAL;
+  if (p->storage < LBM_FP64 || p->storage > LBM_BF16) return LBM_EINVAL;
   return LBM_OK;
 }
 
@@ -1075,11 +1136,12 @@ int launch_shift(lbm_ctx* c, const void* A, void* B, int dir) {
   return LBM_OK;
 }
 
-#define DISPATCH(c, FN, ...)                                                        \
-  ((c)->q == 9 ? ((c)->prm.storage == LBM_FP64 ? FN<9, double>(__VA_ARGS__)        \
-                                                : FN<9, float>(__VA_ARGS__))        \
-               : ((c)->prm.storage == LBM_FP64 ? FN<19, double>(__VA_ARGS__)       \
-                                                : FN<19, float>(__VA_ARGS__)))
+#define DISPATCH_Q(c, Qv, FN, ...)                                                        \
+  ((c)->prm.storage == LBM_FP64   ? FN<Qv, double>(__VA_ARGS__)                             \
+   : (c)->prm.storage == LBM_FP32 ? FN<Qv, float>(__VA_ARGS__)                              \
+   : (c)->prm.storage == LBM_FP16 ? FN<Qv, _Float16>(__VA_ARGS__)                           \
+                                  : FN<Qv, bf16s>(__VA_ARGS__))
+#define DISPATCH(c, FN, ...) ((c)->q == 9 ? DISPATCH_Q(c, 9, FN, __VA_ARGS__) : DISPATCH_Q(c, 19, FN, __VA_ARGS__))
 
 double lattice_w(int q, int i) { return q == 9 ? Lattice<9>::w(i) : Lattice<19>::w(i); }
 
@@ -1474,19 +1536,24 @@ int lbm_get_distributions(lbm_ctx* c, double* f) {
   rc = DISPATCH(c, launch_shift, c, c->f[c->cur], stage, 1);
   if (rc != LBM_OK) return rc;
   const int64_t n = (int64_t)c->q * c->G.N;
-  if (c->prm.storage == LBM_FP64) {
-    HIP_TRY(hipMemcpyAsync(f, stage, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-  } else {
-    std::vector<float> h(n);
-    HIP_TRY(hipMemcpyAsync(h.data(), stage, sizeof(float) * n, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    for (int64_t i = 0; i < n; i++) f[i] = (double)h[i];
-  }
+  const int ss = (int)store_size(c->prm.storage);
+  std::vector<unsigned char> h((size_t)n * ss);
+  HIP_TRY(hipMemcpyAsync(h.data(), stage, (size_t)n * ss, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
   for (int i = 0; i < c->q; i++) {
-    const double base = lattice_w(c->q, i) * c->prm.rho0;
-    double* fi = f + (int64_t)i * c->G.N;
-    for (int64_t s = 0; s < c->G.N; s++) fi[s] += base;
+    const double w = lattice_w(c->q, i);
+    const double base = w * c->prm.rho0;
+    for (int64_t s = 0; s < c->G.N; s++) {
+      const int64_t k = (int64_t)i * c->G.N + s;
+      double g;
+      switch (c->prm.storage) {
+        case LBM_FP64: g = ((const double*)h.data())[k]; break;
+        case LBM_FP32: g = ((const float*)h.data())[k]; break;
+        case LBM_FP16: g = (double)(float)((const _Float16*)h.data())[k] * pop_unit<_Float16>(w); break;
+        default: g = (double)bf16_bits_to_f32(((const uint16_t*)h.data())[k]) * pop_unit<bf16s>(w); break;
+      }
+      f[k] = base + g;
+    }
   }
   return check_status(c);
 }
@@ -1497,24 +1564,24 @@ int lbm_set_distributions(lbm_ctx* c, const double* f) {
   for (int64_t i = 0; i < n; i++)
     if (!std::isfinite(f[i])) return LBM_ENONFINITE;
   void* stage = c->f[1 - c->cur];
-  if (c->prm.storage == LBM_FP64) {
-    std::vector<double> h(n);
-    for (int i = 0; i < c->q; i++) {
-      const double base = lattice_w(c->q, i) * c->prm.rho0;
-      for (int64_t s = 0; s < c->G.N; s++) h[(int64_t)i * c->G.N + s] = f[(int64_t)i * c->G.N + s] - base;
+  const int ss = (int)store_size(c->prm.storage);
+  std::vector<unsigned char> h((size_t)n * ss);
+  for (int i = 0; i < c->q; i++) {
+    const double w = lattice_w(c->q, i);
+    const double base = w * c->prm.rho0;
+    for (int64_t s = 0; s < c->G.N; s++) {
+      const int64_t k = (int64_t)i * c->G.N + s;
+      const double g = f[k] - base;
+      switch (c->prm.storage) {
+        case LBM_FP64: ((double*)h.data())[k] = g; break;
+        case LBM_FP32: ((float*)h.data())[k] = (float)g; break;
+        case LBM_FP16: ((_Float16*)h.data())[k] = (_Float16)(g / pop_unit<_Float16>(w)); break;
+        default: ((uint16_t*)h.data())[k] = f32_to_bf16_bits((float)(g / pop_unit<bf16s>(w))); break;
+      }
     }
-    HIP_TRY(hipMemcpyAsync(stage, h.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-  } else {
-    std::vector<float> h(n);
-    for (int i = 0; i < c->q; i++) {
-      const double base = lattice_w(c->q, i) * c->prm.rho0;
-      for (int64_t s = 0; s < c->G.N; s++)
-        h[(int64_t)i * c->G.N + s] = (float)(f[(int64_t)i * c->G.N + s] - base);
-    }
-    HIP_TRY(hipMemcpyAsync(stage, h.data(), sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
   }
+  HIP_TRY(hipMemcpyAsync(stage, h.data(), (size_t)n * ss, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
   int rc = DISPATCH(c, launch_shift, c, stage, c->f[c->cur], -1);
   if (rc != LBM_OK) return rc;
   // the given populations are the complete post-propagation state

@@ -48,7 +48,6 @@ def _rc_workspace(**kw):
     (dict(lattice=9, nz=2), lbm.LBM_EINVAL),
     (dict(nx=0), lbm.LBM_EINVAL),
     (dict(nx=2048, ny=1024, nz=1024), lbm.LBM_EINVAL),
-    (dict(storage="fp16"), lbm.LBM_EUNSUPPORTED),
     (dict(storage=7), lbm.LBM_EINVAL),
     (dict(max_particles=-1), lbm.LBM_EINVAL),
     (dict(max_radius=0.0), lbm.LBM_EINVAL),

@@ -86,7 +86,7 @@ def compare_particles(sim, ora, tol_F, label=""):
 
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("q", [9, 19])
-@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16", "bf16"])
 def test_initial_state_is_exact(q, storage):
     box = (33, 17, 1) if q == 9 else (19, 11, 7)
     sim, ora = make_pair(q, box, 0.8, storage)
@@ -200,6 +200,59 @@ def test_large_sphere(storage):
         compare_particles(sim, ora, TOL[storage][1], "step %d" % (10 * chunk + 10))
     assert err_f(sim, ora) <= TOL[storage][0]
     assert np.array_equal(sim.site_kind(), ora.site_kind())
+
+
+@pytest.mark.parametrize("q", [9, 19])
+@pytest.mark.parametrize("storage,bits", [("fp16", 11), ("bf16", 8)])
+def test_reduced_precision_lbgk(q, storage, bits):
+    """FP16/BF16 storage of g_i / w_i (FP32 collision): the populations stay
+    within the storage rounding (relative 2^-bits of |g/w|, a few roundings
+    accumulated) of the FP64 oracle."""
+    box = (600, 9, 1) if q == 9 else (260, 6, 5)
+    _, w = oracle.lattice(q)
+    f0 = wl.random_populations(w, box[::-1], seed=71 + q, eps=0.05)
+    sim, ora = make_pair(q, box, 0.7, storage, f0=f0)
+    _say("reduced precision lbgk", q, storage)
+    gw = np.abs(f0 / w.reshape(q, 1, 1, 1) - 1.0).max()
+    tol = 4 * 2.0 ** -bits * gw * w.max() / np.abs(f0).max()
+    assert err_f(sim, ora) <= tol
+    sim.step(25)
+    ora.step(25)
+    e = err_f(sim, ora)
+    _say("  e_f %.2e (bound %.2e)" % (e, tol))
+    assert e <= tol
+
+
+def test_storage_precision_report():
+    """Velocity, drag and settling-velocity errors of each storage mode against
+    the FP64 oracle on a settling 3D suspension (48^3, 4 spheres r = 6,
+    density ratio 1.2), after 300 steps.  FP32 is held to the parity gates;
+    FP16/BF16 errors are reported and bounded loosely (measured values with
+    margin)."""
+    box = (48, 48, 48)
+    p = wl.suspension(19, box, 4, 6.0, 1.2, seed=81)
+    g = (0.0, 0.0, -2e-5)
+    ora = oracle.Oracle(19, *box, 0.6, gravity=g, zero_net_force=True)
+    ora.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
+    steps = 300
+    ora.step(steps)
+    Fo, _, _, uo, _ = ora.forces()
+    _, vo, _ = ora.fields()
+    bounds = {"fp32": (1e-5, 1e-4, 1e-4), "fp16": (2e-2, 5e-2, 5e-2), "bf16": (2e-1, 5e-1, 5e-1)}
+    for storage in ("fp32", "fp16", "bf16"):
+        sim = lbm.Simulation(19, *box, tau=0.6, gravity=g, zero_net_force=True, storage=storage,
+                             max_particles=4, max_radius=6.0)
+        sim.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
+        sim.step(steps)
+        Fg, _, _, ug, _ = sim.forces()
+        _, vg, _ = sim.fields()
+        e_vel = np.linalg.norm(vg - vo) / np.linalg.norm(vo)
+        e_drag = np.linalg.norm(Fg - Fo, axis=1).max() / np.linalg.norm(Fo, axis=1).max()
+        e_settle = abs(ug[:, 2].mean() - uo[:, 2].mean()) / abs(uo[:, 2].mean())
+        _say("  %s: velocity %.2e  drag %.2e  settling %.2e" % (storage, e_vel, e_drag, e_settle))
+        bv, bd, bs = bounds[storage]
+        assert e_vel <= bv and e_drag <= bd and e_settle <= bs, storage
+        sim.close()
 
 
 def test_hard_core_collisions():
