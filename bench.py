@@ -5,8 +5,12 @@ Workload: D3Q19, 256^3 periodic box, 500 spheres of radius 6 (density ratio
 FP32.  A step is the whole hot path (sweep, BS substep + per-particle sums,
 particle update, map rebuild, IS substep) over the box.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage fp32|fp64]
-                  [--no-cpu-baseline]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage fp32|fp64|fp16|bf16]
+                  [--no-cpu-baseline] [--no-variants] [--workload spheres-3d|disks-2d]
+
+The FP32 run also times the FP16 and BF16 storage variants of the same
+workload ("variants") and the FP64 oracle on a few steps of the same box
+("cpu_baseline").
 """
 import argparse
 import json
@@ -18,6 +22,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0  # MI355X HBM3E
+COUNTERS = os.path.join(ROOT, "profiles", "k_sweep_d3q19_256cubed_500spheres_fp32_hbm_counters.json")
+
+
+def measured_traffic(kernel, workload, storage):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
+    counter runs (copy-kernel calibrated), or None when no run covers this
+    kernel and workload or the kernel sources changed since it was taken."""
+    import hashlib
+    try:
+        with open(COUNTERS) as fh:
+            c = json.load(fh)
+    except OSError:
+        return None
+    if (c["kernel"], c["workload"], c["storage"]) != (kernel, workload, storage):
+        return None
+    h = hashlib.sha256()
+    for f in c["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != c["source_sha256"]:
+        return None
+    return c["hbm_bytes_per_launch"]
 
 
 def copy_ceiling(torch, lbm, stream, nbytes=2 << 30, reps=10):
@@ -60,7 +86,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp64", "fp16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip timing the FP16/BF16 storage variants of the same workload")
     ap.add_argument("--particles", type=int, default=-1,
                     help="particles in the box (default: the workload's; fewer only to measure overheads)")
     ap.add_argument("--workload", default="spheres-3d", choices=["spheres-3d", "disks-2d"],
@@ -93,29 +121,40 @@ def main():
     bps = lbm.lbm_bytes_per_site(sim.params)
     stream = sim.stream
 
-    sim.step(args.warmup)
-    torch.cuda.synchronize()
-    print("warmup done (%d steps)" % args.warmup, file=sys.stderr, flush=True)
+    def timed(sim_, steps, warmup, profile):
+        """Whole-step time of `steps` steps and, with profiling on, the summed
+        time and count of the sweep launches (HIP events on the sim's stream)."""
+        sim_.step(warmup)
+        torch.cuda.synchronize()
+        if profile:
+            sim_.set_profiling(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(sim_.stream)
+        sim_.step(steps)
+        e1.record(sim_.stream)
+        e1.synchronize()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        sw = sim_.profile() if profile else None
+        if profile:
+            sim_.set_profiling(False)
+        F_ = sim_.forces()[0]
+        assert F_.shape == (args.particles, 3) and np.isfinite(F_).all()
+        return ms, sw
 
-    sim.set_profiling(True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    sim.step(args.steps)
-    e1.record(stream)
-    e1.synchronize()
-    torch.cuda.synchronize()
-    ms_total = e0.elapsed_time(e1)
-    sweep_ms, sweeps = sim.profile()
-    sim.set_profiling(False)
-    F = sim.forces()[0]
-    assert F.shape == (args.particles, 3) and np.isfinite(F).all()
-
+    ms_total, (sweep_ms, sweeps) = timed(sim, args.steps, args.warmup, True)
+    print("timed %d steps" % args.steps, file=sys.stderr, flush=True)
     ms_step = ms_total / args.steps
     mlups = N / (ms_step * 1e-3) / 1e6
+    kname = {"fp32": "float", "fp64": "double", "fp16": "_Float16", "bf16": "bf16s"}[args.storage]
     sweep_avg_ms = sweep_ms / max(sweeps, 1)
     achieved = bps * N / (sweep_avg_ms * 1e-3) / 1e9
     ceiling = copy_ceiling(torch, lbm, stream)
+    kernel = "k_sweep<%d,%s,%s>" % (q, kname, "true" if args.particles else "false")
+    traffic = None
+    if args.particles == len(cfg["particles"]["radius"]):
+        traffic = measured_traffic(kernel.replace(",", ", "), cfg["name"], args.storage)
     out = {
         "metric": "MLUPS + % HBM roofline, D3Q19 256³ 500 spheres; FP16-store/batched vs FP32",
         "value": round(mlups, 1),
@@ -135,13 +174,34 @@ def main():
                    "density_ratio": 1.2 if q == 19 else 1.5, "gravity": float(-min(cfg["gravity"])),
                    "storage": args.storage, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None,
-                     "kernel": "k_sweep<%d,%s>" % (q, {"fp32": "float", "fp64": "double", "fp16": "_Float16",
-                                                      "bf16": "bf16s"}[args.storage]),
-                     "kernel_avg_ms": round(sweep_avg_ms, 4), "bytes_per_site": bps},
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                     "traffic": None if traffic is None else traffic["total"],
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic_read_write": None if traffic is None else [traffic["read"], traffic["write"]],
+                     "algorithmic_bytes_per_launch": bps * N,
+                     "kernel": kernel, "kernel_avg_ms": round(sweep_avg_ms, 4), "sites_per_launch": N,
+                     "bytes_per_site": bps},
         "step_roofline_frac": round(bps * mlups * 1e6 / 1e9 / PEAK_HBM_GBPS, 4),
         "copy_ceiling_GBps": round(ceiling, 1),
     }
+    if not args.no_variants and args.storage == "fp32":
+        out["variants"] = {}
+        sim.close()
+        for st in ("fp16", "bf16"):
+            v = lbm.Simulation(q, nx, ny, nz, tau=cfg["tau"], gravity=cfg["gravity"], zero_net_force=True,
+                               storage=st, max_particles=max(len(p["radius"]), 1),
+                               max_radius=float(np.max(cfg["particles"]["radius"])))
+            if args.particles:
+                v.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
+            vms, (vsw, vn) = timed(v, args.steps, args.warmup, True)
+            vb = lbm.lbm_bytes_per_site(v.params)
+            vm = N / (vms / args.steps * 1e-3) / 1e6
+            vs = vsw / max(vn, 1)
+            out["variants"][st] = {"value": round(vm, 1), "ms_per_step": round(vms / args.steps, 4),
+                                   "speedup_vs_fp32": round(vm / mlups, 3), "bytes_per_site": vb,
+                                   "sweep_avg_ms": round(vs, 4), "sweep_GBps": round(vb * N / (vs * 1e-3) / 1e9, 1)}
+            v.close()
+            print("variant %s timed" % st, file=sys.stderr, flush=True)
     if not args.no_cpu_baseline and args.workload == "spheres-3d":
         print("cpu baseline: %d oracle steps" % args.cpu_steps, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)

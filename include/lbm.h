@@ -55,9 +55,10 @@ extern "C" {
 enum lbm_lattice { LBM_D2Q9 = 9, LBM_D3Q19 = 19 };
 
 /* Storage precision of the distributions.  Distributions are stored as
- * deviations f_i - w_i rho0.  FP64 computes in FP64; FP32 collides in FP32
- * and performs the particle substeps (BS, IS), the per-particle sums and the
- * Newton-Euler update in FP64.  FP16/BF16 are reserved. */
+ * deviations g_i = f_i - w_i rho0.  FP64 computes in FP64.  FP32 collides in
+ * FP32; FP16 and BF16 store g_i / w_i (FP16 also scaled by 2^10) and collide
+ * in FP32.  In every mode the per-site momentum exchange, the per-particle
+ * sums and the Newton-Euler update are FP64. */
 enum lbm_storage { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16 = 2, LBM_BF16 = 3 };
 
 enum lbm_status {

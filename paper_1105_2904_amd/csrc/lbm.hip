@@ -346,6 +346,126 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
+// K3: particle update, one workgroup (eq. 10-11, 16-19, 13).
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(NT) void k_particles(DevParticles P, int np, int dim, Geo G, int* status) {
+  __shared__ int s_scan[NT];
+  __shared__ double s_vmax[NT / 64];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  double vmax = 0;
+  for (int p = tid; p < np; p += NT) {
+    const double m = P.m[p], I = P.I[p];
+    double v2 = 0;
+    for (int a = 0; a < 3; a++) {
+      const double dp = P.dP[3 * p + a], dl = P.dL[3 * p + a];
+      P.F[3 * p + a] = -dp;
+      P.T[3 * p + a] = -dl;
+      double u = P.u[3 * p + a];
+      if (!isinf(m)) u = u + (P.fext[3 * p + a] - dp) / m;
+      P.u[3 * p + a] = u;
+      if (!isinf(I)) P.om[3 * p + a] = P.om[3 * p + a] - dl / I;
+      v2 += u * u;
+    }
+    vmax = fmax(vmax, sqrt(v2));
+  }
+  for (int o = 32; o > 0; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o));
+  if (lane == 0) s_vmax[wv] = vmax;
+
+  // lexicographic list of candidate pairs: exclusive scan of the counts
+  int total = 0;
+  for (int b = 0; b < np; b += NT) {
+    const int p = b + tid;
+    const int c = p < np ? P.cand_n[p] : 0;
+    if (!__syncthreads_or(c)) continue;  // no close pair in this chunk
+    s_scan[tid] = c;
+    __syncthreads();
+    for (int off = 1; off < NT; off <<= 1) {
+      const int v = tid >= off ? s_scan[tid - off] : 0;
+      __syncthreads();
+      s_scan[tid] += v;
+      __syncthreads();
+    }
+    const int excl = total + s_scan[tid] - c;
+    for (int t = 0; t < c; t++) {
+      P.pairs[2 * (excl + t)] = p;
+      P.pairs[2 * (excl + t) + 1] = P.cand[p * kCandMax + t];
+    }
+    total += s_scan[NT - 1];
+    __syncthreads();
+  }
+
+  __syncthreads();
+  if (tid == 0) {
+    double vseen = 0;
+    for (int w = 0; w < NT / 64; w++) vseen = fmax(vseen, s_vmax[w]);
+    const int L[3] = {G.nx, G.ny, G.nz};
+    for (int t = 0; t < total; t++) {
+      const int i = P.pairs[2 * t], j = P.pairs[2 * t + 1];
+      const bool infA = isinf(P.m[i]), infB = isinf(P.m[j]);
+      if (infA && infB) continue;
+      double d[3], dd = 0;
+      for (int a = 0; a < 3; a++) {
+        d[a] = (P.x[3 * j + a] + P.u[3 * j + a]) - (P.x[3 * i + a] + P.u[3 * i + a]);
+        if (a < dim) d[a] = d[a] - L[a] * floor(d[a] / L[a] + 0.5);
+        dd += d[a] * d[a];
+      }
+      const double dist = sqrt(dd);
+      if (dist > P.rad[i] + P.rad[j] || dist == 0.0) continue;
+      double n[3], vn = 0;
+      for (int a = 0; a < 3; a++) {
+        n[a] = d[a] / dist;
+        vn += (P.u[3 * j + a] - P.u[3 * i + a]) * n[a];
+      }
+      if (!(vn < 0.0)) continue;
+      double V[3];
+      const double mi = P.m[i], mj = P.m[j];
+      for (int a = 0; a < 3; a++) {
+        if (infA)
+          V[a] = P.u[3 * i + a];
+        else if (infB)
+          V[a] = P.u[3 * j + a];
+        else
+          V[a] = (mi * P.u[3 * i + a] + mj * P.u[3 * j + a]) / (mi + mj);
+      }
+      const int who[2] = {i, j};
+      for (int t2 = 0; t2 < 2; t2++) {
+        const int q = who[t2];
+        double wvv[3], wn = 0, v2 = 0;
+        for (int a = 0; a < 3; a++) {
+          wvv[a] = P.u[3 * q + a] - V[a];
+          wn += wvv[a] * n[a];
+        }
+        for (int a = 0; a < 3; a++) {
+          const double u = V[a] + (wvv[a] - 2.0 * wn * n[a]);
+          P.u[3 * q + a] = u;
+          v2 += u * u;
+        }
+        vseen = fmax(vseen, sqrt(v2));
+      }
+    }
+    if (2.0 * vseen >= kMargin) atomicOr(status, kStatusCollision);
+  }
+  __syncthreads();
+  const int L[3] = {G.nx, G.ny, G.nz};
+  for (int p = tid; p < np; p += NT) {
+    int moved = 0;
+    for (int a = 0; a < dim; a++) {
+      const double x = P.x[3 * p + a] + P.u[3 * p + a];
+      P.x[3 * p + a] = x;
+      const int k = (int)floor(x - P.x0[3 * p + a] + 0.5);
+      moved += k != P.k[3 * p + a];
+      P.k[3 * p + a] = k;
+      P.org[3 * p + a] = wrap(P.b0[3 * p + a] + k, L[a]);
+    }
+    // a shift along all three axes at once (not a D3Q19 link) can take an IS
+    // site outside the ball the sweep kept densities for
+    P.jump[p] = moved == 3;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // K2: per-particle sums of the BS slots (eq. 8-9) in a fixed order, release
 // of the particle's stamps, and the list of particles close enough to collide
 // this step.  One workgroup per particle.
@@ -353,7 +473,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own, int* __restrict__ ball,
                                                             const double* __restrict__ slot,
                                                             DevParticles P, DevEntries E, Geo G, int np,
-                                                            double rho0, int* status) {
+                                                            double rho0, int dim, int* status) {
   constexpr int kWaves = kBoundaryBlock / 64;
   __shared__ double s_part[kWaves][6];
   __shared__ int s_cnt[kWaves];
@@ -428,7 +548,7 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
 
   // Close neighbours j > p (positions before translation), listed in
   // increasing j: the only pairs that can pass the collision test this step
-  // while every speed stays below kMargin / 2 (checked in k_particles).
+  // while every speed stays below kMargin / 2 (checked in the particle update).
   const double xpx = P.x[3 * p], xpy = P.x[3 * p + 1], xpz = P.x[3 * p + 2];
   const double rp = P.rad[p];
   int base = 0;
@@ -463,126 +583,7 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
     P.cand_n[p] = base < kCandMax ? base : kCandMax;
     if (base > kCandMax) atomicOr(status, kStatusCollision);
   }
-}
 
-// ---------------------------------------------------------------------------
-// K3: particle update, one workgroup (eq. 10-11, 16-19, 13).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kParticleBlock) void k_particles(DevParticles P, int np, int dim, Geo G,
-                                                              int* status) {
-  __shared__ int s_scan[kParticleBlock];
-  __shared__ double s_vmax[kParticleBlock / 64];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6;
-  double vmax = 0;
-  for (int p = tid; p < np; p += kParticleBlock) {
-    const double m = P.m[p], I = P.I[p];
-    double v2 = 0;
-    for (int a = 0; a < 3; a++) {
-      const double dp = P.dP[3 * p + a], dl = P.dL[3 * p + a];
-      P.F[3 * p + a] = -dp;
-      P.T[3 * p + a] = -dl;
-      double u = P.u[3 * p + a];
-      if (!isinf(m)) u = u + (P.fext[3 * p + a] - dp) / m;
-      P.u[3 * p + a] = u;
-      if (!isinf(I)) P.om[3 * p + a] = P.om[3 * p + a] - dl / I;
-      v2 += u * u;
-    }
-    vmax = fmax(vmax, sqrt(v2));
-  }
-  for (int o = 32; o > 0; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o));
-  if (lane == 0) s_vmax[wv] = vmax;
-
-  // lexicographic list of candidate pairs: exclusive scan of the counts
-  int total = 0;
-  for (int b = 0; b < np; b += kParticleBlock) {
-    const int p = b + tid;
-    const int c = p < np ? P.cand_n[p] : 0;
-    if (!__syncthreads_or(c)) continue;  // no close pair in this chunk
-    s_scan[tid] = c;
-    __syncthreads();
-    for (int off = 1; off < kParticleBlock; off <<= 1) {
-      const int v = tid >= off ? s_scan[tid - off] : 0;
-      __syncthreads();
-      s_scan[tid] += v;
-      __syncthreads();
-    }
-    const int excl = total + s_scan[tid] - c;
-    for (int t = 0; t < c; t++) {
-      P.pairs[2 * (excl + t)] = p;
-      P.pairs[2 * (excl + t) + 1] = P.cand[p * kCandMax + t];
-    }
-    total += s_scan[kParticleBlock - 1];
-    __syncthreads();
-  }
-
-  __syncthreads();
-  if (tid == 0) {
-    double vseen = 0;
-    for (int w = 0; w < kParticleBlock / 64; w++) vseen = fmax(vseen, s_vmax[w]);
-    const int L[3] = {G.nx, G.ny, G.nz};
-    for (int t = 0; t < total; t++) {
-      const int i = P.pairs[2 * t], j = P.pairs[2 * t + 1];
-      const bool infA = isinf(P.m[i]), infB = isinf(P.m[j]);
-      if (infA && infB) continue;
-      double d[3], dd = 0;
-      for (int a = 0; a < 3; a++) {
-        d[a] = (P.x[3 * j + a] + P.u[3 * j + a]) - (P.x[3 * i + a] + P.u[3 * i + a]);
-        if (a < dim) d[a] = d[a] - L[a] * floor(d[a] / L[a] + 0.5);
-        dd += d[a] * d[a];
-      }
-      const double dist = sqrt(dd);
-      if (dist > P.rad[i] + P.rad[j] || dist == 0.0) continue;
-      double n[3], vn = 0;
-      for (int a = 0; a < 3; a++) {
-        n[a] = d[a] / dist;
-        vn += (P.u[3 * j + a] - P.u[3 * i + a]) * n[a];
-      }
-      if (!(vn < 0.0)) continue;
-      double V[3];
-      const double mi = P.m[i], mj = P.m[j];
-      for (int a = 0; a < 3; a++) {
-        if (infA)
-          V[a] = P.u[3 * i + a];
-        else if (infB)
-          V[a] = P.u[3 * j + a];
-        else
-          V[a] = (mi * P.u[3 * i + a] + mj * P.u[3 * j + a]) / (mi + mj);
-      }
-      const int who[2] = {i, j};
-      for (int t2 = 0; t2 < 2; t2++) {
-        const int q = who[t2];
-        double wvv[3], wn = 0, v2 = 0;
-        for (int a = 0; a < 3; a++) {
-          wvv[a] = P.u[3 * q + a] - V[a];
-          wn += wvv[a] * n[a];
-        }
-        for (int a = 0; a < 3; a++) {
-          const double u = V[a] + (wvv[a] - 2.0 * wn * n[a]);
-          P.u[3 * q + a] = u;
-          v2 += u * u;
-        }
-        vseen = fmax(vseen, sqrt(v2));
-      }
-    }
-    if (2.0 * vseen >= kMargin) atomicOr(status, kStatusCollision);
-  }
-  __syncthreads();
-  const int L[3] = {G.nx, G.ny, G.nz};
-  for (int p = tid; p < np; p += kParticleBlock) {
-    int moved = 0;
-    for (int a = 0; a < dim; a++) {
-      const double x = P.x[3 * p + a] + P.u[3 * p + a];
-      P.x[3 * p + a] = x;
-      const int k = (int)floor(x - P.x0[3 * p + a] + 0.5);
-      moved += k != P.k[3 * p + a];
-      P.k[3 * p + a] = k;
-      P.org[3 * p + a] = wrap(P.b0[3 * p + a] + k, L[a]);
-    }
-    // a shift along all three axes at once (not a D3Q19 link) can take an IS
-    // site outside the ball the sweep kept densities for
-    P.jump[p] = moved == 3;
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -720,6 +721,7 @@ __global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ o
   const double phx = P.phi[3 * p], phy = P.phi[3 * p + 1], phz = P.phi[3 * p + 2];
   const double upx = P.u[3 * p], upy = P.u[3 * p + 1], upz = P.u[3 * p + 2];
   const double wx = P.om[3 * p], wy = P.om[3 * p + 1], wz = P.om[3 * p + 2];
+  const C cupx = (C)upx, cupy = (C)upy, cupz = (C)upz, cwx = (C)wx, cwy = (C)wy, cwz = (C)wz;
   const int e0 = P.ent0[p], ne = P.nbs[p] + P.nis[p] + P.nin[p];
   const bool jump = P.jump[p] != 0;
   constexpr int kEnt = 4;
@@ -764,15 +766,17 @@ __global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ o
           } else {
             dr = (double)s_drho[wn];
           }
-          const double rx = (double)(ox - L::cx(i)) - phx, ry = (double)(oy - L::cy(i)) - phy,
-                       rz = (double)(oz - L::cz(i)) - phz;
-          const double vx = upx + (wy * rz - wz * ry);
-          const double vy = upy + (wz * rx - wx * rz);
-          const double vz = upz + (wx * ry - wy * rx);
-          const double rho = rho0 + dr;
-          const double usq = 1.5 * (vx * vx + vy * vy + vz * vz);
-          const double cu = L::cx(i) * vx + L::cy(i) * vy + L::cz(i) * vz;
-          val = L::w(i) * (dr + rho * (3.0 * cu + 4.5 * cu * cu - usq));
+          // in the compute precision of the storage (the value is stored in it)
+          const C rx = (C)((double)(ox - L::cx(i)) - phx), ry = (C)((double)(oy - L::cy(i)) - phy),
+                  rz = (C)((double)(oz - L::cz(i)) - phz);
+          const C vx = cupx + (cwy * rz - cwz * ry);
+          const C vy = cupy + (cwz * rx - cwx * rz);
+          const C vz = cupz + (cwx * ry - cwy * rx);
+          const C dc = (C)dr;
+          const C rho = (C)rho0 + dc;
+          const C usq = C(1.5) * (vx * vx + vy * vy + vz * vz);
+          const C cu = C(L::cx(i)) * vx + C(L::cy(i)) * vy + C(L::cz(i)) * vz;
+          val = (double)(C(L::w(i)) * (dc + rho * (C(3) * cu + C(4.5) * cu * cu - usq)));
         } else {
           // an IS site of another particle (balls overlap)
           const int src = wrap1(x - L::cx(i), G.nx) + G.nx * (wrap1(y - L::cy(i), G.ny) + G.ny * wrap1(z - L::cz(i), G.nz));
@@ -898,10 +902,11 @@ __global__ void k_fill(V* __restrict__ p, int64_t n, V v) {
 
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
-// one 16-byte vector per thread, streaming load and store
+// one 16-byte vector per thread: plain load, streaming store (the access
+// kinds the sweep uses)
 __global__ __launch_bounds__(256) void k_copy16(const v4u* __restrict__ src, v4u* __restrict__ dst, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+  if (i < n) __builtin_nontemporal_store(src[i], dst + i);
 }
 
 inline unsigned blocks_for(int64_t n, int per = 256) { return (unsigned)((n + per - 1) / per); }
@@ -1099,8 +1104,8 @@ int launch_step(lbm_ctx* c) {
   HIP_TRY(hipGetLastError());
   if (c->np > 0) {
     k_reduce<<<c->np, kBoundaryBlock, 0, c->stream>>>(c->own, c->ball, c->slot, c->P, c->E, c->G, c->np,
-                                                      c->prm.rho0, c->status);
-    k_particles<<<1, kParticleBlock, 0, c->stream>>>(c->P, c->np, c->dim, c->G, c->status);
+                                                      c->prm.rho0, c->dim, c->status);
+    k_particles<kParticleBlock><<<1, kParticleBlock, 0, c->stream>>>(c->P, c->np, c->dim, c->G, c->status);
     k_stamp<<<blocks_for(c->nent), 256, 0, c->stream>>>(c->own, c->ball, c->P, c->E, c->G, 0, (int)c->nent);
     HIP_TRY(hipGetLastError());
   }
