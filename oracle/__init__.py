@@ -61,6 +61,8 @@ def lib():
         L.ora_lattice.restype = ctypes.c_int
         L.ora_lattice.argtypes = [ctypes.c_int, _ip, _dp]
         L.ora_feq.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp]
+        L.ora_set_walls.restype = ctypes.c_int
+        L.ora_set_walls.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp]
         _lib = L
     return _lib
 
@@ -95,7 +97,7 @@ class Oracle:
     """A periodic box stepped by the oracle (same call shape as the C ABI)."""
 
     def __init__(self, q, nx, ny, nz, tau, rho0=1.0, gravity=(0, 0, 0),
-                 body_force=(0, 0, 0), zero_net_force=False):
+                 body_force=(0, 0, 0), zero_net_force=False, walls=0, wall_velocity=None):
         self.q, self.nx, self.ny, self.nz = q, nx, ny, nz
         self.N = nx * ny * nz
         g = np.ascontiguousarray(gravity, dtype=np.float64)
@@ -104,6 +106,12 @@ class Oracle:
                                    int(bool(zero_net_force)))
         if not self._h:
             raise ValueError("invalid oracle parameters")
+        if walls:
+            wu = np.zeros((3, 2, 3)) if wall_velocity is None else \
+                np.ascontiguousarray(wall_velocity, dtype=np.float64).reshape(3, 2, 3)
+            if lib().ora_set_walls(self._h, int(walls), _d(wu)) != 0:
+                self.close()
+                raise ValueError("invalid wall parameters")
 
     def close(self):
         if self._h:
@@ -185,8 +193,8 @@ class Oracle:
         return off[:n], kind[:n]
 
     def diagnostics(self):
-        d = np.zeros(14)
+        d = np.zeros(17)
         lib().ora_diagnostics(self._h, _d(d))
         return {"mass": d[0], "momentum": d[1:4].copy(), "is_leak": d[4:7].copy(),
                 "conflicts": int(d[7]), "fragility": d[8], "min_gap": d[9],
-                "step": int(d[10]), "body_force": d[11:14].copy()}
+                "step": int(d[10]), "body_force": d[11:14].copy(), "wall_momentum": d[14:17].copy()}

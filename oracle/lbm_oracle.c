@@ -14,6 +14,8 @@
  *   translation of particle and site sets (eq. 13-15)
  *   IS substep on the new map (eq. 12 and the fourth substep)
  *   propagate every site (eq. 3, left-hand side)
+ * Optional walls close the box along chosen axes (section 3's closed boxes;
+ * the paper does not say how its walls are imposed, see wall_substep).
  */
 #include "lbm_oracle.h"
 
@@ -94,6 +96,9 @@ struct ora_sim {
   double leak[3];
   long conflicts;
   long step;
+  int walls;              /* bit a: axis a closed by wall layers */
+  double wall_u[3][2][3]; /* [axis][low, high][component] */
+  double wall_dp[3];      /* momentum the walls gave the fluid, last step */
 };
 
 static long site_index(const ora_sim *s, long x, long y, long z) {
@@ -103,6 +108,30 @@ static long site_index(const ora_sim *s, long x, long y, long z) {
 static long wrapi(long a, long n) {
   long r = a % n;
   return r < 0 ? r + n : r;
+}
+
+/* Wall layers.  Reading (the paper closes its boxes but does not describe
+ * the walls): a wall is an immobile solid slab treated by the same site
+ * rule as a particle.  A closed axis of n sites keeps layers 2 .. n-3 as
+ * fluid; layers 1 and n-2 are the wall's BS sites (linked to the fluid),
+ * layers 0 and n-1 its IS sites (linked to the BS layers; across the
+ * periodic seam the two walls form one slab of four layers).  The wall
+ * velocity U is tangential and applies to the layers of its side.  At a site
+ * in the layers of several axes the lowest axis decides the velocity.
+ * Returns 1 and the velocity for a wall site, 0 otherwise. */
+static int wall_site(const ora_sim *s, long x, long y, long z, double U[3]) {
+  long c[3] = {x, y, z};
+  int L[3] = {s->nx, s->ny, s->nz};
+  for (int a = 0; a < s->dim; a++) {
+    if (!(s->walls & (1 << a))) continue;
+    if (c[a] < 2 || c[a] >= L[a] - 2) {
+      int side = c[a] >= L[a] - 2;
+      if (U)
+        for (int b = 0; b < 3; b++) U[b] = s->wall_u[a][side][b];
+      return 1;
+    }
+  }
+  return 0;
 }
 
 ora_sim *ora_create(int q, int nx, int ny, int nz, double tau, double rho0,
@@ -261,6 +290,9 @@ static void raster(ora_sim *s) {
     particle *P = &s->P[p];
     for (int e = 0; e < P->nbs + P->nis; e++) {
       long n = entry_site(s, P, e);
+      /* wall sites belong to the wall (it acts as the lowest id) */
+      if (wall_site(s, n % s->nx, (n / s->nx) % s->ny, n / ((long)s->nx * s->ny), NULL))
+        continue;
       if (s->own_p[n] < 0) {
         s->own_p[n] = p;
         s->own_e[n] = e;
@@ -413,6 +445,29 @@ static void boundary_substep(ora_sim *s, double (*dP)[3], double (*dL)[3]) {
   }
 }
 
+/* The wall's share of the substeps.  Every wall site takes f^eq(rho, U)
+ * with its own post-collision density and the wall velocity, as BS and IS
+ * sites of a particle do (eq. 5, 12).  The wall does not move, so its BS
+ * sites (first substep) and IS sites (fourth substep) take the same values
+ * whichever substep imposes them, and no particle owns a wall site; doing
+ * all of them here gives the same state.  The momentum given to the fluid is
+ * kept as a diagnostic. */
+static void wall_substep(ora_sim *s) {
+  for (int a = 0; a < 3; a++) s->wall_dp[a] = 0.0;
+  if (!s->walls) return;
+  for (long z = 0; z < s->nz; z++)
+    for (long y = 0; y < s->ny; y++)
+      for (long x = 0; x < s->nx; x++) {
+        double U[3];
+        if (!wall_site(s, x, y, z, U)) continue;
+        long n = site_index(s, x, y, z);
+        double rho, u[3];
+        site_moments(s, s->fs, n, &rho, u);
+        for (int a = 0; a < 3; a++) s->wall_dp[a] += rho * (U[a] - u[a]);
+        impose_equilibrium(s, n, rho, U);
+      }
+}
+
 /* Second substep (eq. 10-11): the particle takes the opposite change.  The
  * buoyancy-corrected weight is added (the settling runs of section 3 need it
  * though eq. 10 omits it).  Kinematic particles keep their velocities. */
@@ -478,6 +533,27 @@ static void collisions(ora_sim *s) {
     }
 }
 
+/* Hard-core contact with a wall, after the pairs: the wall is an infinite
+ * mass moving tangentially, so the particle's normal velocity reverses when
+ * its predicted surface reaches the wall's BS layer (1 or n-2) while it
+ * approaches.  Kinematic particles keep their velocity.  Particles in id
+ * order, axes in order. */
+static void wall_collisions(ora_sim *s) {
+  if (!s->walls) return;
+  int L[3] = {s->nx, s->ny, s->nz};
+  for (int p = 0; p < s->np; p++) {
+    particle *P = &s->P[p];
+    if (isinf(P->m)) continue;
+    for (int a = 0; a < s->dim; a++) {
+      if (!(s->walls & (1 << a))) continue;
+      double xp = P->x[a] + P->u[a];
+      if ((xp - P->r <= 1.0 && P->u[a] < 0.0) ||
+          (xp + P->r >= (double)(L[a] - 2) && P->u[a] > 0.0))
+        P->u[a] = -P->u[a];
+    }
+  }
+}
+
 /* Third substep (eq. 13-15): x_p' = x_p + u_p'; the site sets move with the
  * particle without rotating, so the new map is the template at the nearest
  * integer shift k = [x_p - x_p0]. */
@@ -531,8 +607,10 @@ void ora_step(ora_sim *s, int nsteps) {
   for (int t = 0; t < nsteps; t++) {
     collide(s);
     boundary_substep(s, dP, dL);
+    wall_substep(s);
     accelerate(s, dP, dL);
     collisions(s);
+    wall_collisions(s);
     translate(s);
     internal_substep(s);
     propagate(s);
@@ -641,4 +719,22 @@ void ora_diagnostics(const ora_sim *s, double *d) {
   d[9] = gap;
   d[10] = (double)s->step;
   for (int a = 0; a < 3; a++) d[11 + a] = s->fb[a];
+  for (int a = 0; a < 3; a++) d[14 + a] = s->wall_dp[a];
+}
+
+int ora_set_walls(ora_sim *s, int walls, const double *wall_u) {
+  int L[3] = {s->nx, s->ny, s->nz};
+  if (walls < 0 || walls >= (1 << s->dim) || s->np > 0) return -1;
+  for (int a = 0; a < 3; a++)
+    for (int side = 0; side < 2; side++)
+      for (int b = 0; b < 3; b++) {
+        double v = wall_u ? wall_u[6 * a + 3 * side + b] : 0.0;
+        if (!(walls & (1 << a))) v = 0.0;
+        if (b == a && v != 0.0) return -1; /* walls move tangentially only */
+        s->wall_u[a][side][b] = v;
+      }
+  for (int a = 0; a < s->dim; a++)
+    if ((walls & (1 << a)) && L[a] < 5) return -1;
+  s->walls = walls;
+  return 0;
 }

@@ -86,8 +86,16 @@ int ora_template(const ora_sim *s, int p, int32_t *nbs, int32_t *nis,
  *  d[8] smallest distance of any displacement component to a half integer,
  *  d[9] smallest surface gap between two particles,
  *  d[10] step counter,
- *  d[11..13] fluid body force density applied each step. */
+ *  d[11..13] fluid body force density applied each step,
+ *  d[14..16] momentum the walls gave the fluid in the last step. */
 void ora_diagnostics(const ora_sim *s, double *d);
+
+/* Close the box along the axes in the bit mask `walls` (bit 0 x, 1 y, 2 z)
+ * with immobile site-based wall layers: on a closed axis of n sites, layers
+ * 0, 1, n-2, n-1 are wall sites and 2 .. n-3 fluid.  wall_u is
+ * [axis][low, high][3] (NULL = at rest); the component along the axis must
+ * be 0.  Call before adding particles.  Returns 0, or -1 on invalid input. */
+int ora_set_walls(ora_sim *s, int walls, const double *wall_u);
 
 int ora_num_particles(const ora_sim *s);
 
