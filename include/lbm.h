@@ -21,6 +21,15 @@
  * to the particle's shift; lowest particle id owns a site claimed twice;
  * F_ext = (m - rho0 V) g with the analytic V.
  *
+ * Walls (optional; the paper closes its boxes in section 3 without describing
+ * how): a closed axis of n sites keeps layers 2 .. n-3 as fluid, and its
+ * layers 0, 1, n-2, n-1 are an immobile (or tangentially sliding) solid slab
+ * treated by the site rule of the particles: every wall site takes
+ * f^eq(rho, U_wall) with its own density after the collision.  Particles never
+ * own wall sites, and a particle whose predicted surface reaches the wall's
+ * BS layer (1 or n-2) while approaching it has its normal velocity reversed
+ * (eq. 16-19 with the wall as an infinite mass), after the particle pairs.
+ *
  * Conventions
  *  - Lattice units: dx = dt = 1.  Every axis is periodic.
  *  - Distribution layout (host buffers): f[q][nz][ny][nx], x fastest, plain f
@@ -88,6 +97,10 @@ typedef struct lbm_params {
   int32_t storage;       /* enum lbm_storage */
   int32_t max_particles; /* capacity (>= 0) */
   double max_radius;     /* largest particle radius that will be added (0 < r <= 120) */
+  int32_t walls;         /* bit a (0 x, 1 y, 2 z; z only for D3Q19): axis a closed by
+                            wall layers at both ends, which needs n_a >= 5; 0 = periodic */
+  double wall_velocity[3][2][3]; /* [axis][0 low wall, 1 high wall][component]; the
+                            component along the axis must be 0; ignored for open axes */
 } lbm_params;
 
 /* Bytes of device workspace lbm_create needs for these parameters. */
@@ -106,8 +119,9 @@ int lbm_create(const lbm_params* prm, void* d_workspace, size_t bytes,
  * (0, max_radius]; mass, inertia > 0, or +INFINITY for a kinematic particle
  * whose velocity is imposed (forces are still reported).  The particle record
  * is that of section 2.2 (x_p, r_p, m_p, I_p, u_p, omega_p).  Rejects overlap
- * with any particle (centre distance < r_i + r_j, minimum image).  Host
- * arrays are read before the call returns. */
+ * with any particle (centre distance < r_i + r_j, minimum image) or with a
+ * wall (x - r < 1 or x + r > n - 2 along a closed axis) as LBM_EOVERLAP.
+ * Host arrays are read before the call returns. */
 int lbm_add_particles(lbm_ctx* ctx, int32_t n, const double* x, const double* u,
                       const double* omega, const double* radius,
                       const double* mass, const double* inertia,
@@ -141,7 +155,8 @@ int lbm_get_distributions(lbm_ctx* ctx, double* f);
  * Rounded to the storage precision.  Synchronises. */
 int lbm_set_distributions(lbm_ctx* ctx, const double* f);
 
-/* Site kind of the current map: 0 none, 1 BS, 2 IS (int8 [N]). Synchronises. */
+/* Site kind of the current particle map: 0 none (wall sites included), 1 BS,
+ * 2 IS (int8 [N]).  Synchronises. */
 int lbm_site_kind(lbm_ctx* ctx, int8_t* kind);
 
 /* Integer shift k = [x - x0] of every particle, int32 [n][3]. Synchronises. */

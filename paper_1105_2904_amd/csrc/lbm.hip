@@ -140,7 +140,14 @@ __device__ __forceinline__ T pop_enc(int i, double v) {
 struct Geo {
   int nx, ny, nz;
   int64_t N;
+  int walls;  // bit a: axis a closed by wall layers 0, 1, n-2, n-1
 };
+
+// A site of the wall layers of a closed axis (particles never own these).
+__device__ __forceinline__ bool wall_site(const Geo& G, int x, int y, int z) {
+  return ((G.walls & 1) && (x < 2 || x >= G.nx - 2)) || ((G.walls & 2) && (y < 2 || y >= G.ny - 2)) ||
+         ((G.walls & 4) && (z < 2 || z >= G.nz - 2));
+}
 
 struct DevParticles {
   double *x, *x0, *u, *om, *phi, *fext, *dP, *dL, *F, *T;  // [n][3]
@@ -240,7 +247,37 @@ struct SweepArgs {
   C omega;   // 1 / tau
   C rho0;
   C fbt[Q];  // 3 w_i c_i . f_b
+  int walls;           // bit a: axis a closed by wall layers
+  C wu[3][2][3];       // wall velocity [axis][low, high][component]
 };
+
+// Velocity of the wall whose layers hold (x, y, z), the lowest closed axis
+// deciding at edges; false for a fluid site.  Selects, not indexing, so the
+// kernel-argument array stays in scalar registers.
+template <int Q, typename C>
+__device__ __forceinline__ bool wall_velocity(const SweepArgs<Q, C>& a, int x, int y, int z, C& vx, C& vy,
+                                              C& vz) {
+  int ax, hi;
+  if ((a.walls & 1) && (x < 2 || x >= a.nx - 2)) {
+    ax = 0;
+    hi = x >= a.nx - 2;
+  } else if ((a.walls & 2) && (y < 2 || y >= a.ny - 2)) {
+    ax = 1;
+    hi = y >= a.ny - 2;
+  } else if ((a.walls & 4) && (z < 2 || z >= a.nz - 2)) {
+    ax = 2;
+    hi = z >= a.nz - 2;
+  } else {
+    return false;
+  }
+  vx = ax == 0 ? (hi ? a.wu[0][1][0] : a.wu[0][0][0]) : ax == 1 ? (hi ? a.wu[1][1][0] : a.wu[1][0][0])
+                                                               : (hi ? a.wu[2][1][0] : a.wu[2][0][0]);
+  vy = ax == 0 ? (hi ? a.wu[0][1][1] : a.wu[0][0][1]) : ax == 1 ? (hi ? a.wu[1][1][1] : a.wu[1][0][1])
+                                                               : (hi ? a.wu[2][1][1] : a.wu[2][0][1]);
+  vz = ax == 0 ? (hi ? a.wu[0][1][2] : a.wu[0][0][2]) : ax == 1 ? (hi ? a.wu[1][1][2] : a.wu[1][0][2])
+                                                               : (hi ? a.wu[2][1][2] : a.wu[2][0][2]);
+  return true;
+}
 
 template <int Q, typename T, bool PART>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, T* __restrict__ B,
@@ -329,6 +366,19 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, 
       for (int i = 0; i < Q; i++) {
         const C cu = C(L::cx(i)) * vx + C(L::cy(i)) * vy + C(L::cz(i)) * vz;
         g[i] = C(L::w(i)) * (drB + rhoB * (C(3) * cu + C(4.5) * cu * cu - usqB));
+      }
+    }
+  }
+  if (a.walls) {
+    // wall layers: f^eq(rho, U_wall) with the site's own density (no
+    // particle owns a wall site, so no BS exchange above touched it)
+    C vx, vy, vz;
+    if (wall_velocity(a, x, y, z, vx, vy, vz)) {
+      const C usqW = C(1.5) * (vx * vx + vy * vy + vz * vz);
+#pragma unroll
+      for (int i = 0; i < Q; i++) {
+        const C cu = C(L::cx(i)) * vx + C(L::cy(i)) * vy + C(L::cz(i)) * vz;
+        g[i] = C(L::w(i)) * (drho + rho * (C(3) * cu + C(4.5) * cu * cu - usqW));
       }
     }
   }
@@ -450,6 +500,15 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int np, int di
   __syncthreads();
   const int L[3] = {G.nx, G.ny, G.nz};
   for (int p = tid; p < np; p += NT) {
+    if (G.walls && !isinf(P.m[p])) {
+      // contact with a wall after the pairs: the normal velocity reverses
+      // when the predicted surface reaches the BS layer while approaching
+      for (int a = 0; a < dim; a++) {
+        if (!(G.walls & (1 << a))) continue;
+        const double u = P.u[3 * p + a], xp = P.x[3 * p + a] + u, r = P.rad[p];
+        if ((xp - r <= 1.0 && u < 0.0) || (xp + r >= (double)(L[a] - 2) && u > 0.0)) P.u[3 * p + a] = -u;
+      }
+    }
     int moved = 0;
     for (int a = 0; a < dim; a++) {
       const double x = P.x[3 * p + a] + P.u[3 * p + a];
@@ -598,10 +657,13 @@ __global__ __launch_bounds__(256) void k_stamp(int* __restrict__ own, int* __res
   const int e = e_begin + blockIdx.x * 256 + threadIdx.x;
   if (e >= e_end) return;
   const int pk = E.off[e];
-  const int s = entry_site(P, G, E.pid[e], pk);
+  int x, y, z;
+  entry_xyz(P, G, E.pid[e], pk, x, y, z);
+  const int s = x + G.nx * (y + G.ny * z);
   ball[s] = e;
   const int kind = entry_kind(pk);
-  if (kind != 3) atomicMin(&own[s], 2 * e + (kind == 2));
+  // wall sites belong to the wall
+  if (kind != 3 && !wall_site(G, x, y, z)) atomicMin(&own[s], 2 * e + (kind == 2));
 }
 
 // ---------------------------------------------------------------------------
@@ -985,6 +1047,17 @@ int check_params(const lbm_params* p) {
   if (std::max<int64_t>(p->max_particles, 1) * entries_per_particle(dim, p->max_radius) > kMaxEntries)
     return LBM_ECAPACITY;
   if (p->storage < LBM_FP64 || p->storage > LBM_BF16) return LBM_EINVAL;
+  if (p->walls < 0 || p->walls >= (1 << dim)) return LBM_EINVAL;
+  const int n[3] = {p->nx, p->ny, p->nz};
+  for (int a = 0; a < dim; a++) {
+    if (!((p->walls >> a) & 1)) continue;
+    if (n[a] < 5) return LBM_EINVAL;
+    for (int hi = 0; hi < 2; hi++) {
+      for (int k = 0; k < 3; k++)
+        if (!std::isfinite(p->wall_velocity[a][hi][k])) return LBM_ENONFINITE;
+      if (p->wall_velocity[a][hi][a] != 0.0) return LBM_EINVAL;  // walls slide tangentially
+    }
+  }
   return LBM_OK;
 }
 
@@ -1075,6 +1148,10 @@ int launch_step(lbm_ctx* c) {
   a.N = c->G.N;
   a.omega = (C)(1.0 / c->prm.tau);
   a.rho0 = (C)c->prm.rho0;
+  a.walls = c->prm.walls;
+  for (int ax = 0; ax < 3; ax++)
+    for (int hi = 0; hi < 2; hi++)
+      for (int k = 0; k < 3; k++) a.wu[ax][hi][k] = (C)((c->prm.walls >> ax) & 1 ? c->prm.wall_velocity[ax][hi][k] : 0.0);
   for (int i = 0; i < Q; i++) {
     const double cf = Lt::cx(i) * c->fb[0] + Lt::cy(i) * c->fb[1] + Lt::cz(i) * c->fb[2];
     a.fbt[i] = (C)(3.0 * Lt::w(i) * cf);
@@ -1260,7 +1337,7 @@ int lbm_create(const lbm_params* prm, void* d_workspace, size_t bytes, void* hip
   c->prm = *prm;
   c->q = prm->lattice;
   c->dim = prm->lattice == LBM_D2Q9 ? 2 : 3;
-  c->G = Geo{prm->nx, prm->ny, prm->nz, (int64_t)prm->nx * prm->ny * prm->nz};
+  c->G = Geo{prm->nx, prm->ny, prm->nz, (int64_t)prm->nx * prm->ny * prm->nz, prm->walls};
   c->stream = (hipStream_t)hip_stream;
   c->ws = (char*)d_workspace;
   c->L = L;
@@ -1345,6 +1422,9 @@ int lbm_add_particles(lbm_ctx* c, int32_t n, const double* x, const double* u, c
     if (!(mass[j] > 0) || !(inertia[j] > 0)) return LBM_EINVAL;
     for (int a = 0; a < dim; a++)
       if (2 * (int)std::ceil(r) + 3 > box[a]) return LBM_EINVAL;
+    for (int a = 0; a < dim; a++)
+      if (((c->prm.walls >> a) & 1) && (x[3 * j + a] - r < 1.0 || x[3 * j + a] + r > box[a] - 2.0))
+        return LBM_EOVERLAP;
   }
   // positions of the particles already in the box
   std::vector<double> cur((size_t)3 * c->np);

@@ -32,7 +32,8 @@ class lbm_params(ctypes.Structure):
                 ("nz", ctypes.c_int32), ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("gravity", ctypes.c_double * 3), ("body_force", ctypes.c_double * 3),
                 ("zero_net_force", ctypes.c_int32), ("storage", ctypes.c_int32),
-                ("max_particles", ctypes.c_int32), ("max_radius", ctypes.c_double)]
+                ("max_particles", ctypes.c_int32), ("max_radius", ctypes.c_double),
+                ("walls", ctypes.c_int32), ("wall_velocity", ctypes.c_double * 18)]
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -91,7 +92,8 @@ def _d(a):
 
 
 def make_params(lattice, nx, ny, nz=1, tau=1.0, rho0=1.0, gravity=(0, 0, 0), body_force=(0, 0, 0),
-                zero_net_force=False, storage="fp32", max_particles=0, max_radius=1.0):
+                zero_net_force=False, storage="fp32", max_particles=0, max_radius=1.0, walls=0,
+                wall_velocity=None):
     p = lbm_params()
     p.lattice, p.nx, p.ny, p.nz = int(lattice), int(nx), int(ny), int(nz)
     p.tau, p.rho0 = float(tau), float(rho0)
@@ -102,6 +104,11 @@ def make_params(lattice, nx, ny, nz=1, tau=1.0, rho0=1.0, gravity=(0, 0, 0), bod
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     p.max_particles = int(max_particles)
     p.max_radius = float(max_radius)
+    p.walls = int(walls)
+    if wall_velocity is not None:
+        wu = np.asarray(wall_velocity, dtype=np.float64).reshape(18)
+        for k in range(18):
+            p.wall_velocity[k] = float(wu[k])
     return p
 
 
@@ -144,10 +151,11 @@ class Simulation:
 
     def __init__(self, lattice, nx, ny, nz=1, tau=1.0, rho0=1.0, gravity=(0, 0, 0),
                  body_force=(0, 0, 0), zero_net_force=False, storage="fp32", max_particles=0,
-                 max_radius=1.0, device="cuda", stream=None):
+                 max_radius=1.0, walls=0, wall_velocity=None, device="cuda", stream=None):
         import torch
         self.params = make_params(lattice, nx, ny, nz, tau, rho0, gravity, body_force,
-                                  zero_net_force, storage, max_particles, max_radius)
+                                  zero_net_force, storage, max_particles, max_radius, walls,
+                                  wall_velocity)
         self.q, self.nx, self.ny, self.nz = int(lattice), int(nx), int(ny), int(nz)
         self.N = self.nx * self.ny * self.nz
         self.nbytes = lbm_workspace_size(self.params)

@@ -53,6 +53,11 @@ def _rc_workspace(**kw):
     (dict(max_radius=0.0), lbm.LBM_EINVAL),
     (dict(max_radius=200.0), lbm.LBM_EINVAL),
     (dict(gravity=(0, 0, math.inf)), lbm.LBM_ENONFINITE),
+    (dict(walls=8), lbm.LBM_EINVAL),
+    (dict(lattice=9, nz=1, walls=4), lbm.LBM_EINVAL),   # no z walls in 2D
+    (dict(ny=4, walls=2), lbm.LBM_EINVAL),               # no fluid layer left
+    (dict(walls=2, wall_velocity=[0] * 7 + [0.01] + [0] * 10), lbm.LBM_EINVAL),  # normal wall velocity
+    (dict(walls=2, wall_velocity=[0] * 6 + [math.nan] + [0] * 11), lbm.LBM_ENONFINITE),
 ])
 def test_invalid_parameters_rejected_on_host(kw, code):
     rc, _ = _rc_workspace(**kw)

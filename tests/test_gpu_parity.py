@@ -38,12 +38,14 @@ def _say(*a):
 
 
 def make_pair(q, box, tau, storage, particles=None, gravity=(0, 0, 0), body_force=(0, 0, 0),
-              znf=False, f0=None, max_particles=None, max_radius=None):
+              znf=False, f0=None, max_particles=None, max_radius=None, walls=0, wall_velocity=None):
     n = 0 if particles is None else len(particles["radius"])
     rmax = max_radius or (float(np.max(particles["radius"])) if n else 1.0)
     sim = lbm.Simulation(q, *box, tau=tau, gravity=gravity, body_force=body_force, zero_net_force=znf,
-                         storage=storage, max_particles=max_particles or n, max_radius=rmax)
-    ora = oracle.Oracle(q, *box, tau, gravity=gravity, body_force=body_force, zero_net_force=znf)
+                         storage=storage, max_particles=max_particles or n, max_radius=rmax, walls=walls,
+                         wall_velocity=wall_velocity)
+    ora = oracle.Oracle(q, *box, tau, gravity=gravity, body_force=body_force, zero_net_force=znf,
+                        walls=walls, wall_velocity=wall_velocity)
     if f0 is not None:
         sim.set_distributions(f0)
         ora.set_f(f0)
@@ -324,6 +326,94 @@ def test_argument_errors():
     assert e.value.code == lbm.LBM_EOVERLAP
     sim.step(3)
     sim.forces()
+
+
+def _closed_box(q):
+    """Heavy particles settling in a box closed along two axes, one wall
+    sliding; one particle is launched at the bottom wall so that a
+    particle-wall contact happens early."""
+    if q == 9:
+        box, walls = (96, 80, 1), 0b011
+        wu = np.zeros((3, 2, 3))
+        wu[1, 1, 0] = 0.02  # top wall slides along x
+        p = wl.suspension(9, (90, 60, 1), 5, 5.0, 1.5, seed=41)
+        p["x"][:, 0] += 3.0
+        p["x"][:, 1] += 12.0
+        g = (0.0, -2e-4, 0.0)
+        extra = [[48.0, 1.0 + 5.0 + 0.25, 0.0]]
+    else:
+        box, walls = (40, 36, 44), 0b101
+        wu = np.zeros((3, 2, 3))
+        wu[2, 1, 0], wu[2, 1, 1] = 0.01, 0.005  # top wall slides in its plane
+        p = wl.suspension(19, (34, 36, 30), 3, 4.0, 1.5, seed=42)
+        p["x"][:, 0] += 3.0
+        p["x"][:, 2] += 9.0
+        g = (0.0, 0.0, -2e-4)
+        extra = [[20.0, 18.0, 1.0 + 4.0 + 0.25]]
+    r = float(p["radius"][0])
+    V = np.pi * r * r if q == 9 else 4.0 / 3.0 * np.pi * r ** 3
+    m = 1.5 * V
+    parts = {"x": np.vstack([p["x"], extra]), "radius": np.append(p["radius"], r),
+             "mass": np.append(p["mass"], m), "inertia": np.append(p["inertia"], p["inertia"][0]),
+             "u": np.vstack([np.zeros_like(p["x"]), [[0.0, -0.08, 0.0] if q == 9 else [0.0, 0.0, -0.08]]])}
+    return box, walls, wu, parts, g
+
+
+@pytest.mark.parametrize("q", [9, 19])
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_closed_box_with_walls(q, storage):
+    box, walls, wu, parts, g = _closed_box(q)
+    sim, ora = make_pair(q, box, 0.7, storage, particles=parts, gravity=g, walls=walls, wall_velocity=wu)
+    tf, tF = TOL[storage]
+    steps, chunk = (120, 30) if q == 9 else (60, 20)
+    _say("closed box", q, storage, box, "walls", walls)
+    axis = 1 if q == 9 else 2
+    bounced = False
+    for t in range(0, steps, chunk):
+        sim.step(chunk)
+        ora.step(chunk)
+        eF, eT = compare_particles(sim, ora, tF, "step %d" % (t + chunk))
+        e = err_f(sim, ora)
+        _say("  step", t + chunk, "e_f", e, "e_F", eF, "e_T", eT)
+        assert e <= tf
+        assert np.array_equal(sim.site_kind(), ora.site_kind())
+        bounced |= ora.forces()[3][-1, axis] > 0
+    assert bounced  # the launched particle came back off the wall
+    rg, ug, og = sim.fields()
+    ro, uo, oo = ora.fields()
+    assert np.array_equal(og, oo)
+    assert np.abs(ug - uo).max() <= 10 * tf
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_poiseuille_closed_form_on_gpu(q):
+    """The GPU's steady channel flow at tau = 1 equals the closed form of the
+    discrete steady state: u(y) = A - 3 f (y - c)^2, A = 5 f + 3 f [2 (2 - c)^2
+    - (3 - c)^2], c the channel centre (derived in the oracle's wall pins)."""
+    n, f = 20, 1e-6
+    axis = 1 if q == 9 else 2
+    box = (3, n, 1) if q == 9 else (3, 3, n)
+    sim = lbm.Simulation(q, *box, tau=1.0, body_force=(f, 0, 0), storage="fp64", walls=1 << axis)
+    sim.step(6000)
+    _, u, _ = sim.fields()
+    prof = u[0, :, 1, 0] if q == 9 else u[:, 1, 1, 0]
+    y = np.arange(n, dtype=np.float64)
+    c = (n - 1) / 2.0
+    exact = 5 * f + 3 * f * (2 * (2 - c) ** 2 - (3 - c) ** 2) - 3 * f * (y - c) ** 2
+    err = np.abs(prof[2:n - 2] - exact[2:n - 2]).max() / exact.max()
+    _say("poiseuille", q, "rel err", err)
+    assert err < 1e-10
+
+
+def test_particle_overlapping_wall_rejected():
+    sim = lbm.Simulation(9, 40, 30, tau=0.8, storage="fp64", max_particles=2, max_radius=4.0, walls=2)
+    with pytest.raises(lbm.LbmError) as e:
+        sim.add_particles([[20, 4.5, 0]], radius=4.0, mass=10.0, inertia=10.0)
+    assert e.value.code == lbm.LBM_EOVERLAP
+    with pytest.raises(lbm.LbmError) as e:
+        sim.add_particles([[20, 24.5, 0]], radius=4.0, mass=10.0, inertia=10.0)
+    assert e.value.code == lbm.LBM_EOVERLAP
+    assert sim.add_particles([[20, 5.0, 0]], radius=4.0, mass=10.0, inertia=10.0) == 0
 
 
 def test_runs_are_bitwise_deterministic():
