@@ -172,6 +172,55 @@ int lbm_particle_info(lbm_ctx* ctx, int32_t p, int32_t* nbs, int32_t* nis);
 int lbm_set_profiling(lbm_ctx* ctx, int32_t on);
 int lbm_profile(lbm_ctx* ctx, double* sweep_ms, int64_t* sweeps);
 
+/* ---- ensembles of independent boxes ------------------------------------
+ * nbox boxes of sizes dims[b][0..2] (dims is int32 [nbox][3]) that share the
+ * lattice, tau, rho0, gravity, body force, walls and storage of prm (whose
+ * nx, ny, nz are ignored) step together: one launch of each kernel covers
+ * every box, so a step of 64 small boxes costs what a step of one box of
+ * their total size does.  Each box is an independent copy of the problem of
+ * section 2: its own periodic (or walled) lattice, particles and zero-net-force
+ * frame.  Sites of all boxes are numbered box after box (box b starts at the
+ * first_site lbm_box_info reports, x fastest inside a box), so lbm_fields,
+ * lbm_site_kind and the distribution calls cover NT = sum of the box sizes
+ * sites; particle ids run over all boxes.  max_particles counts all boxes. */
+int lbm_ensemble_workspace_size(const lbm_params* prm, int32_t nbox, const int32_t* dims, size_t* bytes);
+int lbm_ensemble_create(const lbm_params* prm, int32_t nbox, const int32_t* dims, void* d_workspace,
+                        size_t bytes, void* hip_stream, lbm_ctx** out);
+
+/* Append n particles to box `box` (coordinates local to the box).  Boxes are
+ * filled in order: box must be >= the box of the last particle added
+ * (LBM_EINVAL otherwise), so that every box holds consecutive ids.
+ * lbm_add_particles adds to box 0. */
+int lbm_ensemble_add_particles(lbm_ctx* ctx, int32_t box, int32_t n, const double* x, const double* u,
+                               const double* omega, const double* radius, const double* mass,
+                               const double* inertia, int32_t* first_id);
+
+/* Size (int32 [3]), first site, first particle id and particle count of a box.
+ * Any pointer may be NULL. */
+int lbm_box_info(lbm_ctx* ctx, int32_t box, int32_t* dims, int64_t* first_site, int32_t* first_particle,
+                 int32_t* n_particles);
+
+/* ---- launch shape, autotuning and step graphs ---------------------------
+ * The sweep runs either as the one-box row kernel (width 0; one box only) or
+ * as a persistent kernel over tiles of `width` sites of one row (64, 128, 256
+ * or 512) with `grid` workgroups (0: one per tile).  Every shape computes the
+ * same values bit for bit. */
+int lbm_set_sweep_config(lbm_ctx* ctx, int32_t width, int32_t grid);
+int lbm_get_sweep_config(lbm_ctx* ctx, int32_t* width, int32_t* grid);
+
+/* Time every sweep shape (reps launches each, after one warm-up) on the
+ * context's own state and keep the fastest; returns it and its time per
+ * sweep in ms.  Sweeping again from the same state recomputes the same
+ * values, so the simulation is unchanged.  Synchronises. */
+int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* width, int32_t* grid, double* best_ms);
+
+/* steps_per_graph > 0 (even): lbm_step replays a HIP graph of that many
+ * steps, captured on the first use and again after the particle set, the
+ * buffer parity or the sweep shape changed, and launches the remainder one by
+ * one; 0 (default) launches every kernel.  Profiling covers eager sweeps only.
+ * Synchronises. */
+int lbm_set_graph(lbm_ctx* ctx, int32_t steps_per_graph);
+
 /* Algorithmic HBM bytes one sweep moves per site (2 q sizeof(storage)). */
 int lbm_bytes_per_site(const lbm_params* prm, int64_t* bytes);
 

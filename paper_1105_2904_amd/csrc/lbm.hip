@@ -53,6 +53,7 @@ constexpr int64_t kMaxEntries = (int64_t)1 << 29;  // owner map stores 2e + 1 < 
 constexpr int kCandMax = 64;        // close neighbours listed per particle
 constexpr double kMargin = 1.0;     // candidate search margin (lattice units)
 constexpr int kSweepBlock = 256;
+constexpr int kTileMax = 512;        // widest tile of the ensemble sweep
 constexpr int kBoundaryBlock = 256;  // reduce workgroup
 constexpr int kParticleBlock = 1024;
 constexpr int kStatusCollision = 1;
@@ -137,10 +138,26 @@ __device__ __forceinline__ T pop_enc(int i, double v) {
     return (T)x;
 }
 
+// One box of the context: its size, walls, first site in the site arrays
+// (boxes of an ensemble are stored one after the other) and one past the id
+// of its last particle (the particles of a box have consecutive ids).
 struct Geo {
   int nx, ny, nz;
   int64_t N;
   int walls;  // bit a: axis a closed by wall layers 0, 1, n-2, n-1
+  int64_t off;
+  int p1;
+};
+
+struct DevParticles;
+
+// Geometry of every box: the box itself when there is one (kernel argument,
+// no load), a device table indexed by the particle's box otherwise.
+struct Boxes {
+  Geo g0;
+  const Geo* tab;
+  int nbox;
+  int64_t NT;  // sites of all boxes: the stride of a population plane
 };
 
 // A site of the wall layers of a closed axis (particles never own these).
@@ -153,10 +170,14 @@ struct DevParticles {
   double *x, *x0, *u, *om, *phi, *fext, *dP, *dL, *F, *T;  // [n][3]
   double *m, *I, *rad;                                     // [n]
   int *b0, *k, *org;                                       // [n][3]; org = b0 + k wrapped into the box
-  int *ent0, *nbs, *nis, *nin, *cand_n, *jump;             // [n]
+  int *ent0, *nbs, *nis, *nin, *cand_n, *jump, *box;       // [n]
   int *cand;                                               // [n][kCandMax]
   int *pairs;                                              // [n*kCandMax][2]
 };
+
+__device__ __forceinline__ Geo geo_of(const Boxes& B, const DevParticles& P, int p) {
+  return B.nbox == 1 ? B.g0 : B.tab[P.box[p]];
+}
 
 struct DevEntries {
   int* off;  // packed int8 offsets x,y,z and kind (1 BS, 2 IS, 3 interior) in the top byte
@@ -188,10 +209,14 @@ __device__ __forceinline__ void entry_xyz(const DevParticles& P, const Geo& G, i
   z = wrap1(P.org[3 * p + 2] + off_z(pk), G.nz);
 }
 
+__device__ __forceinline__ int site_of(const Geo& G, int x, int y, int z) {
+  return (int)G.off + x + G.nx * (y + G.ny * z);
+}
+
 __device__ __forceinline__ int entry_site(const DevParticles& P, const Geo& G, int p, int pk) {
   int x, y, z;
   entry_xyz(P, G, p, pk, x, y, z);
-  return x + G.nx * (y + G.ny * z);
+  return site_of(G, x, y, z);
 }
 
 // ---------------------------------------------------------------------------
@@ -255,18 +280,18 @@ struct SweepArgs {
 // deciding at edges; false for a fluid site.  Selects, not indexing, so the
 // kernel-argument array stays in scalar registers.
 template <int Q, typename C>
-__device__ __forceinline__ bool wall_velocity(const SweepArgs<Q, C>& a, int x, int y, int z, C& vx, C& vy,
-                                              C& vz) {
+__device__ __forceinline__ bool wall_velocity(const SweepArgs<Q, C>& a, int x, int y, int z, int nx, int ny,
+                                              int nz, C& vx, C& vy, C& vz) {
   int ax, hi;
-  if ((a.walls & 1) && (x < 2 || x >= a.nx - 2)) {
+  if ((a.walls & 1) && (x < 2 || x >= nx - 2)) {
     ax = 0;
-    hi = x >= a.nx - 2;
-  } else if ((a.walls & 2) && (y < 2 || y >= a.ny - 2)) {
+    hi = x >= nx - 2;
+  } else if ((a.walls & 2) && (y < 2 || y >= ny - 2)) {
     ax = 1;
-    hi = y >= a.ny - 2;
-  } else if ((a.walls & 4) && (z < 2 || z >= a.nz - 2)) {
+    hi = y >= ny - 2;
+  } else if ((a.walls & 4) && (z < 2 || z >= nz - 2)) {
     ax = 2;
-    hi = z >= a.nz - 2;
+    hi = z >= nz - 2;
   } else {
     return false;
   }
@@ -279,21 +304,19 @@ __device__ __forceinline__ bool wall_velocity(const SweepArgs<Q, C>& a, int x, i
   return true;
 }
 
+// The work of one site (x, y, z) of a box of nx x ny x nz sites whose first
+// site is `off`; fbt holds 3 w_i c_i . f_b of that box.
 template <int Q, typename T, bool PART>
-__global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, T* __restrict__ B,
-                                                        SweepArgs<Q, typename Store<T>::C> a, SiteArgs<T> sa) {
+__device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restrict__ B,
+                                           const SweepArgs<Q, typename Store<T>::C>& a, const SiteArgs<T>& sa,
+                                           int x, int y, int z, int nx, int ny, int nz, int off,
+                                           const typename Store<T>::C (&fbt)[Q]) {
   using L = Lattice<Q>;
   using C = typename Store<T>::C;
-  const int blk = blockIdx.x;
-  const int row = blk / a.nxb;
-  const int x = (blk - row * a.nxb) * kSweepBlock + threadIdx.x;
-  if (x >= a.nx) return;
-  const int y = row % a.ny;
-  const int z = row / a.ny;
-  const int xm = x == 0 ? a.nx - 1 : x - 1, xp = x == a.nx - 1 ? 0 : x + 1;
-  const int ym = y == 0 ? a.ny - 1 : y - 1, yp = y == a.ny - 1 ? 0 : y + 1;
-  const int zm = z == 0 ? a.nz - 1 : z - 1, zp = z == a.nz - 1 ? 0 : z + 1;
-  const int s = x + a.nx * (y + a.ny * z);
+  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+  const int s = off + x + nx * (y + ny * z);
 
   // ball sites first: their record is needed before the collision
   const int b = PART ? sa.ball[s] : kEmpty;
@@ -306,7 +329,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, 
     const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
     const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
     const int sz = L::cz(i) > 0 ? zm : (L::cz(i) < 0 ? zp : z);
-    g[i] = pop_ld<Q, T>(A + (size_t)i * a.N + (sx + a.nx * (sy + a.ny * sz)), i);
+    g[i] = pop_ld<Q, T>(A + (size_t)i * a.N + (off + sx + nx * (sy + ny * sz)), i);
   }
   const int bs = h.y;
   if (PART && h.x) {
@@ -336,7 +359,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, 
   for (int i = 0; i < Q; i++) {
     const C cu = C(L::cx(i)) * ux + C(L::cy(i)) * uy + C(L::cz(i)) * uz;
     const C geq = C(L::w(i)) * (drho + rho * (C(3) * cu + C(4.5) * cu * cu - usq));
-    g[i] = g[i] + a.omega * (geq - g[i]) + a.fbt[i];
+    g[i] = g[i] + a.omega * (geq - g[i]) + fbt[i];
   }
   if (PART && b != kEmpty) {
     sa.drho[s] = drho;
@@ -373,7 +396,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, 
     // wall layers: f^eq(rho, U_wall) with the site's own density (no
     // particle owns a wall site, so no BS exchange above touched it)
     C vx, vy, vz;
-    if (wall_velocity(a, x, y, z, vx, vy, vz)) {
+    if (wall_velocity(a, x, y, z, nx, ny, nz, vx, vy, vz)) {
       const C usqW = C(1.5) * (vx * vx + vy * vy + vz * vz);
 #pragma unroll
       for (int i = 0; i < Q; i++) {
@@ -384,6 +407,38 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, 
   }
 #pragma unroll
   for (int i = 0; i < Q; i++) pop_st<Q, T>(B + (size_t)i * a.N + s, i, g[i]);
+}
+
+// One box: workgroup b covers kSweepBlock sites of row b / nxb.
+template <int Q, typename T, bool PART>
+__global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, T* __restrict__ B,
+                                                        SweepArgs<Q, typename Store<T>::C> a, SiteArgs<T> sa) {
+  const int blk = blockIdx.x;
+  const int row = blk / a.nxb;
+  const int x = (blk - row * a.nxb) * kSweepBlock + threadIdx.x;
+  if (x >= a.nx) return;
+  sweep_site<Q, T, PART>(A, B, a, sa, x, row % a.ny, row / a.ny, a.nx, a.ny, a.nz, 0, a.fbt);
+}
+
+// Any number of boxes: a tile is a run of blockDim.x sites of one row of
+// one box, {box, y, z, x0}; a persistent grid walks the tile list (the
+// workgroup width and grid size are the tunable launch shape).
+template <int Q, typename T, bool PART>
+__global__ __launch_bounds__(kTileMax) void k_sweep_tiles(const T* __restrict__ A, T* __restrict__ B,
+                                                           SweepArgs<Q, typename Store<T>::C> a, SiteArgs<T> sa,
+                                                           const Geo* __restrict__ tab, const int4* __restrict__ tiles,
+                                                           int ntiles, const typename Store<T>::C* __restrict__ fbt_tab) {
+  using C = typename Store<T>::C;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int4 tl = tiles[t];
+    const Geo g = tab[tl.x];
+    const int x = tl.w + (int)threadIdx.x;
+    if (x >= g.nx) continue;
+    C fb[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) fb[i] = fbt_tab[tl.x * Q + i];
+    sweep_site<Q, T, PART>(A, B, a, sa, x, tl.y, tl.z, g.nx, g.ny, g.nz, (int)g.off, fb);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -399,7 +454,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // K3: particle update, one workgroup (eq. 10-11, 16-19, 13).
 // ---------------------------------------------------------------------------
 template <int NT>
-__global__ __launch_bounds__(NT) void k_particles(DevParticles P, int np, int dim, Geo G, int* status) {
+__global__ __launch_bounds__(NT) void k_particles(DevParticles P, int np, int dim, Boxes BX, int* status) {
   __shared__ int s_scan[NT];
   __shared__ double s_vmax[NT / 64];
   const int tid = threadIdx.x;
@@ -450,9 +505,10 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int np, int di
   if (tid == 0) {
     double vseen = 0;
     for (int w = 0; w < NT / 64; w++) vseen = fmax(vseen, s_vmax[w]);
-    const int L[3] = {G.nx, G.ny, G.nz};
     for (int t = 0; t < total; t++) {
       const int i = P.pairs[2 * t], j = P.pairs[2 * t + 1];
+      const Geo G = geo_of(BX, P, i);  // pairs never cross boxes
+      const int L[3] = {G.nx, G.ny, G.nz};
       const bool infA = isinf(P.m[i]), infB = isinf(P.m[j]);
       if (infA && infB) continue;
       double d[3], dd = 0;
@@ -498,8 +554,9 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int np, int di
     if (2.0 * vseen >= kMargin) atomicOr(status, kStatusCollision);
   }
   __syncthreads();
-  const int L[3] = {G.nx, G.ny, G.nz};
   for (int p = tid; p < np; p += NT) {
+    const Geo G = geo_of(BX, P, p);
+    const int L[3] = {G.nx, G.ny, G.nz};
     if (G.walls && !isinf(P.m[p])) {
       // contact with a wall after the pairs: the normal velocity reverses
       // when the predicted surface reaches the BS layer while approaching
@@ -531,14 +588,15 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int np, int di
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own, int* __restrict__ ball,
                                                             const double* __restrict__ slot,
-                                                            DevParticles P, DevEntries E, Geo G, int np,
-                                                            double rho0, int dim, int* status) {
+                                                            DevParticles P, DevEntries E, Boxes BX,
+                                                            double rho0, int* status) {
   constexpr int kWaves = kBoundaryBlock / 64;
   __shared__ double s_part[kWaves][6];
   __shared__ int s_cnt[kWaves];
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
+  const Geo G = geo_of(BX, P, p);
   const int e0 = P.ent0[p], nbs = P.nbs[p], nis = P.nis[p], nin = P.nin[p];
   const double phx = P.phi[3 * p], phy = P.phi[3 * p + 1], phz = P.phi[3 * p + 2];
   const double upx = P.u[3 * p], upy = P.u[3 * p + 1], upz = P.u[3 * p + 2];
@@ -605,11 +663,13 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
       P.dL[3 * p + tid - 3] = v;
   }
 
-  // Close neighbours j > p (positions before translation), listed in
-  // increasing j: the only pairs that can pass the collision test this step
-  // while every speed stays below kMargin / 2 (checked in the particle update).
+  // Close neighbours j > p in the same box (positions before translation),
+  // listed in increasing j: the only pairs that can pass the collision test
+  // this step while every speed stays below kMargin / 2 (checked in the
+  // particle update).
   const double xpx = P.x[3 * p], xpy = P.x[3 * p + 1], xpz = P.x[3 * p + 2];
   const double rp = P.rad[p];
+  const int np = G.p1;
   int base = 0;
   for (int j0 = p + 1; j0 < np; j0 += kBoundaryBlock) {
     const int j = j0 + tid;
@@ -653,13 +713,15 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
 // the same results).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_stamp(int* __restrict__ own, int* __restrict__ ball, DevParticles P,
-                                                DevEntries E, Geo G, int e_begin, int e_end) {
+                                                DevEntries E, Boxes BX, int e_begin, int e_end) {
   const int e = e_begin + blockIdx.x * 256 + threadIdx.x;
   if (e >= e_end) return;
   const int pk = E.off[e];
+  const int p = E.pid[e];
+  const Geo G = geo_of(BX, P, p);
   int x, y, z;
-  entry_xyz(P, G, E.pid[e], pk, x, y, z);
-  const int s = x + G.nx * (y + G.ny * z);
+  entry_xyz(P, G, p, pk, x, y, z);
+  const int s = site_of(G, x, y, z);
   ball[s] = e;
   const int kind = entry_kind(pk);
   // wall sites belong to the wall
@@ -680,15 +742,16 @@ template <int Q, typename T>
 __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own, const int* __restrict__ ball,
                                                   int2* __restrict__ hdr, typename Store<T>::C* __restrict__ vel,
                                                   T* __restrict__ sub, const typename Store<T>::C* __restrict__ drho,
-                                                  const T* __restrict__ B, DevParticles P, DevEntries E, Geo G,
+                                                  const T* __restrict__ B, DevParticles P, DevEntries E, Boxes BX,
                                                   int nent, int64_t stride, double rho0, int pending) {
   using L = Lattice<Q>;
   using C = typename Store<T>::C;
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= nent) return;
+  const Geo G = geo_of(BX, P, E.pid[e]);
   int x, y, z;
   entry_xyz(P, G, E.pid[e], E.off[e], x, y, z);
-  const int s = x + G.nx * (y + G.ny * z);
+  const int s = site_of(G, x, y, z);
   if (ball[s] != e) return;  // another entry represents this site
   unsigned mask = 0;
   if (pending) {
@@ -700,14 +763,14 @@ __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own, co
       const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
       const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
       const int sz = L::cz(i) > 0 ? zm : (L::cz(i) < 0 ? zp : z);
-      const int src = sx + G.nx * (sy + G.ny * sz);
+      const int src = site_of(G, sx, sy, sz);
       const int o = own[src];
       if (o == kEmpty || !(o & 1)) continue;  // not an owned IS site
       const int ie = o >> 1;
       double dr;
       if (P.jump[E.pid[ie]]) {
         dr = 0;
-        for (int j = 0; j < Q; j++) dr += (double)pop_ld<Q, T>(B + (size_t)j * G.N + src, j);
+        for (int j = 0; j < Q; j++) dr += (double)pop_ld<Q, T>(B + (size_t)j * BX.NT + src, j);
       } else {
         dr = (double)drho[src];
       }
@@ -740,13 +803,14 @@ template <int Q, typename T>
 __global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ own, const int* __restrict__ ball,
                                                         int2* __restrict__ hdr, typename Store<T>::C* __restrict__ vel,
                                                         T* __restrict__ sub, const typename Store<T>::C* __restrict__ drho,
-                                                        const T* __restrict__ B, DevParticles P, DevEntries E, Geo G,
+                                                        const T* __restrict__ B, DevParticles P, DevEntries E, Boxes BX,
                                                         int64_t stride, double rho0, int pending, int dim) {
   using L = Lattice<Q>;
   using C = typename Store<T>::C;
   extern __shared__ __align__(16) unsigned char smem[];
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
+  const Geo G = geo_of(BX, P, p);
   const int hw = (int)floor(P.rad[p] + 0.5) + 1;
   const int W = 2 * hw + 1, Wz = dim == 3 ? W : 1, hz = dim == 3 ? hw : 0;
   const int nW = W * W * Wz;
@@ -765,7 +829,7 @@ __global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ o
       if (idx < nW) {
         const int wx = idx % W, wy = (idx / W) % W, wz = idx / (W * W);
         const int x = wrap1(ox0 + wx - hw, G.nx), y = wrap1(oy0 + wy - hw, G.ny), z = wrap1(oz0 + wz - hz, G.nz);
-        const int site = x + G.nx * (y + G.ny * z);
+        const int site = site_of(G, x, y, z);
         vo[j] = own[site];
         vd[j] = pending ? drho[site] : C(0);
       }
@@ -797,7 +861,7 @@ __global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ o
       pkv[j] = E.off[e0 + t];
       const int x = wrap1(ox0 + off_x(pkv[j]), G.nx), y = wrap1(oy0 + off_y(pkv[j]), G.ny),
                 z = wrap1(oz0 + off_z(pkv[j]), G.nz);
-      rep[j] = ball[x + G.nx * (y + G.ny * z)];
+      rep[j] = ball[site_of(G, x, y, z)];
     }
   }
 #pragma unroll 1
@@ -822,9 +886,9 @@ __global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ o
           // an IS site of this particle: lever arm (o - c_i) - phi
           double dr;
           if (jump) {
-            const int src = wrap1(x - L::cx(i), G.nx) + G.nx * (wrap1(y - L::cy(i), G.ny) + G.ny * wrap1(z - L::cz(i), G.nz));
+            const int src = site_of(G, wrap1(x - L::cx(i), G.nx), wrap1(y - L::cy(i), G.ny), wrap1(z - L::cz(i), G.nz));
             dr = 0;
-            for (int j = 0; j < Q; j++) dr += (double)pop_ld<Q, T>(B + (size_t)j * G.N + src, j);
+            for (int j = 0; j < Q; j++) dr += (double)pop_ld<Q, T>(B + (size_t)j * BX.NT + src, j);
           } else {
             dr = (double)s_drho[wn];
           }
@@ -841,11 +905,11 @@ __global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ o
           val = (double)(C(L::w(i)) * (dc + rho * (C(3) * cu + C(4.5) * cu * cu - usq)));
         } else {
           // an IS site of another particle (balls overlap)
-          const int src = wrap1(x - L::cx(i), G.nx) + G.nx * (wrap1(y - L::cy(i), G.ny) + G.ny * wrap1(z - L::cz(i), G.nz));
+          const int src = site_of(G, wrap1(x - L::cx(i), G.nx), wrap1(y - L::cy(i), G.ny), wrap1(z - L::cz(i), G.nz));
           double dr;
           if (P.jump[E.pid[ie]]) {
             dr = 0;
-            for (int j = 0; j < Q; j++) dr += (double)pop_ld<Q, T>(B + (size_t)j * G.N + src, j);
+            for (int j = 0; j < Q; j++) dr += (double)pop_ld<Q, T>(B + (size_t)j * BX.NT + src, j);
           } else {
             dr = (double)drho[src];
           }
@@ -890,14 +954,15 @@ __global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ o
 template <int Q, typename T>
 __global__ __launch_bounds__(256) void k_materialize(T* __restrict__ S, const int* __restrict__ ball,
                                                       int2* __restrict__ hdr, const T* __restrict__ sub,
-                                                      DevParticles P, DevEntries E, Geo G, int nent, int64_t stride,
+                                                      DevParticles P, DevEntries E, Boxes BX, int nent, int64_t stride,
                                                       int write) {
   using L = Lattice<Q>;
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= nent) return;
+  const Geo G = geo_of(BX, P, E.pid[e]);
   int x, y, z;
   entry_xyz(P, G, E.pid[e], E.off[e], x, y, z);
-  const int s = x + G.nx * (y + G.ny * z);
+  const int s = site_of(G, x, y, z);
   if (ball[s] != e) return;
   int2 h = hdr[e];
   if (h.x == 0) return;
@@ -906,8 +971,8 @@ __global__ __launch_bounds__(256) void k_materialize(T* __restrict__ S, const in
 #pragma unroll
     for (int i = 0; i < Q; i++)
       if (h.x & (1 << i)) {
-        const int src = wrap1(x - L::cx(i), G.nx) + G.nx * (wrap1(y - L::cy(i), G.ny) + G.ny * wrap1(z - L::cz(i), G.nz));
-        S[(size_t)i * G.N + src] = sub[(size_t)i * stride + e];
+        const int src = site_of(G, wrap1(x - L::cx(i), G.nx), wrap1(y - L::cy(i), G.ny), wrap1(z - L::cz(i), G.nz));
+        S[(size_t)i * BX.NT + src] = sub[(size_t)i * stride + e];
       }
   }
   h.x = 0;
@@ -917,9 +982,11 @@ __global__ __launch_bounds__(256) void k_materialize(T* __restrict__ S, const in
 // ---------------------------------------------------------------------------
 // Read-out and set-up kernels (off the step loop).
 // ---------------------------------------------------------------------------
+// Moments of sites s0 .. s0 + cnt - 1 of box G (box-local indices); NT is
+// the stride of a population plane.
 template <int Q, typename T>
 __global__ void k_moments(const T* __restrict__ A, double* __restrict__ rho, double* __restrict__ u,
-                          Geo G, double rho0, int64_t s0, int64_t cnt) {
+                          Geo G, int64_t NT, double rho0, int64_t s0, int64_t cnt) {
   using L = Lattice<Q>;
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= cnt) return;
@@ -929,7 +996,7 @@ __global__ void k_moments(const T* __restrict__ A, double* __restrict__ rho, dou
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     const int sx = wrap(x - L::cx(i), G.nx), sy = wrap(y - L::cy(i), G.ny), sz = wrap(z - L::cz(i), G.nz);
-    const double g = (double)pop_ld<Q, T>(A + (size_t)i * G.N + sx + (int64_t)G.nx * (sy + (int64_t)G.ny * sz), i);
+    const double g = (double)pop_ld<Q, T>(A + (size_t)i * NT + site_of(G, sx, sy, sz), i);
     drho += g;
     j[0] += L::cx(i) * g;
     j[1] += L::cy(i) * g;
@@ -940,10 +1007,10 @@ __global__ void k_moments(const T* __restrict__ A, double* __restrict__ rho, dou
   for (int a = 0; a < 3; a++) u[3 * idx + a] = j[a] / r;
 }
 
-// B_i(s) = A_i(s - dir * c_i): dir = +1 pulls (state -> post-stream f),
-// dir = -1 pushes (post-stream f -> state).
+// B_i(s) = A_i(s - dir * c_i) over the sites of box G: dir = +1 pulls
+// (state -> post-stream f), dir = -1 pushes (post-stream f -> state).
 template <int Q, typename T>
-__global__ void k_shift(const T* __restrict__ A, T* __restrict__ B, Geo G, int dir) {
+__global__ void k_shift(const T* __restrict__ A, T* __restrict__ B, Geo G, int64_t NT, int dir) {
   using L = Lattice<Q>;
   const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (s >= G.N) return;
@@ -952,7 +1019,7 @@ __global__ void k_shift(const T* __restrict__ A, T* __restrict__ B, Geo G, int d
   for (int i = 0; i < Q; i++) {
     const int sx = wrap(x - dir * L::cx(i), G.nx), sy = wrap(y - dir * L::cy(i), G.ny),
               sz = wrap(z - dir * L::cz(i), G.nz);
-    B[(size_t)i * G.N + s] = A[(size_t)i * G.N + sx + (int64_t)G.nx * (sy + (int64_t)G.ny * sz)];
+    B[(size_t)i * NT + G.off + s] = A[(size_t)i * NT + site_of(G, sx, sy, sz)];
   }
 }
 
@@ -978,11 +1045,33 @@ inline unsigned blocks_for(int64_t n, int per = 256) { return (unsigned)((n + pe
 // ---------------------------------------------------------------------------
 struct Layout {
   size_t f[2], drho, own, ball, status;
-  size_t x, x0, u, om, phi, fext, dP, dL, F, T, m, I, rad, b0, k, org, ent0, nbs, nis, nin, jump, cand_n, cand, pairs;
+  size_t x, x0, u, om, phi, fext, dP, dL, F, T, m, I, rad, b0, k, org, ent0, nbs, nis, nin, jump, box, cand_n, cand,
+      pairs;
   size_t off, pid, slot, hdr, vel, sub;
-  int64_t max_ent;
+  size_t boxes, fbt, tiles;
+  int64_t max_ent, max_tiles;
   size_t total;
 };
+
+// The boxes of a context: one for lbm_create, several for an ensemble.
+struct BoxSet {
+  std::vector<int> dims;  // [nbox][3]
+  int64_t NT = 0;         // all sites
+  int64_t max_tiles = 0;  // tiles of the narrowest tile width
+};
+
+constexpr int kTileMin = 64;
+
+BoxSet make_boxset(int nbox, const int32_t* dims) {
+  BoxSet b;
+  b.dims.assign(dims, dims + 3 * (size_t)nbox);
+  for (int i = 0; i < nbox; i++) {
+    const int64_t nx = dims[3 * i], ny = dims[3 * i + 1], nz = dims[3 * i + 2];
+    b.NT += nx * ny * nz;
+    b.max_tiles += ny * nz * ((nx + kTileMin - 1) / kTileMin);
+  }
+  return b;
+}
 
 size_t store_size(int storage) { return storage == LBM_FP64 ? 8 : storage == LBM_FP32 ? 4 : 2; }
 
@@ -991,9 +1080,10 @@ int64_t entries_per_particle(int dim, double rmax) {
   return dim == 2 ? e * e : e * e * e;
 }
 
-Layout make_layout(const lbm_params& p) {
+Layout make_layout(const lbm_params& p, const BoxSet& bs) {
   Layout L{};
-  const int64_t N = (int64_t)p.nx * p.ny * p.nz;
+  const int64_t N = bs.NT;
+  const int64_t nbox = (int64_t)bs.dims.size() / 3;
   const int dim = p.lattice == LBM_D2Q9 ? 2 : 3;
   const int64_t np = std::max<int64_t>(p.max_particles, 1);
   L.max_ent = np * entries_per_particle(dim, p.max_radius);
@@ -1018,6 +1108,7 @@ Layout make_layout(const lbm_params& p) {
   L.ent0 = take(sizeof(int) * np); L.nbs = take(sizeof(int) * np); L.nis = take(sizeof(int) * np);
   L.nin = take(sizeof(int) * np);
   L.jump = take(sizeof(int) * np);
+  L.box = take(sizeof(int) * np);
   L.cand_n = take(sizeof(int) * np);
   L.cand = take(sizeof(int) * np * kCandMax);
   L.pairs = take(sizeof(int) * 2 * np * kCandMax);
@@ -1027,8 +1118,31 @@ Layout make_layout(const lbm_params& p) {
   L.hdr = take(sizeof(int) * 2 * L.max_ent);
   L.vel = take((p.storage == LBM_FP64 ? 8 : 4) * 4 * L.max_ent);
   L.sub = take((size_t)p.lattice * store_size(p.storage) * L.max_ent);
+  L.boxes = take(sizeof(Geo) * nbox);
+  L.fbt = take(sizeof(double) * p.lattice * nbox);
+  L.max_tiles = bs.max_tiles;
+  L.tiles = take(sizeof(int4) * bs.max_tiles);
   L.total = cur;
   return L;
+}
+
+int check_params(const lbm_params* p);
+
+// Parameters of an ensemble: those of every box (prm with the box's size).
+int check_boxes(const lbm_params* p, int nbox, const int32_t* dims) {
+  if (!p || nbox < 1 || !dims) return LBM_EINVAL;
+  int64_t NT = 0;
+  for (int b = 0; b < nbox; b++) {
+    lbm_params q = *p;
+    q.nx = dims[3 * b];
+    q.ny = dims[3 * b + 1];
+    q.nz = dims[3 * b + 2];
+    const int rc = check_params(&q);
+    if (rc != LBM_OK) return rc;
+    NT += (int64_t)q.nx * q.ny * q.nz;
+  }
+  if (NT >= ((int64_t)1 << 31)) return LBM_EINVAL;
+  return LBM_OK;
 }
 
 int check_params(const lbm_params* p) {
@@ -1069,7 +1183,25 @@ int check_params(const lbm_params* p) {
 struct lbm_ctx {
   lbm_params prm;
   int q, dim;
-  Geo G;
+  Geo G;                    // box 0 (the box of a single-box context)
+  int nbox;
+  int64_t NT;               // sites of all boxes
+  std::vector<Geo> boxes;   // host copy of the box table
+  Geo* d_boxes;
+  void* d_fbt;              // [nbox][q] 3 w_i c_i . f_b per box, compute type
+  int4* d_tiles;
+  int64_t ntiles;           // tiles of the current tile width
+  int tiles_w;              // tile width the table was built for (0: none)
+  int sweep_w, sweep_grid;  // sweep launch shape: w = 0 the one-box kernel, else tile width; grid 0 = one per tile
+  std::vector<int> h_box;   // box of every particle
+  std::vector<double> fbb;  // [nbox][3] fluid body force density
+  // step graph
+  hipStream_t cap;
+  hipGraph_t graph;
+  hipGraphExec_t gexec;
+  int g_steps, g_cur, g_w, g_grid;
+  int64_t g_np, g_nent;
+  int graph_steps;          // 0: eager launches
   hipStream_t stream;
   char* ws;
   Layout L;
@@ -1089,7 +1221,6 @@ struct lbm_ctx {
   int64_t nent;
   std::vector<double> h_x0, h_rad, h_m, h_I, h_fext;
   std::vector<int> h_off, h_pid, h_nbs, h_nis, h_nin;
-  double fb[3];  // fluid body force density
   size_t lds_window;  // LDS bytes of the per-particle record window (0: not used)
   bool prof;
   std::vector<hipEvent_t> ev;
@@ -1116,6 +1247,15 @@ SiteArgs<T> site_args(lbm_ctx* c) {
   return sa;
 }
 
+Boxes boxes_arg(const lbm_ctx* c) {
+  Boxes b;
+  b.g0 = c->boxes[0];
+  b.tab = c->d_boxes;
+  b.nbox = c->nbox;
+  b.NT = c->NT;
+  return b;
+}
+
 // Records of every ball site for the next sweep; with pending = 1 the IS
 // substep of the step that just ran is prepared.  Per-particle LDS windows
 // when they fit, one thread per entry otherwise.
@@ -1125,19 +1265,37 @@ int launch_prepare(lbm_ctx* c, int pending) {
   using C = typename Store<T>::C;
   if (c->lds_window > 0) {
     k_prepare_local<Q, T><<<c->np, 256, c->lds_window, c->stream>>>(
-        c->own, c->ball, c->hdr, (C*)c->vel, (T*)c->sub, (const C*)c->drho, (const T*)c->f[c->cur], c->P, c->E, c->G,
-        c->L.max_ent, c->prm.rho0, pending, c->dim);
+        c->own, c->ball, c->hdr, (C*)c->vel, (T*)c->sub, (const C*)c->drho, (const T*)c->f[c->cur], c->P, c->E,
+        boxes_arg(c), c->L.max_ent, c->prm.rho0, pending, c->dim);
   } else {
     k_prepare<Q, T><<<blocks_for(c->nent), 256, 0, c->stream>>>(
-        c->own, c->ball, c->hdr, (C*)c->vel, (T*)c->sub, (const C*)c->drho, (const T*)c->f[c->cur], c->P, c->E, c->G,
-        (int)c->nent, c->L.max_ent, c->prm.rho0, pending);
+        c->own, c->ball, c->hdr, (C*)c->vel, (T*)c->sub, (const C*)c->drho, (const T*)c->f[c->cur], c->P, c->E,
+        boxes_arg(c), (int)c->nent, c->L.max_ent, c->prm.rho0, pending);
   }
   HIP_TRY(hipGetLastError());
   return LBM_OK;
 }
 
+// Tile list {box, y, z, x0} of width w, box by box, rows in z, y order.
+int build_tiles(lbm_ctx* c, int w) {
+  if (c->tiles_w == w) return LBM_OK;
+  std::vector<int4> t;
+  for (int b = 0; b < c->nbox; b++) {
+    const Geo& g = c->boxes[b];
+    for (int z = 0; z < g.nz; z++)
+      for (int y = 0; y < g.ny; y++)
+        for (int x0 = 0; x0 < g.nx; x0 += w) t.push_back(make_int4(b, y, z, x0));
+  }
+  if ((int64_t)t.size() > c->L.max_tiles) return LBM_EINVAL;
+  HIP_TRY(hipMemcpyAsync(c->d_tiles, t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->ntiles = (int64_t)t.size();
+  c->tiles_w = w;
+  return LBM_OK;
+}
+
 template <int Q, typename T>
-int launch_step(lbm_ctx* c) {
+SweepArgs<Q, typename Store<T>::C> sweep_args(const lbm_ctx* c) {
   using C = typename Store<T>::C;
   using Lt = Lattice<Q>;
   SweepArgs<Q, C> a;
@@ -1145,7 +1303,7 @@ int launch_step(lbm_ctx* c) {
   a.ny = c->G.ny;
   a.nz = c->G.nz;
   a.nxb = (c->G.nx + kSweepBlock - 1) / kSweepBlock;
-  a.N = c->G.N;
+  a.N = c->NT;
   a.omega = (C)(1.0 / c->prm.tau);
   a.rho0 = (C)c->prm.rho0;
   a.walls = c->prm.walls;
@@ -1153,13 +1311,42 @@ int launch_step(lbm_ctx* c) {
     for (int hi = 0; hi < 2; hi++)
       for (int k = 0; k < 3; k++) a.wu[ax][hi][k] = (C)((c->prm.walls >> ax) & 1 ? c->prm.wall_velocity[ax][hi][k] : 0.0);
   for (int i = 0; i < Q; i++) {
-    const double cf = Lt::cx(i) * c->fb[0] + Lt::cy(i) * c->fb[1] + Lt::cz(i) * c->fb[2];
+    const double cf = Lt::cx(i) * c->fbb[0] + Lt::cy(i) * c->fbb[1] + Lt::cz(i) * c->fbb[2];
     a.fbt[i] = (C)(3.0 * Lt::w(i) * cf);
   }
+  return a;
+}
+
+// One sweep in the context's launch shape.
+template <int Q, typename T>
+int launch_sweep(lbm_ctx* c, int w, int grid) {
+  using C = typename Store<T>::C;
+  const SweepArgs<Q, C> a = sweep_args<Q, T>(c);
   const T* A = (const T*)c->f[c->cur];
   T* B = (T*)c->f[1 - c->cur];
   const SiteArgs<T> sa = site_args<Q, T>(c);
-  const unsigned nblk = (unsigned)((int64_t)a.nxb * c->G.ny * c->G.nz);
+  if (w == 0) {
+    const unsigned nblk = (unsigned)((int64_t)a.nxb * c->G.ny * c->G.nz);
+    if (c->np > 0)
+      k_sweep<Q, T, true><<<nblk, kSweepBlock, 0, c->stream>>>(A, B, a, sa);
+    else
+      k_sweep<Q, T, false><<<nblk, kSweepBlock, 0, c->stream>>>(A, B, a, sa);
+  } else {
+    const int64_t nt = c->ntiles;
+    const unsigned g = (unsigned)(grid > 0 && grid < nt ? grid : nt);
+    if (c->np > 0)
+      k_sweep_tiles<Q, T, true><<<g, w, 0, c->stream>>>(A, B, a, sa, c->d_boxes, c->d_tiles, (int)nt,
+                                                        (const C*)c->d_fbt);
+    else
+      k_sweep_tiles<Q, T, false><<<g, w, 0, c->stream>>>(A, B, a, sa, c->d_boxes, c->d_tiles, (int)nt,
+                                                         (const C*)c->d_fbt);
+  }
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+template <int Q, typename T>
+int launch_step(lbm_ctx* c) {
   if (c->prof) {
     if (c->ev_used + 2 > c->ev.size()) {
       for (int t = 0; t < 64; t++) {
@@ -1170,20 +1357,18 @@ int launch_step(lbm_ctx* c) {
     }
     HIP_TRY(hipEventRecord(c->ev[c->ev_used], c->stream));
   }
-  if (c->np > 0)
-    k_sweep<Q, T, true><<<nblk, kSweepBlock, 0, c->stream>>>(A, B, a, sa);
-  else
-    k_sweep<Q, T, false><<<nblk, kSweepBlock, 0, c->stream>>>(A, B, a, sa);
+  const int rc = launch_sweep<Q, T>(c, c->sweep_w, c->sweep_grid);
+  if (rc != LBM_OK) return rc;
   if (c->prof) {
     HIP_TRY(hipEventRecord(c->ev[c->ev_used + 1], c->stream));
     c->ev_used += 2;
   }
-  HIP_TRY(hipGetLastError());
   if (c->np > 0) {
-    k_reduce<<<c->np, kBoundaryBlock, 0, c->stream>>>(c->own, c->ball, c->slot, c->P, c->E, c->G, c->np,
-                                                      c->prm.rho0, c->dim, c->status);
-    k_particles<kParticleBlock><<<1, kParticleBlock, 0, c->stream>>>(c->P, c->np, c->dim, c->G, c->status);
-    k_stamp<<<blocks_for(c->nent), 256, 0, c->stream>>>(c->own, c->ball, c->P, c->E, c->G, 0, (int)c->nent);
+    const Boxes bx = boxes_arg(c);
+    k_reduce<<<c->np, kBoundaryBlock, 0, c->stream>>>(c->own, c->ball, c->slot, c->P, c->E, bx, c->prm.rho0,
+                                                      c->status);
+    k_particles<kParticleBlock><<<1, kParticleBlock, 0, c->stream>>>(c->P, c->np, c->dim, bx, c->status);
+    k_stamp<<<blocks_for(c->nent), 256, 0, c->stream>>>(c->own, c->ball, c->P, c->E, bx, 0, (int)c->nent);
     HIP_TRY(hipGetLastError());
   }
   c->cur = 1 - c->cur;  // f[cur] now holds this step's post-collision state
@@ -1197,15 +1382,16 @@ template <int Q, typename T>
 int launch_materialize(lbm_ctx* c, int write) {
   if (c->nent > 0) {
     k_materialize<Q, T><<<blocks_for(c->nent), 256, 0, c->stream>>>(
-        (T*)c->f[c->cur], c->ball, c->hdr, (const T*)c->sub, c->P, c->E, c->G, (int)c->nent, c->L.max_ent, write);
+        (T*)c->f[c->cur], c->ball, c->hdr, (const T*)c->sub, c->P, c->E, boxes_arg(c), (int)c->nent, c->L.max_ent,
+        write);
     HIP_TRY(hipGetLastError());
   }
   return LBM_OK;
 }
 
 template <int Q, typename T>
-int launch_moments(lbm_ctx* c, double* d_rho, double* d_u, int64_t s0, int64_t cnt) {
-  k_moments<Q, T><<<blocks_for(cnt), 256, 0, c->stream>>>((const T*)c->f[c->cur], d_rho, d_u, c->G,
+int launch_moments(lbm_ctx* c, int box, double* d_rho, double* d_u, int64_t s0, int64_t cnt) {
+  k_moments<Q, T><<<blocks_for(cnt), 256, 0, c->stream>>>((const T*)c->f[c->cur], d_rho, d_u, c->boxes[box], c->NT,
                                                           c->prm.rho0, s0, cnt);
   HIP_TRY(hipGetLastError());
   return LBM_OK;
@@ -1213,7 +1399,8 @@ int launch_moments(lbm_ctx* c, double* d_rho, double* d_u, int64_t s0, int64_t c
 
 template <int Q, typename T>
 int launch_shift(lbm_ctx* c, const void* A, void* B, int dir) {
-  k_shift<Q, T><<<blocks_for(c->G.N), 256, 0, c->stream>>>((const T*)A, (T*)B, c->G, dir);
+  for (int b = 0; b < c->nbox; b++)
+    k_shift<Q, T><<<blocks_for(c->boxes[b].N), 256, 0, c->stream>>>((const T*)A, (T*)B, c->boxes[b], c->NT, dir);
   HIP_TRY(hipGetLastError());
   return LBM_OK;
 }
@@ -1296,6 +1483,35 @@ int check_status(lbm_ctx* c) {
   return LBM_OK;
 }
 
+// Box table and per-box forcing terms 3 w_i c_i . f_b to the device.
+int upload_boxes(lbm_ctx* c) {
+  HIP_TRY(hipMemcpyAsync(c->d_boxes, c->boxes.data(), sizeof(Geo) * c->nbox, hipMemcpyHostToDevice, c->stream));
+  std::vector<double> fd((size_t)c->nbox * c->q);
+  for (int b = 0; b < c->nbox; b++)
+    for (int i = 0; i < c->q; i++) {
+      const int cx = c->q == 9 ? Lattice<9>::cx(i) : Lattice<19>::cx(i);
+      const int cy = c->q == 9 ? Lattice<9>::cy(i) : Lattice<19>::cy(i);
+      const int cz = c->q == 9 ? Lattice<9>::cz(i) : Lattice<19>::cz(i);
+      const double cf = cx * c->fbb[3 * b] + cy * c->fbb[3 * b + 1] + cz * c->fbb[3 * b + 2];
+      fd[(size_t)b * c->q + i] = 3.0 * lattice_w(c->q, i) * cf;
+    }
+  if (c->prm.storage == LBM_FP64) {
+    HIP_TRY(hipMemcpyAsync(c->d_fbt, fd.data(), sizeof(double) * fd.size(), hipMemcpyHostToDevice, c->stream));
+  } else {
+    std::vector<float> ff(fd.begin(), fd.end());
+    HIP_TRY(hipMemcpyAsync(c->d_fbt, ff.data(), sizeof(float) * ff.size(), hipMemcpyHostToDevice, c->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));  // the host vectors die here
+  return LBM_OK;
+}
+
+void drop_graph(lbm_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+}
+
 template <typename V>
 int upload(lbm_ctx* c, V* dst, const V* src, size_t count) {
   if (count == 0) return LBM_OK;
@@ -1314,7 +1530,16 @@ int lbm_workspace_size(const lbm_params* prm, size_t* bytes) {
   const int rc = check_params(prm);
   if (rc != LBM_OK) return rc;
   if (!bytes) return LBM_EINVAL;
-  *bytes = make_layout(*prm).total;
+  const int32_t dims[3] = {prm->nx, prm->ny, prm->nz};
+  *bytes = make_layout(*prm, make_boxset(1, dims)).total;
+  return LBM_OK;
+}
+
+int lbm_ensemble_workspace_size(const lbm_params* prm, int32_t nbox, const int32_t* dims, size_t* bytes) {
+  const int rc = check_boxes(prm, nbox, dims);
+  if (rc != LBM_OK) return rc;
+  if (!bytes) return LBM_EINVAL;
+  *bytes = make_layout(*prm, make_boxset(nbox, dims)).total;
   return LBM_OK;
 }
 
@@ -1325,19 +1550,28 @@ int lbm_bytes_per_site(const lbm_params* prm, int64_t* bytes) {
   return LBM_OK;
 }
 
-int lbm_create(const lbm_params* prm, void* d_workspace, size_t bytes, void* hip_stream, lbm_ctx** out) {
-  int rc = check_params(prm);
-  if (rc != LBM_OK) return rc;
+static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, void* d_workspace, size_t bytes,
+                       void* hip_stream, lbm_ctx** out) {
   if (!out) return LBM_EINVAL;
   *out = nullptr;
-  const Layout L = make_layout(*prm);
+  const BoxSet bset = make_boxset(nbox, dims);
+  const Layout L = make_layout(*prm, bset);
   if (!d_workspace || ((uintptr_t)d_workspace % kAlign) != 0 || bytes < L.total) return LBM_EWORKSPACE;
   lbm_ctx* c = new (std::nothrow) lbm_ctx();
   if (!c) return LBM_EINVAL;
   c->prm = *prm;
   c->q = prm->lattice;
   c->dim = prm->lattice == LBM_D2Q9 ? 2 : 3;
-  c->G = Geo{prm->nx, prm->ny, prm->nz, (int64_t)prm->nx * prm->ny * prm->nz, prm->walls};
+  c->nbox = nbox;
+  c->NT = bset.NT;
+  int64_t off = 0;
+  for (int b = 0; b < nbox; b++) {
+    const int nx = dims[3 * b], ny = dims[3 * b + 1], nz = dims[3 * b + 2];
+    const int64_t N = (int64_t)nx * ny * nz;
+    c->boxes.push_back(Geo{nx, ny, nz, N, prm->walls, off, 0});
+    off += N;
+  }
+  c->G = c->boxes[0];
   c->stream = (hipStream_t)hip_stream;
   c->ws = (char*)d_workspace;
   c->L = L;
@@ -1352,6 +1586,18 @@ int lbm_create(const lbm_params* prm, void* d_workspace, size_t bytes, void* hip
   c->own = (int*)(c->ws + L.own);
   c->ball = (int*)(c->ws + L.ball);
   c->status = (int*)(c->ws + L.status);
+  c->d_boxes = (Geo*)(c->ws + L.boxes);
+  c->d_fbt = c->ws + L.fbt;
+  c->d_tiles = (int4*)(c->ws + L.tiles);
+  c->ntiles = 0;
+  c->tiles_w = 0;
+  // one box: the row kernel; an ensemble: tiles of 128 sites, one workgroup each
+  c->sweep_w = nbox == 1 ? 0 : 128;
+  c->sweep_grid = 0;
+  c->cap = nullptr;
+  c->graph = nullptr;
+  c->gexec = nullptr;
+  c->graph_steps = 0;
   char* w = c->ws;
   c->P = DevParticles{(double*)(w + L.x),    (double*)(w + L.x0),  (double*)(w + L.u),
                       (double*)(w + L.om),   (double*)(w + L.phi), (double*)(w + L.fext),
@@ -1361,11 +1607,14 @@ int lbm_create(const lbm_params* prm, void* d_workspace, size_t bytes, void* hip
                       (int*)(w + L.org),
                       (int*)(w + L.ent0),    (int*)(w + L.nbs),    (int*)(w + L.nis),
                       (int*)(w + L.nin),     (int*)(w + L.cand_n), (int*)(w + L.jump),
+                      (int*)(w + L.box),
                       (int*)(w + L.cand),    (int*)(w + L.pairs)};
   c->E = DevEntries{(int*)(w + L.off), (int*)(w + L.pid)};
   c->np = 0;
   c->nent = 0;
-  for (int a = 0; a < 3; a++) c->fb[a] = prm->body_force[a];
+  c->fbb.assign(3 * (size_t)nbox, 0.0);
+  for (int b = 0; b < nbox; b++)
+    for (int a = 0; a < 3; a++) c->fbb[3 * b + a] = prm->body_force[a];
   c->prof = false;
   c->ev_used = 0;
   {
@@ -1376,13 +1625,14 @@ int lbm_create(const lbm_params* prm, void* d_workspace, size_t bytes, void* hip
     c->lds_window = bytes <= 65536 ? bytes : 0;
   }
   // fluid at rest: every deviation zero; empty map; clear status
-  const size_t fbytes = (size_t)c->q * c->G.N * store_size(prm->storage);
+  const size_t fbytes = (size_t)c->q * c->NT * store_size(prm->storage);
   const int64_t nwords = (int64_t)(fbytes / 4);
   k_fill<uint32_t><<<blocks_for(nwords), 256, 0, c->stream>>>((uint32_t*)c->f[0], nwords, 0u);
-  k_fill<int><<<blocks_for(c->G.N), 256, 0, c->stream>>>(c->own, c->G.N, kEmpty);
-  k_fill<int><<<blocks_for(c->G.N), 256, 0, c->stream>>>(c->ball, c->G.N, kEmpty);
+  k_fill<int><<<blocks_for(c->NT), 256, 0, c->stream>>>(c->own, c->NT, kEmpty);
+  k_fill<int><<<blocks_for(c->NT), 256, 0, c->stream>>>(c->ball, c->NT, kEmpty);
   k_fill<int><<<1, 256, 0, c->stream>>>(c->status, 16, 0);
-  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+  if (hipGetLastError() != hipSuccess || upload_boxes(c) != LBM_OK ||
+      (nbox > 1 && build_tiles(c, c->sweep_w) != LBM_OK) || hipStreamSynchronize(c->stream) != hipSuccess) {
     delete c;
     return LBM_EHIP;
   }
@@ -1390,17 +1640,35 @@ int lbm_create(const lbm_params* prm, void* d_workspace, size_t bytes, void* hip
   return LBM_OK;
 }
 
+int lbm_create(const lbm_params* prm, void* d_workspace, size_t bytes, void* hip_stream, lbm_ctx** out) {
+  const int rc = check_params(prm);
+  if (rc != LBM_OK) return rc;
+  const int32_t dims[3] = {prm->nx, prm->ny, prm->nz};
+  return create_impl(prm, 1, dims, d_workspace, bytes, hip_stream, out);
+}
+
+int lbm_ensemble_create(const lbm_params* prm, int32_t nbox, const int32_t* dims, void* d_workspace, size_t bytes,
+                        void* hip_stream, lbm_ctx** out) {
+  const int rc = check_boxes(prm, nbox, dims);
+  if (rc != LBM_OK) return rc;
+  return create_impl(prm, nbox, dims, d_workspace, bytes, hip_stream, out);
+}
+
 int lbm_destroy(lbm_ctx* c) {
   if (!c) return LBM_EINVAL;
   (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  drop_graph(c);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   delete c;
   return LBM_OK;
 }
 
-int lbm_add_particles(lbm_ctx* c, int32_t n, const double* x, const double* u, const double* omega,
-                      const double* radius, const double* mass, const double* inertia, int32_t* first_id) {
-  if (!c || n < 0) return LBM_EINVAL;
+static int add_impl(lbm_ctx* c, int32_t bx, int32_t n, const double* x, const double* u, const double* omega,
+                    const double* radius, const double* mass, const double* inertia, int32_t* first_id) {
+  if (!c || n < 0 || bx < 0 || bx >= c->nbox) return LBM_EINVAL;
+  // particles of a box have consecutive ids: boxes are filled in order
+  if (c->np > 0 && bx < c->h_box.back()) return LBM_EINVAL;
   if (n == 0) {
     if (first_id) *first_id = c->np;
     return LBM_OK;
@@ -1408,7 +1676,8 @@ int lbm_add_particles(lbm_ctx* c, int32_t n, const double* x, const double* u, c
   if (!x || !radius || !mass || !inertia) return LBM_EINVAL;
   if (c->np + (int64_t)n > c->prm.max_particles) return LBM_ECAPACITY;
   const int dim = c->dim;
-  const int box[3] = {c->G.nx, c->G.ny, c->G.nz};
+  const Geo& BG = c->boxes[bx];
+  const int box[3] = {BG.nx, BG.ny, BG.nz};
   for (int j = 0; j < n; j++) {
     for (int a = 0; a < 3; a++) {
       if (a < dim && !std::isfinite(x[3 * j + a])) return LBM_ENONFINITE;
@@ -1443,6 +1712,7 @@ int lbm_add_particles(lbm_ctx* c, int32_t n, const double* x, const double* u, c
   };
   for (int j = 0; j < n; j++) {
     for (int p = 0; p < c->np; p++) {
+      if (c->h_box[p] != bx) continue;  // boxes are independent
       const double lim = radius[j] + c->h_rad[p];
       if (dist2(&cur[3 * p], &x[3 * j]) < lim * lim) return LBM_EOVERLAP;
     }
@@ -1501,6 +1771,8 @@ int lbm_add_particles(lbm_ctx* c, int32_t n, const double* x, const double* u, c
   UP(c->P.nbs + p0, hnbs.data(), (size_t)n);
   UP(c->P.nis + p0, hnis.data(), (size_t)n);
   UP(c->P.nin + p0, hnin.data(), (size_t)n);
+  const std::vector<int> hbox((size_t)n, bx);
+  UP(c->P.box + p0, hbox.data(), (size_t)n);
   UP(c->E.off + c->nent, hoff.data(), hoff.size());
   UP(c->E.pid + c->nent, hpid.data(), hpid.size());
 #undef UP
@@ -1509,7 +1781,9 @@ int lbm_add_particles(lbm_ctx* c, int32_t n, const double* x, const double* u, c
   HIP_TRY(hipMemcpyAsync(c->P.T + 3 * p0, zero.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
   // stamp the new entries into the current map (existing owners have lower ids)
   const int64_t e0 = c->nent, e1 = c->nent + (int64_t)hoff.size();
-  k_stamp<<<blocks_for(e1 - e0), 256, 0, c->stream>>>(c->own, c->ball, c->P, c->E, c->G, (int)e0, (int)e1);
+  for (int b = bx; b < c->nbox; b++) c->boxes[b].p1 = c->np + n;  // later boxes are still empty
+  c->G = c->boxes[0];
+  k_stamp<<<blocks_for(e1 - e0), 256, 0, c->stream>>>(c->own, c->ball, c->P, c->E, boxes_arg(c), (int)e0, (int)e1);
   HIP_TRY(hipGetLastError());
   c->nent = e1;
   c->np += n;
@@ -1529,23 +1803,189 @@ int lbm_add_particles(lbm_ctx* c, int32_t n, const double* x, const double* u, c
   }
   c->h_off.insert(c->h_off.end(), hoff.begin(), hoff.end());
   c->h_pid.insert(c->h_pid.end(), hpid.begin(), hpid.end());
-  // fluid body force: user value, plus the opposite of the particles' total
-  // external force spread over every site in a zero-net-force box
-  double tot[3] = {0, 0, 0};
+  c->h_box.insert(c->h_box.end(), (size_t)n, bx);
+  // fluid body force of every box: user value, plus the opposite of the
+  // box's particles' total external force spread over its sites in a
+  // zero-net-force box
+  std::vector<double> tot(3 * (size_t)c->nbox, 0.0);
   for (int p = 0; p < c->np; p++)
-    for (int a = 0; a < 3; a++) tot[a] += c->h_fext[3 * p + a];
-  for (int a = 0; a < 3; a++)
-    c->fb[a] = c->prm.body_force[a] - (c->prm.zero_net_force ? tot[a] / (double)c->G.N : 0.0);
+    for (int a = 0; a < 3; a++) tot[3 * c->h_box[p] + a] += c->h_fext[3 * p + a];
+  for (int b = 0; b < c->nbox; b++)
+    for (int a = 0; a < 3; a++)
+      c->fbb[3 * b + a] =
+          c->prm.body_force[a] - (c->prm.zero_net_force ? tot[3 * b + a] / (double)c->boxes[b].N : 0.0);
+  const int urc = upload_boxes(c);
+  if (urc != LBM_OK) return urc;
+  drop_graph(c);
   if (first_id) *first_id = p0;
+  return LBM_OK;
+}
+
+int lbm_add_particles(lbm_ctx* c, int32_t n, const double* x, const double* u, const double* omega,
+                      const double* radius, const double* mass, const double* inertia, int32_t* first_id) {
+  return add_impl(c, 0, n, x, u, omega, radius, mass, inertia, first_id);
+}
+
+int lbm_ensemble_add_particles(lbm_ctx* c, int32_t box, int32_t n, const double* x, const double* u,
+                               const double* omega, const double* radius, const double* mass,
+                               const double* inertia, int32_t* first_id) {
+  return add_impl(c, box, n, x, u, omega, radius, mass, inertia, first_id);
+}
+
+// Capture graph_steps steps (an even number, so the population buffers come
+// back to the same roles) on a private stream; the graph is rebuilt when the
+// particle set, the buffer roles or the sweep launch shape changed.
+static int ensure_graph(lbm_ctx* c) {
+  if (c->gexec && c->g_steps == c->graph_steps && c->g_cur == c->cur && c->g_np == c->np &&
+      c->g_nent == c->nent && c->g_w == c->sweep_w && c->g_grid == c->sweep_grid)
+    return LBM_OK;
+  drop_graph(c);
+  if (!c->cap) HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  hipStream_t user = c->stream;
+  const bool prof = c->prof;
+  const int cur0 = c->cur;
+  c->stream = c->cap;
+  c->prof = false;
+  int rc = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal) == hipSuccess ? LBM_OK : LBM_EHIP;
+  for (int t = 0; rc == LBM_OK && t < c->graph_steps; t++) rc = DISPATCH(c, launch_step, c);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(c->cap, &g);
+  c->stream = user;
+  c->prof = prof;
+  c->cur = cur0;  // nothing ran yet
+  if (rc != LBM_OK || ec != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return LBM_EHIP;
+  }
+  c->graph = g;
+  if (hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+    drop_graph(c);
+    return LBM_EHIP;
+  }
+  c->g_steps = c->graph_steps;
+  c->g_cur = c->cur;
+  c->g_np = c->np;
+  c->g_nent = c->nent;
+  c->g_w = c->sweep_w;
+  c->g_grid = c->sweep_grid;
   return LBM_OK;
 }
 
 int lbm_step(lbm_ctx* c, int32_t nsteps) {
   if (!c || nsteps < 0) return LBM_EINVAL;
+  if (c->sweep_w > 0) {
+    const int rc = build_tiles(c, c->sweep_w);
+    if (rc != LBM_OK) return rc;
+  }
+  if (c->graph_steps > 0) {
+    while (nsteps >= c->graph_steps) {
+      const int rc = ensure_graph(c);
+      if (rc != LBM_OK) return rc;
+      HIP_TRY(hipGraphLaunch(c->gexec, c->stream));
+      nsteps -= c->graph_steps;
+    }
+  }
   for (int t = 0; t < nsteps; t++) {
     const int rc = DISPATCH(c, launch_step, c);
     if (rc != LBM_OK) return rc;
   }
+  return LBM_OK;
+}
+
+int lbm_set_graph(lbm_ctx* c, int32_t steps_per_graph) {
+  if (!c || steps_per_graph < 0 || steps_per_graph % 2) return LBM_EINVAL;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->graph_steps = steps_per_graph;
+  drop_graph(c);
+  return LBM_OK;
+}
+
+int lbm_set_sweep_config(lbm_ctx* c, int32_t width, int32_t grid) {
+  if (!c || grid < 0) return LBM_EINVAL;
+  if (width != 0 && width != 64 && width != 128 && width != 256 && width != 512) return LBM_EINVAL;
+  if (width == 0 && c->nbox != 1) return LBM_EINVAL;  // the row kernel covers one box
+  if (width > 0) {
+    const int rc = build_tiles(c, width);
+    if (rc != LBM_OK) return rc;
+  }
+  c->sweep_w = width;
+  c->sweep_grid = width > 0 ? grid : 0;
+  return LBM_OK;
+}
+
+int lbm_get_sweep_config(lbm_ctx* c, int32_t* width, int32_t* grid) {
+  if (!c) return LBM_EINVAL;
+  if (width) *width = c->sweep_w;
+  if (grid) *grid = c->sweep_grid;
+  return LBM_OK;
+}
+
+int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* width, int32_t* grid, double* best_ms) {
+  if (!c || reps < 1) return LBM_EINVAL;
+  // a sweep recomputes B and the ball-site scratch from A and the records,
+  // so repeating it leaves the state as one sweep does: time the candidates
+  // on the live state
+  int dev = 0, ncu = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  struct Cand {
+    int w, g;
+  };
+  std::vector<Cand> cands;
+  if (c->nbox == 1) cands.push_back({0, 0});
+  for (int w : {64, 128, 256, 512})
+    for (int k : {0, 4, 8, 16, 32}) cands.push_back({w, k * ncu});
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int rc = LBM_OK;
+  double best = 1e300;
+  Cand win = {c->sweep_w, c->sweep_grid};
+  for (const Cand& cd : cands) {
+    if (cd.w > 0 && (rc = build_tiles(c, cd.w)) != LBM_OK) break;
+    if ((rc = DISPATCH(c, launch_sweep, c, cd.w, cd.g)) != LBM_OK) break;  // warm-up
+    if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = LBM_EHIP; break; }
+    for (int r = 0; r < reps && rc == LBM_OK; r++) rc = DISPATCH(c, launch_sweep, c, cd.w, cd.g);
+    if (rc != LBM_OK) break;
+    float ms = 0;
+    if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      rc = LBM_EHIP;
+      break;
+    }
+    if (ms / reps < best) {
+      best = ms / reps;
+      win = cd;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != LBM_OK) return rc;
+  rc = lbm_set_sweep_config(c, win.w, win.g);
+  if (rc != LBM_OK) return rc;
+  if (width) *width = win.w;
+  if (grid) *grid = win.g;
+  if (best_ms) *best_ms = best;
+  return LBM_OK;
+}
+
+int lbm_box_info(lbm_ctx* c, int32_t box, int32_t* dims, int64_t* first_site, int32_t* first_particle,
+                 int32_t* n_particles) {
+  if (!c || box < 0 || box >= c->nbox) return LBM_EINVAL;
+  const Geo& g = c->boxes[box];
+  if (dims) {
+    dims[0] = g.nx;
+    dims[1] = g.ny;
+    dims[2] = g.nz;
+  }
+  if (first_site) *first_site = g.off;
+  int p0 = 0, cnt = 0;
+  for (int p = 0; p < c->np; p++) {
+    if (c->h_box[p] < box) p0 = p + 1;
+    if (c->h_box[p] == box) cnt++;
+  }
+  if (first_particle) *first_particle = p0;
+  if (n_particles) *n_particles = cnt;
   return LBM_OK;
 }
 
@@ -1568,35 +2008,40 @@ int lbm_fields(lbm_ctx* c, double* rho, double* u, int32_t* owner) {
     const int mrc = DISPATCH(c, launch_materialize, c, 1);
     if (mrc != LBM_OK) return mrc;
     // the other population buffer is free between steps: stage moments there
-    const size_t stage = (size_t)c->q * c->G.N * store_size(c->prm.storage);
+    const size_t stage = (size_t)c->q * c->NT * store_size(c->prm.storage);
     const int64_t chunk = (int64_t)(stage / (4 * sizeof(double)));
     double* d_rho = (double*)c->f[1 - c->cur];
     double* d_u = d_rho + chunk;
-    std::vector<double> hr, hu;
-    for (int64_t s0 = 0; s0 < c->G.N; s0 += chunk) {
-      const int64_t cnt = std::min<int64_t>(chunk, c->G.N - s0);
-      const int rc = DISPATCH(c, launch_moments, c, d_rho, d_u, s0, cnt);
-      if (rc != LBM_OK) return rc;
-      if (rho) HIP_TRY(hipMemcpyAsync(rho + s0, d_rho, sizeof(double) * cnt, hipMemcpyDeviceToHost, c->stream));
-      if (u) HIP_TRY(hipMemcpyAsync(u + 3 * s0, d_u, sizeof(double) * 3 * cnt, hipMemcpyDeviceToHost, c->stream));
-      HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int b = 0; b < c->nbox; b++) {
+      const Geo& g = c->boxes[b];
+      for (int64_t s0 = 0; s0 < g.N; s0 += chunk) {
+        const int64_t cnt = std::min<int64_t>(chunk, g.N - s0);
+        const int rc = DISPATCH(c, launch_moments, c, b, d_rho, d_u, s0, cnt);
+        if (rc != LBM_OK) return rc;
+        if (rho)
+          HIP_TRY(hipMemcpyAsync(rho + g.off + s0, d_rho, sizeof(double) * cnt, hipMemcpyDeviceToHost, c->stream));
+        if (u)
+          HIP_TRY(hipMemcpyAsync(u + 3 * (g.off + s0), d_u, sizeof(double) * 3 * cnt, hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+      }
     }
   }
   if (owner) {
-    std::vector<int> m(c->G.N);
-    HIP_TRY(hipMemcpyAsync(m.data(), c->own, sizeof(int) * c->G.N, hipMemcpyDeviceToHost, c->stream));
+    std::vector<int> m(c->NT);
+    HIP_TRY(hipMemcpyAsync(m.data(), c->own, sizeof(int) * c->NT, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    for (int64_t s = 0; s < c->G.N; s++) owner[s] = m[s] == kEmpty ? -1 : c->h_pid[m[s] >> 1];
+    for (int64_t s = 0; s < c->NT; s++) owner[s] = m[s] == kEmpty ? -1 : c->h_pid[m[s] >> 1];
   }
   return check_status(c);
 }
 
 int lbm_site_kind(lbm_ctx* c, int8_t* kind) {
   if (!c || !kind) return LBM_EINVAL;
-  std::vector<int> m(c->G.N);
-  HIP_TRY(hipMemcpyAsync(m.data(), c->own, sizeof(int) * c->G.N, hipMemcpyDeviceToHost, c->stream));
+  std::vector<int> m(c->NT);
+  HIP_TRY(hipMemcpyAsync(m.data(), c->own, sizeof(int) * c->NT, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  for (int64_t s = 0; s < c->G.N; s++) kind[s] = m[s] == kEmpty ? 0 : (int8_t)(1 + (m[s] & 1));
+  for (int64_t s = 0; s < c->NT; s++) kind[s] = m[s] == kEmpty ? 0 : (int8_t)(1 + (m[s] & 1));
   return check_status(c);
 }
 
@@ -1620,7 +2065,7 @@ int lbm_get_distributions(lbm_ctx* c, double* f) {
   if (rc != LBM_OK) return rc;
   rc = DISPATCH(c, launch_shift, c, c->f[c->cur], stage, 1);
   if (rc != LBM_OK) return rc;
-  const int64_t n = (int64_t)c->q * c->G.N;
+  const int64_t n = (int64_t)c->q * c->NT;
   const int ss = (int)store_size(c->prm.storage);
   std::vector<unsigned char> h((size_t)n * ss);
   HIP_TRY(hipMemcpyAsync(h.data(), stage, (size_t)n * ss, hipMemcpyDeviceToHost, c->stream));
@@ -1628,8 +2073,8 @@ int lbm_get_distributions(lbm_ctx* c, double* f) {
   for (int i = 0; i < c->q; i++) {
     const double w = lattice_w(c->q, i);
     const double base = w * c->prm.rho0;
-    for (int64_t s = 0; s < c->G.N; s++) {
-      const int64_t k = (int64_t)i * c->G.N + s;
+    for (int64_t s = 0; s < c->NT; s++) {
+      const int64_t k = (int64_t)i * c->NT + s;
       double g;
       switch (c->prm.storage) {
         case LBM_FP64: g = ((const double*)h.data())[k]; break;
@@ -1645,7 +2090,7 @@ int lbm_get_distributions(lbm_ctx* c, double* f) {
 
 int lbm_set_distributions(lbm_ctx* c, const double* f) {
   if (!c || !f) return LBM_EINVAL;
-  const int64_t n = (int64_t)c->q * c->G.N;
+  const int64_t n = (int64_t)c->q * c->NT;
   for (int64_t i = 0; i < n; i++)
     if (!std::isfinite(f[i])) return LBM_ENONFINITE;
   void* stage = c->f[1 - c->cur];
@@ -1654,8 +2099,8 @@ int lbm_set_distributions(lbm_ctx* c, const double* f) {
   for (int i = 0; i < c->q; i++) {
     const double w = lattice_w(c->q, i);
     const double base = w * c->prm.rho0;
-    for (int64_t s = 0; s < c->G.N; s++) {
-      const int64_t k = (int64_t)i * c->G.N + s;
+    for (int64_t s = 0; s < c->NT; s++) {
+      const int64_t k = (int64_t)i * c->NT + s;
       const double g = f[k] - base;
       switch (c->prm.storage) {
         case LBM_FP64: ((double*)h.data())[k] = g; break;

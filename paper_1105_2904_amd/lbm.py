@@ -67,6 +67,14 @@ def lib():
             "lbm_profile": [vp, _dp, ctypes.POINTER(ctypes.c_int64)],
             "lbm_bytes_per_site": [P, ctypes.POINTER(ctypes.c_int64)],
             "lbm_device_copy": [vp, vp, ctypes.c_size_t, vp],
+            "lbm_ensemble_workspace_size": [P, ctypes.c_int32, _ip, ctypes.POINTER(ctypes.c_size_t)],
+            "lbm_ensemble_create": [P, ctypes.c_int32, _ip, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)],
+            "lbm_ensemble_add_particles": [vp, ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp, _dp, _dp, _dp, _ip],
+            "lbm_box_info": [vp, ctypes.c_int32, _ip, ctypes.POINTER(ctypes.c_int64), _ip, _ip],
+            "lbm_set_sweep_config": [vp, ctypes.c_int32, ctypes.c_int32],
+            "lbm_get_sweep_config": [vp, _ip, _ip],
+            "lbm_autotune": [vp, ctypes.c_int32, _ip, _ip, _dp],
+            "lbm_set_graph": [vp, ctypes.c_int32],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -146,22 +154,56 @@ def _vec1(a, n):
     return np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), (n,)))
 
 
+def _dims(dims):
+    d = np.ascontiguousarray(dims, dtype=np.int32).reshape(-1, 3)
+    return d, d.ctypes.data_as(_ip)
+
+
+def lbm_ensemble_workspace_size(params, dims):
+    d, dp = _dims(dims)
+    n = ctypes.c_size_t(0)
+    _check(lib().lbm_ensemble_workspace_size(ctypes.byref(params), len(d), dp, ctypes.byref(n)),
+           "lbm_ensemble_workspace_size")
+    return n.value
+
+
 class Simulation:
     """A context plus the torch workspace tensor it lives in."""
 
     def __init__(self, lattice, nx, ny, nz=1, tau=1.0, rho0=1.0, gravity=(0, 0, 0),
                  body_force=(0, 0, 0), zero_net_force=False, storage="fp32", max_particles=0,
-                 max_radius=1.0, walls=0, wall_velocity=None, device="cuda", stream=None):
+                 max_radius=1.0, walls=0, wall_velocity=None, device="cuda", stream=None, boxes=None):
+        """One box of nx x ny x nz sites, or with boxes = [[nx, ny, nz], ...]
+        an ensemble of independent boxes stepped together (nx, ny, nz are then
+        ignored)."""
         import torch
         self.params = make_params(lattice, nx, ny, nz, tau, rho0, gravity, body_force,
                                   zero_net_force, storage, max_particles, max_radius, walls,
                                   wall_velocity)
-        self.q, self.nx, self.ny, self.nz = int(lattice), int(nx), int(ny), int(nz)
-        self.N = self.nx * self.ny * self.nz
-        self.nbytes = lbm_workspace_size(self.params)
-        self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
-        self.ctx = lbm_create(self.params, self.workspace.data_ptr(), self.nbytes, self.stream.cuda_stream)
+        self.q = int(lattice)
+        if boxes is None:
+            self.dims = np.array([[int(nx), int(ny), int(nz)]], dtype=np.int32)
+        else:
+            self.dims = np.ascontiguousarray(boxes, dtype=np.int32).reshape(-1, 3)
+        self.nx, self.ny, self.nz = (int(v) for v in self.dims[0])
+        self.box_sites = self.dims.prod(axis=1).astype(np.int64)
+        self.box_start = np.concatenate([[0], np.cumsum(self.box_sites)[:-1]])
+        self.N = int(self.box_sites.sum())
+        stream = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
+        self.stream = stream
+        if boxes is None:
+            self.nbytes = lbm_workspace_size(self.params)
+            self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+            self.ctx = lbm_create(self.params, self.workspace.data_ptr(), self.nbytes, stream.cuda_stream)
+        else:
+            self.nbytes = lbm_ensemble_workspace_size(self.params, self.dims)
+            self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+            ctx = ctypes.c_void_p()
+            _check(lib().lbm_ensemble_create(ctypes.byref(self.params), len(self.dims), _dims(self.dims)[1],
+                                             ctypes.c_void_p(self.workspace.data_ptr()), self.nbytes,
+                                             ctypes.c_void_p(stream.cuda_stream), ctypes.byref(ctx)),
+                   "lbm_ensemble_create")
+            self.ctx = ctx
         self.n_particles = 0
 
     def close(self):
@@ -175,15 +217,40 @@ class Simulation:
         except Exception:
             pass
 
-    def add_particles(self, x, u=None, omega=None, radius=None, mass=None, inertia=None):
+    def add_particles(self, x, u=None, omega=None, radius=None, mass=None, inertia=None, box=0):
         x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 3)
         n = x.shape[0]
         first = ctypes.c_int32(-1)
-        _check(lib().lbm_add_particles(self.ctx, n, _d(x), _d(_vec3(u, n)), _d(_vec3(omega, n)),
-                                       _d(_vec1(radius, n)), _d(_vec1(mass, n)), _d(_vec1(inertia, n)),
-                                       ctypes.byref(first)), "lbm_add_particles")
+        _check(lib().lbm_ensemble_add_particles(self.ctx, int(box), n, _d(x), _d(_vec3(u, n)),
+                                                _d(_vec3(omega, n)), _d(_vec1(radius, n)),
+                                                _d(_vec1(mass, n)), _d(_vec1(inertia, n)),
+                                                ctypes.byref(first)), "lbm_ensemble_add_particles")
         self.n_particles += n
         return first.value
+
+    def box_info(self, box):
+        dims = np.zeros(3, dtype=np.int32)
+        s0, p0, n = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().lbm_box_info(self.ctx, int(box), dims.ctypes.data_as(_ip), ctypes.byref(s0),
+                                  ctypes.byref(p0), ctypes.byref(n)), "lbm_box_info")
+        return dims, s0.value, p0.value, n.value
+
+    def set_sweep_config(self, width, grid=0):
+        _check(lib().lbm_set_sweep_config(self.ctx, int(width), int(grid)), "lbm_set_sweep_config")
+
+    def sweep_config(self):
+        w, g = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().lbm_get_sweep_config(self.ctx, ctypes.byref(w), ctypes.byref(g)), "lbm_get_sweep_config")
+        return w.value, g.value
+
+    def autotune(self, reps=5):
+        w, g, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(lib().lbm_autotune(self.ctx, int(reps), ctypes.byref(w), ctypes.byref(g), ctypes.byref(ms)),
+               "lbm_autotune")
+        return w.value, g.value, ms.value
+
+    def set_graph(self, steps_per_graph):
+        _check(lib().lbm_set_graph(self.ctx, int(steps_per_graph)), "lbm_set_graph")
 
     def step(self, n=1):
         _check(lib().lbm_step(self.ctx, int(n)), "lbm_step")
@@ -199,12 +266,16 @@ class Simulation:
         u = np.zeros((self.N, 3))
         own = np.zeros(self.N, dtype=np.int32)
         _check(lib().lbm_fields(self.ctx, _d(rho), _d(u), own.ctypes.data_as(_ip)), "lbm_fields")
+        if len(self.dims) > 1:
+            return rho, u, own  # sites of every box, box after box
         shp = (self.nz, self.ny, self.nx)
         return rho.reshape(shp), u.reshape(shp + (3,)), own.reshape(shp)
 
     def get_distributions(self):
         f = np.zeros((self.q, self.N))
         _check(lib().lbm_get_distributions(self.ctx, _d(f)), "lbm_get_distributions")
+        if len(self.dims) > 1:
+            return f
         return f.reshape(self.q, self.nz, self.ny, self.nx)
 
     def set_distributions(self, f):
@@ -215,6 +286,8 @@ class Simulation:
         k = np.zeros(self.N, dtype=np.int8)
         _check(lib().lbm_site_kind(self.ctx, k.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))),
                "lbm_site_kind")
+        if len(self.dims) > 1:
+            return k
         return k.reshape(self.nz, self.ny, self.nx)
 
     def shifts(self):

@@ -141,3 +141,30 @@ def spheres_3d_config(seed=2, storage="fp32"):
             "tau": 0.6, "rho0": 1.0, "gravity": (0.0, 0.0, -1e-6),
             "zero_net_force": True, "storage": storage, "steps": 2000,
             "particles": suspension(19, (256, 256, 256), 500, 6.0, 1.2, seed)}
+
+
+def ensemble_2d_config(seed=4, nbox=64, phi_max=0.25):
+    """An ensemble of independent D2Q9 boxes: side L uniform in 128..512,
+    n uniform in 10..80 disks with radii uniform in [6, 12], density ratio
+    1.5, gravity 1e-5, tau 0.7, FP32.  The count is clipped (last disks
+    dropped) so that the area fraction stays <= phi_max: 80 disks of mean
+    area 264 do not fit a 128^2 box."""
+    rng = SplitMix64(seed)
+    boxes, parts, clipped = [], [], []
+    for b in range(nbox):
+        L = rng.randint(128, 512)
+        n = rng.randint(10, 80)
+        radii = np.array([6.0 + 6.0 * rng.uniform() for _ in range(n)])
+        keep = n
+        while keep > 0 and np.pi * (radii[:keep] ** 2).sum() > phi_max * L * L:
+            keep -= 1
+        radii = radii[:keep]
+        clipped.append(n - keep)
+        x = place_particles((L, L, 1), radii, seed * 1000 + b)
+        m, inertia = solid_body(2, radii, 1.5)
+        boxes.append((L, L, 1))
+        parts.append({"x": x, "u": np.zeros((keep, 3)), "omega": np.zeros((keep, 3)), "radius": radii,
+                      "mass": np.asarray(m, dtype=np.float64), "inertia": np.asarray(inertia, dtype=np.float64)})
+    return {"name": "d2q9-ensemble-%d-boxes" % nbox, "q": 9, "boxes": np.array(boxes, dtype=np.int32),
+            "tau": 0.7, "rho0": 1.0, "gravity": (0.0, -1e-5, 0.0), "zero_net_force": True,
+            "storage": "fp32", "steps": 10000, "particles": parts, "clipped": clipped}

@@ -1,0 +1,222 @@
+"""Ensembles of independent boxes, sweep launch shapes, the autotuner and
+step graphs, through the C ABI on the GPU.
+
+An ensemble steps every box with one launch per kernel; each box must match
+its own FP64 oracle instance exactly as a single box does (same gates as
+test_gpu_parity).  Every sweep shape and a graph replay must give the same
+bits as the default eager launches.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1105_2904_amd import lbm
+from paper_1105_2904_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": (1e-12, 1e-12), "fp32": (1e-5, 1e-4)}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    lbm.lib()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _boxes_2d():
+    dims = [(40, 36, 1), (64, 30, 1), (33, 47, 1), (80, 80, 1), (50, 50, 1), (130, 24, 1)]
+    counts = [2, 0, 1, 4, 3, 1]
+    parts = []
+    for b, (d, n) in enumerate(zip(dims, counts)):
+        if n == 0:
+            parts.append(None)
+            continue
+        r = 4.0 if d[1] < 30 else 5.0
+        parts.append(wl.suspension(9, d, n, r, 1.5, seed=60 + b))
+    return dims, parts
+
+
+def _boxes_3d():
+    dims = [(24, 20, 18), (30, 26, 22), (20, 20, 20)]
+    parts = [wl.suspension(19, d, n, 3.5, 1.3, seed=70 + b) for b, (d, n) in enumerate(zip(dims, [1, 2, 1]))]
+    return dims, parts
+
+
+def _make(q, dims, parts, storage, g, tau=0.7, extra=0):
+    n = sum(0 if p is None else len(p["radius"]) for p in parts) + extra
+    rmax = max(float(p["radius"].max()) for p in parts if p is not None)
+    sim = lbm.Simulation(q, 1, 1, 1, tau=tau, gravity=g, zero_net_force=True, storage=storage,
+                         max_particles=n, max_radius=rmax, boxes=dims)
+    oras = []
+    for b, (d, p) in enumerate(zip(dims, parts)):
+        o = oracle.Oracle(q, *d, tau, gravity=g, zero_net_force=True)
+        if p is not None:
+            kw = dict(radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
+            sim.add_particles(p["x"], box=b, **kw)
+            o.add_particles(p["x"], **kw)
+        oras.append(o)
+    return sim, oras
+
+
+def _compare(sim, oras, storage, label):
+    tf, tF = TOL[storage]
+    f = sim.get_distributions()
+    kind = sim.site_kind()
+    F, T, x, u, om = sim.forces()
+    worst = [0.0, 0.0]
+    for b, o in enumerate(oras):
+        dims, s0, p0, n = sim.box_info(b)
+        N = int(np.prod(dims))
+        fo = o.get_f().reshape(o.q, -1)
+        e = np.abs(f[:, s0:s0 + N] - fo).max() / np.abs(fo).max()
+        assert e <= tf, (label, b, e)
+        assert np.array_equal(kind[s0:s0 + N], o.site_kind().ravel()), (label, b)
+        worst[0] = max(worst[0], e)
+        if n:
+            Fo, To, xo, uo, wo = o.forces()
+            scale = max(np.linalg.norm(Fo, axis=1).max(), 1e-30)
+            eF = np.linalg.norm(F[p0:p0 + n] - Fo, axis=1).max() / scale
+            assert eF <= tF, (label, b, eF)
+            worst[1] = max(worst[1], eF)
+            assert np.array_equal(sim.shifts()[p0:p0 + n], o.shifts()), (label, b)
+            assert np.abs(x[p0:p0 + n] - xo).max() <= tF * max(np.abs(xo - x[p0:p0 + n]).max(), 1.0)
+    return worst
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_ensemble_2d_matches_one_oracle_per_box(storage):
+    dims, parts = _boxes_2d()
+    sim, oras = _make(9, dims, parts, storage, (0.0, -2e-4, 0.0))
+    _say("ensemble 2d", storage, dims)
+    for t in range(3):
+        if t == 1:
+            sim.set_sweep_config(256, 0)
+        if t == 2:
+            sim.set_sweep_config(64, 8)  # persistent: 8 workgroups walk every tile
+        sim.step(20)
+        for o in oras:
+            o.step(20)
+        e = _compare(sim, oras, storage, "step %d" % (20 * (t + 1)))
+        _say("  step", 20 * (t + 1), "e_f", e[0], "e_F", e[1])
+
+
+def test_ensemble_3d_matches_one_oracle_per_box():
+    dims, parts = _boxes_3d()
+    sim, oras = _make(19, dims, parts, "fp64", (0.0, 0.0, -2e-4), tau=0.8)
+    _say("ensemble 3d", dims)
+    for t in range(2):
+        sim.step(15)
+        for o in oras:
+            o.step(15)
+        e = _compare(sim, oras, "fp64", "step %d" % (15 * (t + 1)))
+        _say("  e_f", e[0], "e_F", e[1])
+
+
+def _state(sim):
+    F, T, x, u, om = sim.forces()
+    return sim.get_distributions(), F, x
+
+
+def _same(a, b):
+    return all(np.array_equal(p, q) for p, q in zip(a, b))
+
+
+def test_sweep_shapes_and_autotune_give_identical_bits():
+    """One box: the row kernel, tile kernels of every width, a persistent grid
+    and the autotuner's pick all produce the same state after 30 steps."""
+    box = (70, 45, 1)
+    p = wl.suspension(9, box, 3, 5.0, 1.5, seed=81)
+    ref = None
+    for shape in [(0, 0), (64, 0), (128, 16), (512, 0), "auto"]:
+        sim = lbm.Simulation(9, *box, tau=0.7, gravity=(0, -1e-4, 0), zero_net_force=True, storage="fp32",
+                             max_particles=3, max_radius=5.0)
+        sim.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
+        sim.step(3)
+        if shape == "auto":
+            w, g, ms = sim.autotune(reps=3)
+            _say("autotune picked", w, g, ms)
+            assert sim.sweep_config() == (w, g)
+        else:
+            sim.set_sweep_config(*shape)
+        sim.step(27)
+        st = _state(sim)
+        if ref is None:
+            ref = st
+        assert _same(st, ref), shape
+        sim.close()
+
+
+def test_ensemble_autotune_keeps_the_state():
+    cfg = wl.ensemble_2d_config(seed=5, nbox=6)
+    dims = [tuple(int(v) for v in d) for d in cfg["boxes"]]
+    runs = []
+    for tune in (False, True):
+        n = sum(len(p["radius"]) for p in cfg["particles"])
+        sim = lbm.Simulation(9, 1, 1, 1, tau=0.7, gravity=cfg["gravity"], zero_net_force=True, storage="fp32",
+                             max_particles=n, max_radius=12.0, boxes=dims)
+        for b, p in enumerate(cfg["particles"]):
+            sim.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"], box=b)
+        sim.step(4)
+        if tune:
+            _say("ensemble autotune", sim.autotune(reps=2))
+        sim.step(16)
+        runs.append(_state(sim))
+        sim.close()
+    assert _same(runs[0], runs[1])
+
+
+def test_graph_replays_match_eager_launches():
+    """Graph replays of 4 steps, with eager steps, read-outs and a particle
+    added in between, give the same bits as eager launches every time."""
+    dims, parts = _boxes_2d()
+    sims = []
+    for graph in (0, 4):
+        sim, _ = _make(9, dims, parts, "fp32", (0.0, -2e-4, 0.0), extra=1)
+        sim.set_graph(graph)
+        sims.append(sim)
+    plan = [8, 3, 4, 1, 12]  # odd counts change the buffer parity: recapture
+    for k, n in enumerate(plan):
+        for sim in sims:
+            sim.step(n)
+        a, b = _state(sims[0]), _state(sims[1])
+        assert _same(a, b), ("after chunk", k)
+        _say("graph chunk", k, "equal")
+    # a new particle (box 5 is the last box with particles) invalidates the graph
+    for sim in sims:
+        sim.add_particles([[100.0, 12.0, 0.0]], radius=4.0, mass=75.0, inertia=600.0, box=5)
+        sim.step(8)
+    assert _same(_state(sims[0]), _state(sims[1]))
+
+
+def test_ensemble_argument_errors():
+    dims = [(40, 36, 1), (30, 30, 1)]
+    sim = lbm.Simulation(9, 1, 1, 1, tau=0.8, storage="fp64", max_particles=4, max_radius=5.0, boxes=dims)
+    with pytest.raises(lbm.LbmError) as e:
+        sim.add_particles([[10, 10, 0]], radius=4.0, mass=10.0, inertia=10.0, box=2)
+    assert e.value.code == lbm.LBM_EINVAL
+    with pytest.raises(lbm.LbmError) as e:  # outside box 1 (30 wide), inside box 0
+        sim.add_particles([[35, 10, 0]], radius=4.0, mass=10.0, inertia=10.0, box=1)
+    assert e.value.code == lbm.LBM_EINVAL
+    assert sim.add_particles([[10, 10, 0]], radius=4.0, mass=10.0, inertia=10.0, box=1) == 0
+    with pytest.raises(lbm.LbmError) as e:  # boxes are filled in order
+        sim.add_particles([[10, 10, 0]], radius=4.0, mass=10.0, inertia=10.0, box=0)
+    assert e.value.code == lbm.LBM_EINVAL
+    # the same position in another box is no overlap; in the same box it is
+    with pytest.raises(lbm.LbmError) as e:
+        sim.add_particles([[12, 10, 0]], radius=4.0, mass=10.0, inertia=10.0, box=1)
+    assert e.value.code == lbm.LBM_EOVERLAP
+    with pytest.raises(lbm.LbmError) as e:
+        sim.set_sweep_config(0, 0)  # the row kernel covers one box
+    assert e.value.code == lbm.LBM_EINVAL
+    with pytest.raises(lbm.LbmError) as e:
+        sim.set_graph(3)
+    assert e.value.code == lbm.LBM_EINVAL
+    sim.step(2)
+    sim.forces()
