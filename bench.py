@@ -9,7 +9,9 @@ particle update, map rebuild, IS substep) over the box.  Prints one JSON line.
                   [--no-cpu-baseline] [--no-variants] [--workload spheres-3d|disks-2d]
 
 The FP32 run also times the FP16 and BF16 storage variants of the same
-workload ("variants") and the FP64 oracle on a few steps of the same box
+workload ("variants"), a 64-box D2Q9 ensemble stepped by one launch per
+kernel with a tuned sweep shape and step graphs against a loop of one-box
+contexts ("batched"), and the FP64 oracle on a few steps of the same box
 ("cpu_baseline").
 """
 import argparse
@@ -17,6 +19,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -79,6 +83,63 @@ def cpu_baseline(cfg, steps):
                       % (steps, dt)}
 
 
+def ensemble_rates(torch, lbm, wl, steps, warmup, graph_steps=20):
+    """The 64-box D2Q9 ensemble (seeded sides 128..512, 10..80 disks of radius
+    6..12): MLUPS of one ensemble context with eager launches, of the same
+    context after autotuning and with step graphs, and of a loop over 64
+    one-box contexts (each box's steps launched back to back)."""
+    cfg = wl.ensemble_2d_config()
+    dims = [tuple(int(v) for v in d) for d in cfg["boxes"]]
+    NT = int(np.prod(cfg["boxes"], axis=1).sum())
+    npart = sum(len(p["radius"]) for p in cfg["particles"])
+    kw = dict(tau=cfg["tau"], gravity=cfg["gravity"], zero_net_force=True, storage="fp32", max_radius=12.0)
+
+    def clock(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    ens = lbm.Simulation(9, 1, 1, 1, max_particles=npart, boxes=dims, **kw)
+    for b, p in enumerate(cfg["particles"]):
+        ens.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"], box=b)
+    ens.step(warmup)
+    ms_eager = clock(lambda: ens.step(steps))
+    width, grid, _ = ens.autotune(reps=5)
+    ens.set_graph(graph_steps)
+    ens.step(max(warmup, graph_steps))
+    ms_graph = clock(lambda: ens.step(steps))
+    assert np.isfinite(ens.forces()[0]).all()
+    ens.close()
+    singles = []
+    for d, p in zip(dims, cfg["particles"]):
+        s1 = lbm.Simulation(9, *d, max_particles=len(p["radius"]), **kw)
+        s1.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
+        s1.step(warmup)
+        singles.append(s1)
+
+    def loop():
+        for s1 in singles:
+            s1.step(steps)
+    ms_loop = clock(loop)
+    for s1 in singles:
+        s1.close()
+    rate = lambda ms: NT * steps / (ms * 1e-3) / 1e6
+    return {"workload": cfg["name"], "boxes": len(dims), "sites": NT, "particles": npart,
+            "clipped_particles": int(sum(cfg["clipped"])), "steps": steps,
+            "value": round(rate(ms_graph), 1), "unit": "MLUPS",
+            "ms_per_step": round(ms_graph / steps, 4),
+            "eager_one_launch_per_kernel": round(rate(ms_eager), 1),
+            "loop_of_single_boxes": round(rate(ms_loop), 1),
+            "speedup_vs_loop": round(ms_loop / ms_graph, 2),
+            "tuned_sweep_shape": {"tile_width": width, "grid": grid}, "graph_steps": graph_steps,
+            "step_roofline_frac": round(72 * rate(ms_graph) * 1e6 / 1e9 / PEAK_HBM_GBPS, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +155,9 @@ def main():
     ap.add_argument("--workload", default="spheres-3d", choices=["spheres-3d", "disks-2d"],
                     help="spheres-3d: D3Q19 256^3, 500 spheres (the headline); "
                          "disks-2d: D2Q9 1024^2, 200 disks")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip timing the 64-box D2Q9 ensemble (batched) variant")
+    ap.add_argument("--batched-steps", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -202,6 +266,9 @@ def main():
                                    "sweep_avg_ms": round(vs, 4), "sweep_GBps": round(vb * N / (vs * 1e-3) / 1e9, 1)}
             v.close()
             print("variant %s timed" % st, file=sys.stderr, flush=True)
+    if not args.no_batched and args.storage == "fp32" and args.workload == "spheres-3d":
+        out["batched"] = ensemble_rates(torch, lbm, wl, args.batched_steps, args.warmup)
+        print("batched ensemble timed", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline and args.workload == "spheres-3d":
         print("cpu baseline: %d oracle steps" % args.cpu_steps, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
