@@ -221,6 +221,34 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* width, int32_t* grid, doub
  * Synchronises. */
 int lbm_set_graph(lbm_ctx* ctx, int32_t steps_per_graph);
 
+/* ---- near-contact closure network ---------------------------------------
+ * A perceptron 8 -> 64 -> 64 -> 2 with tanh hidden units:
+ *   y = tanh(tanh(x W1 + b1) W2 + b2) W3 + b3,
+ * run on the matrix cores with FP16 inputs, weights and hidden activations and
+ * FP32 sums.  Parameters are one flat FP32 device vector: W1 [8][64], b1 [64],
+ * W2 [64][64], b2 [64], W3 [64][2], b3 [2], row-major (lbm_mlp_param_count
+ * values).  Rows of x are [n][8] FP32, of y and targets t [n][2] FP32, all
+ * device memory; every call only enqueues on hip_stream.  The loss over B rows
+ * is (1/B) sum (y - t)^2; backward signals are multiplied by loss_scale before
+ * their FP16 rounding and the gradients divided by it again. */
+int lbm_mlp_param_count(int32_t* n);
+int lbm_mlp_forward(const float* d_params, const float* d_x, float* d_y, int64_t n, void* hip_stream);
+
+/* Loss (d_loss[0], may be NULL) and its gradient (d_grad, one value per
+ * parameter) over all n rows; n >= 1. */
+int lbm_mlp_gradient(const float* d_params, const float* d_x, const float* d_t, int32_t n, float loss_scale,
+                     float* d_grad, float* d_loss, void* hip_stream);
+
+/* `steps` Adam steps (Kingma & Ba 2015; beta 0.9, 0.999, eps 1e-8, learning
+ * rate lr) on mini-batches of `batch` rows (a multiple of 64) taken in order,
+ * cycling through the n rows: step s uses rows (s * batch + j) mod n.  step0
+ * is the number of steps already taken (bias correction, row position).
+ * d_adam_m, d_adam_v hold the moment estimates (zero before the first step);
+ * d_loss, if not NULL, receives the loss of every step. */
+int lbm_mlp_train(float* d_params, float* d_adam_m, float* d_adam_v, const float* d_x, const float* d_t,
+                  int32_t n, int32_t batch, int32_t steps, int32_t step0, float lr, float loss_scale,
+                  float* d_loss, void* hip_stream);
+
 /* Algorithmic HBM bytes one sweep moves per site (2 q sizeof(storage)). */
 int lbm_bytes_per_site(const lbm_params* prm, int64_t* bytes);
 

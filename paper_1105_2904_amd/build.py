@@ -4,8 +4,9 @@ import subprocess
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(_HERE)
-SOURCES = [os.path.join(_HERE, "csrc", "lbm.hip")]
-HEADERS = [os.path.join(_HERE, "csrc", "lattice.h"), os.path.join(ROOT, "include", "lbm.h")]
+SOURCES = [os.path.join(_HERE, "csrc", "lbm.hip"), os.path.join(_HERE, "csrc", "mlp.hip")]
+HEADERS = [os.path.join(_HERE, "csrc", "lattice.h"), os.path.join(_HERE, "csrc", "mlp_core.h"),
+           os.path.join(ROOT, "include", "lbm.h")]
 OUT = os.path.join(_HERE, "liblbm.so")
 
 HIPCC_FLAGS = [

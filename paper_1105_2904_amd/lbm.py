@@ -75,6 +75,11 @@ def lib():
             "lbm_get_sweep_config": [vp, _ip, _ip],
             "lbm_autotune": [vp, ctypes.c_int32, _ip, _ip, _dp],
             "lbm_set_graph": [vp, ctypes.c_int32],
+            "lbm_mlp_param_count": [_ip],
+            "lbm_mlp_forward": [vp, vp, vp, ctypes.c_int64, vp],
+            "lbm_mlp_gradient": [vp, vp, vp, ctypes.c_int32, ctypes.c_float, vp, vp, vp],
+            "lbm_mlp_train": [vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                              ctypes.c_float, ctypes.c_float, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -308,3 +313,49 @@ class Simulation:
         ms, n = ctypes.c_double(), ctypes.c_int64()
         _check(lib().lbm_profile(self.ctx, ctypes.byref(ms), ctypes.byref(n)), "lbm_profile")
         return ms.value, n.value
+
+
+# ---- closure network: torch CUDA float32 tensors in, kernels of liblbm.so ----
+def _ptr(t):
+    import torch
+    assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous(), "float32 contiguous CUDA tensor expected"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    return ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+
+
+def mlp_param_count():
+    n = ctypes.c_int32()
+    _check(lib().lbm_mlp_param_count(ctypes.byref(n)), "lbm_mlp_param_count")
+    return n.value
+
+
+def mlp_forward(params, x, stream=None):
+    """y [n, 2] of the network with flat parameters `params` on inputs x [n, 8]."""
+    import torch
+    y = torch.empty((x.shape[0], 2), dtype=torch.float32, device=x.device)
+    _check(lib().lbm_mlp_forward(_ptr(params), _ptr(x), _ptr(y), x.shape[0], _stream(stream)), "lbm_mlp_forward")
+    return y
+
+
+def mlp_gradient(params, x, t, loss_scale=1024.0, stream=None):
+    """(loss, gradient) over all rows."""
+    import torch
+    g = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float32, device=params.device)
+    _check(lib().lbm_mlp_gradient(_ptr(params), _ptr(x), _ptr(t), x.shape[0], float(loss_scale), _ptr(g),
+                                  _ptr(loss), _stream(stream)), "lbm_mlp_gradient")
+    return loss, g
+
+
+def mlp_train(params, adam_m, adam_v, x, t, batch, steps, step0=0, lr=1e-3, loss_scale=1024.0, stream=None):
+    """Adam steps in place on params; returns the per-step losses."""
+    import torch
+    losses = torch.empty(max(steps, 1), dtype=torch.float32, device=params.device)
+    _check(lib().lbm_mlp_train(_ptr(params), _ptr(adam_m), _ptr(adam_v), _ptr(x), _ptr(t), x.shape[0], int(batch),
+                               int(steps), int(step0), float(lr), float(loss_scale), _ptr(losses), _stream(stream)),
+           "lbm_mlp_train")
+    return losses[:steps]

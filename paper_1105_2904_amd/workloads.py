@@ -168,3 +168,21 @@ def ensemble_2d_config(seed=4, nbox=64, phi_max=0.25):
     return {"name": "d2q9-ensemble-%d-boxes" % nbox, "q": 9, "boxes": np.array(boxes, dtype=np.int32),
             "tau": 0.7, "rho0": 1.0, "gravity": (0.0, -1e-5, 0.0), "zero_net_force": True,
             "storage": "fp32", "steps": 10000, "particles": parts, "clipped": clipped}
+
+
+MLP_SHAPES = [(8, 64), (64,), (64, 64), (64,), (64, 2), (2,)]
+
+
+def mlp_init(seed):
+    """Initial parameters of the 8 -> 64 -> 64 -> 2 closure network as one flat
+    FP32-representable vector (W1, b1, W2, b2, W3, b3, row-major): Glorot-uniform
+    weights (Glorot & Bengio, AISTATS 2010) from numpy's PCG64, zero biases."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for shp in MLP_SHAPES:
+        if len(shp) == 2:
+            lim = math.sqrt(6.0 / (shp[0] + shp[1]))
+            parts.append(rng.uniform(-lim, lim, size=shp).ravel())
+        else:
+            parts.append(np.zeros(shp))
+    return np.concatenate(parts).astype(np.float32).astype(np.float64)
