@@ -63,6 +63,14 @@ def lib():
         L.ora_feq.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp]
         L.ora_set_walls.restype = ctypes.c_int
         L.ora_set_walls.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp]
+        L.ora_set_closure.restype = ctypes.c_int
+        L.ora_set_closure.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double]
+        L.ora_closure_inputs.restype = ctypes.c_int
+        L.ora_closure_inputs.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _dp]
+        L.ora_closure_net.restype = ctypes.c_int
+        L.ora_closure_net.argtypes = [_dp, _dp, _dp]
+        L.ora_half.restype = ctypes.c_double
+        L.ora_half.argtypes = [ctypes.c_double]
         _lib = L
     return _lib
 
@@ -83,6 +91,20 @@ def lattice(q):
     if lib().ora_lattice(q, c.ctypes.data_as(_ip), _d(w)) != 0:
         raise ValueError("unknown lattice q=%d" % q)
     return c, w
+
+
+def closure_net(params, x):
+    """The closure network of the oracle on inputs x [n, 8] -> [n, 2]."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 8)
+    y = np.zeros((x.shape[0], 2))
+    for k in range(x.shape[0]):
+        lib().ora_closure_net(_d(p), _d(x[k]), y[k].ctypes.data_as(_dp))
+    return y
+
+
+def half(x):
+    return lib().ora_half(float(x))
 
 
 def feq(q, rho, u):
@@ -191,6 +213,17 @@ class Oracle:
         kind = np.zeros(max(n, 1), dtype=np.int8)
         lib().ora_template(self._h, p, None, None, off.ctypes.data_as(_ip), kind.ctypes.data_as(_bp))
         return off[:n], kind[:n]
+
+    def set_closure(self, params, h_max=2.0):
+        p = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+        if lib().ora_set_closure(self._h, _d(p), float(h_max)) != 0:
+            raise ValueError("invalid closure parameters")
+
+    def closure_inputs(self, i, j):
+        x = np.zeros(8)
+        if lib().ora_closure_inputs(self._h, int(i), int(j), _d(x)) != 0:
+            raise ValueError("invalid pair")
+        return x
 
     def diagnostics(self):
         d = np.zeros(17)

@@ -99,6 +99,10 @@ struct ora_sim {
   int walls;              /* bit a: axis a closed by wall layers */
   double wall_u[3][2][3]; /* [axis][low, high][component] */
   double wall_dp[3];      /* momentum the walls gave the fluid, last step */
+  int closure;            /* near-contact closure network on */
+  double clo_p[4866];     /* its parameters (FP32 values) */
+  double clo_h;           /* gap below which it acts */
+  double (*Fc)[3];        /* closure force of the last step, per particle */
 };
 
 static long site_index(const ora_sim *s, long x, long y, long z) {
@@ -176,6 +180,7 @@ void ora_destroy(ora_sim *s) {
   if (!s) return;
   for (int p = 0; p < s->np; p++) free(s->P[p].off);
   free(s->P);
+  free(s->Fc);
   free(s->f);
   free(s->fs);
   free(s->own_p);
@@ -280,6 +285,8 @@ static void cross(const double a[3], const double b[3], double out[3]) {
   out[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+static double min_image(double d, int n) { return d - n * floor(d / n + 0.5); }
+
 /* Rasterise every particle at b0 + k (section 2.2, integer counterpart [x]).
  * A site claimed by two particles belongs to the lower id (the paper is
  * silent on overlapping site sets). */
@@ -329,6 +336,9 @@ int ora_add_particles(ora_sim *s, int n, const double *x, const double *u,
     particle *np = (particle *)realloc(s->P, sizeof(particle) * nc);
     if (!np) return -1;
     s->P = np;
+    double(*fc)[3] = (double(*)[3])realloc(s->Fc, sizeof(double[3]) * nc);
+    if (!fc) return -1;
+    s->Fc = fc;
     s->cap = nc;
   }
   for (int j = 0; j < n; j++) {
@@ -468,6 +478,107 @@ static void wall_substep(ora_sim *s) {
       }
 }
 
+/* ------------------------------------------------------------------------
+ * Near-contact closure (not in the paper: it leaves lubrication untreated,
+ * section 2.3).  A perceptron 8 -> 64 -> 64 -> 2 with tanh hidden units maps
+ * the geometry of a close pair to the force the coarse lattice misses, in
+ * units of mu U (2D Stokes forces per unit depth are mu U times a function of
+ * the geometry).  Readings of the closure, shared with the GPU:
+ *  - every pair i < j whose surface gap h = |d| - r_i - r_j is below clo_h
+ *    at the start of the step (minimum image); kinematic particles report
+ *    the force but keep their velocity, as for the hydrodynamic force;
+ *  - inputs: h, (r_i - 9)/3, (r_j - 9)/3, the unit vector n from i to j, the
+ *    offset of the gap midpoint x_i + n (r_i + h/2) from its nearest site,
+ *    and (tau - 0.7)/0.1; computed in FP64, rounded to FP32 and then FP16;
+ *  - outputs (a_n, a_t): force on i = mu U (a_n n + a_t t), t = (-n_y, n_x),
+ *    mu = rho0 nu, U = (u_i - u_j).n (approach speed); j takes the opposite;
+ *  - the network rounds its inputs, weights and hidden activations to FP16
+ *    (nearest even) and sums exactly;
+ *  - the closure force joins the hydrodynamic force in the acceleration
+ *    substep and in the reported F, before the hard-core collisions.
+ * 2D only.
+ * ---------------------------------------------------------------------- */
+
+/* Round to the nearest IEEE binary16 value, ties to even (11 significant
+ * bits, quantum 2^-24 below the smallest normal, overflow to infinity). */
+static double to_half(double x) {
+  if (x == 0.0 || x != x) return x;
+  double a = fabs(x);
+  if (a >= 65520.0) return copysign(INFINITY, x);
+  int e;
+  frexp(a, &e);
+  double q = e >= -13 ? ldexp(1.0, e - 11) : ldexp(1.0, -24);
+  return copysign(nearbyint(a / q) * q, x);
+}
+
+static double fp32_then_half(double x) { return to_half((double)(float)x); }
+
+static void closure_inputs(const ora_sim *s, const particle *A, const particle *B,
+                           const double d[3], double dist, double in[8]) {
+  double n[2] = {d[0] / dist, d[1] / dist};
+  double h = dist - A->r - B->r;
+  double mx = A->x[0] + n[0] * (A->r + 0.5 * h), my = A->x[1] + n[1] * (A->r + 0.5 * h);
+  in[0] = h;
+  in[1] = (A->r - 9.0) / 3.0;
+  in[2] = (B->r - 9.0) / 3.0;
+  in[3] = n[0];
+  in[4] = n[1];
+  in[5] = mx - floor(mx + 0.5);
+  in[6] = my - floor(my + 0.5);
+  in[7] = (s->tau - 0.7) / 0.1;
+}
+
+/* y = tanh(tanh(x W1 + b1) W2 + b2) W3 + b3 at the FP16 rounding points. */
+static void closure_net(const double *p, const double in[8], double y[2]) {
+  const double *W1 = p, *b1 = p + 512, *W2 = p + 576, *b2 = p + 4672, *W3 = p + 4736, *b3 = p + 4864;
+  double x[8], h1[64], h2[64];
+  for (int k = 0; k < 8; k++) x[k] = fp32_then_half(in[k]);
+  for (int m = 0; m < 64; m++) {
+    double z = b1[m];
+    for (int k = 0; k < 8; k++) z += x[k] * to_half(W1[k * 64 + m]);
+    h1[m] = to_half(tanh(z));
+  }
+  for (int m = 0; m < 64; m++) {
+    double z = b2[m];
+    for (int k = 0; k < 64; k++) z += h1[k] * to_half(W2[k * 64 + m]);
+    h2[m] = to_half(tanh(z));
+  }
+  for (int o = 0; o < 2; o++) {
+    double z = b3[o];
+    for (int k = 0; k < 64; k++) z += h2[k] * to_half(W3[k * 2 + o]);
+    y[o] = z;
+  }
+}
+
+static void closure_forces(ora_sim *s) {
+  for (int p = 0; p < s->np; p++)
+    for (int a = 0; a < 3; a++) s->Fc[p][a] = 0.0;
+  if (!s->closure) return;
+  int L[3] = {s->nx, s->ny, s->nz};
+  double mu = s->rho0 * (s->tau - 0.5) / 3.0;
+  for (int i = 0; i < s->np; i++)
+    for (int j = i + 1; j < s->np; j++) {
+      particle *A = &s->P[i], *B = &s->P[j];
+      double d[3] = {0, 0, 0}, dd = 0;
+      for (int a = 0; a < 2; a++) {
+        d[a] = min_image(B->x[a] - A->x[a], L[a]);
+        dd += d[a] * d[a];
+      }
+      double dist = sqrt(dd);
+      if (!(dist - A->r - B->r < s->clo_h) || dist == 0.0) continue;
+      double in[8], y[2];
+      closure_inputs(s, A, B, d, dist, in);
+      closure_net(s->clo_p, in, y);
+      double n[2] = {d[0] / dist, d[1] / dist}, t[2] = {-n[1], n[0]};
+      double U = (A->u[0] - B->u[0]) * n[0] + (A->u[1] - B->u[1]) * n[1];
+      for (int a = 0; a < 2; a++) {
+        double f = mu * U * (y[0] * n[a] + y[1] * t[a]);
+        s->Fc[i][a] += f;
+        s->Fc[j][a] -= f;
+      }
+    }
+}
+
 /* Second substep (eq. 10-11): the particle takes the opposite change.  The
  * buoyancy-corrected weight is added (the settling runs of section 3 need it
  * though eq. 10 omits it).  Kinematic particles keep their velocities. */
@@ -475,17 +586,16 @@ static void accelerate(ora_sim *s, double (*dP)[3], double (*dL)[3]) {
   for (int p = 0; p < s->np; p++) {
     particle *P = &s->P[p];
     for (int a = 0; a < 3; a++) {
-      P->F[a] = -dP[p][a];
+      P->F[a] = -dP[p][a] + s->Fc[p][a];
       P->T[a] = -dL[p][a];
     }
     if (!isinf(P->m))
-      for (int a = 0; a < 3; a++) P->u[a] = P->u[a] + (P->fext[a] - dP[p][a]) / P->m;
+      for (int a = 0; a < 3; a++) P->u[a] = P->u[a] + (P->fext[a] - dP[p][a] + s->Fc[p][a]) / P->m;
     if (!isinf(P->I))
       for (int a = 0; a < 3; a++) P->om[a] = P->om[a] - dL[p][a] / P->I;
   }
 }
 
-static double min_image(double d, int n) { return d - n * floor(d / n + 0.5); }
 
 /* Hard-core collisions (eq. 16-19): in the pair's centre-of-mass frame the
  * normal velocities reverse and the tangential ones are kept; applied as
@@ -608,6 +718,7 @@ void ora_step(ora_sim *s, int nsteps) {
     collide(s);
     boundary_substep(s, dP, dL);
     wall_substep(s);
+    closure_forces(s);
     accelerate(s, dP, dL);
     collisions(s);
     wall_collisions(s);
@@ -720,6 +831,36 @@ void ora_diagnostics(const ora_sim *s, double *d) {
   d[10] = (double)s->step;
   for (int a = 0; a < 3; a++) d[11 + a] = s->fb[a];
   for (int a = 0; a < 3; a++) d[14 + a] = s->wall_dp[a];
+}
+
+int ora_set_closure(ora_sim *s, const double *params, double h_max) {
+  if (s->dim != 2 || !(h_max >= 0.0)) return -1;
+  s->closure = params != NULL && h_max > 0.0;
+  if (params)
+    for (int k = 0; k < 4866; k++) s->clo_p[k] = (double)(float)params[k];
+  s->clo_h = h_max;
+  return 0;
+}
+
+double ora_half(double x) { return to_half(x); }
+
+int ora_closure_inputs(const ora_sim *s, int i, int j, double *in) {
+  if (i < 0 || j < 0 || i >= s->np || j >= s->np || i == j) return -1;
+  int L[3] = {s->nx, s->ny, s->nz};
+  double d[3] = {0, 0, 0}, dd = 0;
+  for (int a = 0; a < 2; a++) {
+    d[a] = min_image(s->P[j].x[a] - s->P[i].x[a], L[a]);
+    dd += d[a] * d[a];
+  }
+  closure_inputs(s, &s->P[i], &s->P[j], d, sqrt(dd), in);
+  return 0;
+}
+
+int ora_closure_net(const double *params, const double *in, double *y) {
+  double p[4866];
+  for (int k = 0; k < 4866; k++) p[k] = (double)(float)params[k];
+  closure_net(p, in, y);
+  return 0;
 }
 
 int ora_set_walls(ora_sim *s, int walls, const double *wall_u) {

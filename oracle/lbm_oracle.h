@@ -97,6 +97,20 @@ void ora_diagnostics(const ora_sim *s, double *d);
  * be 0.  Call before adding particles.  Returns 0, or -1 on invalid input. */
 int ora_set_walls(ora_sim *s, int walls, const double *wall_u);
 
+/* Near-contact closure network (2D): params are the 4866 network parameters
+ * (W1 [8][64], b1, W2 [64][64], b2, W3 [64][2], b3; taken as FP32 values),
+ * h_max the gap below which it acts (0 or params NULL: off).  Returns 0, or
+ * -1 for a 3D box or a negative h_max. */
+int ora_set_closure(ora_sim *s, const double *params, double h_max);
+
+/* The closure's 8 inputs for particles i, j at the current positions, and
+ * the network alone on given inputs (its FP16 rounding points included). */
+int ora_closure_inputs(const ora_sim *s, int i, int j, double *in);
+int ora_closure_net(const double *params, const double *in, double *y);
+
+/* Nearest IEEE binary16 value (ties to even). */
+double ora_half(double x);
+
 int ora_num_particles(const ora_sim *s);
 
 #ifdef __cplusplus
