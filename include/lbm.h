@@ -249,6 +249,29 @@ int lbm_mlp_train(float* d_params, float* d_adam_m, float* d_adam_v, const float
                   int32_t n, int32_t batch, int32_t steps, int32_t step0, float lr, float loss_scale,
                   float* d_loss, void* hip_stream);
 
+/* Near-contact closure in the step (2D only; LBM_EUNSUPPORTED in 3D).  The
+ * paper leaves lubrication untreated (section 2.3); with the closure on,
+ * every pair i < j of a box whose surface gap h = |d| - r_i - r_j is below
+ * h_max at the start of a step gets from the network (parameters d_params,
+ * copied into the context) the force on i
+ *     mu U (a_n n + a_t t),  n = d/|d|, t = (-n_y, n_x), mu = rho0 (tau - 1/2)/3,
+ *     U = (u_i - u_j).n (approach speed),
+ * and j the opposite.  The inputs are h, (r_i - 9)/3, (r_j - 9)/3, n_x, n_y,
+ * the offset of the gap midpoint x_i + n (r_i + h/2) from its nearest site
+ * (per axis, in [-1/2, 1/2)) and (tau - 0.7)/0.1 (lbm_closure_inputs).  The
+ * force joins the hydrodynamic force in the acceleration (eq. 10) and in the
+ * reported F, before the hard-core collisions, which still apply; kinematic
+ * particles report it and keep their velocity.  d_params NULL or h_max 0
+ * switches it off.  More than 1024 such pairs in a step are reported as
+ * LBM_ECAPACITY by the next synchronising call.  Synchronises. */
+int lbm_set_closure(lbm_ctx* ctx, const float* d_params, double h_max);
+
+/* The closure's inputs for n pairs (host arrays): xi [n][2] centre of i,
+ * d [n][2] minimum-image separation from i to j, ri, rj [n], relaxation time
+ * tau; out [n][8] FP32. */
+int lbm_closure_inputs(int32_t n, const double* xi, const double* d, const double* ri, const double* rj,
+                       double tau, float* out);
+
 /* Algorithmic HBM bytes one sweep moves per site (2 q sizeof(storage)). */
 int lbm_bytes_per_site(const lbm_params* prm, int64_t* bytes);
 

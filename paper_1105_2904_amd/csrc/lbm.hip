@@ -45,6 +45,7 @@
 
 #include "lattice.h"
 #include "lbm.h"
+#include "mlp_core.h"
 
 namespace {
 
@@ -57,6 +58,8 @@ constexpr int kTileMax = 512;        // widest tile of the ensemble sweep
 constexpr int kBoundaryBlock = 256;  // reduce workgroup
 constexpr int kParticleBlock = 1024;
 constexpr int kStatusCollision = 1;
+constexpr int kStatusClosure = 2;     // more close pairs than kClosurePairs
+constexpr int kClosurePairs = 1024;   // close pairs one step of the closure handles
 constexpr size_t kAlign = 256;
 
 // ---------------------------------------------------------------------------
@@ -171,6 +174,7 @@ struct DevParticles {
   double *m, *I, *rad;                                     // [n]
   int *b0, *k, *org;                                       // [n][3]; org = b0 + k wrapped into the box
   int *ent0, *nbs, *nis, *nin, *cand_n, *jump, *box;       // [n]
+  double* fc;                                              // [n][3] closure force of the step
   int *cand;                                               // [n][kCandMax]
   int *pairs;                                              // [n*kCandMax][2]
 };
@@ -464,11 +468,11 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int np, int di
     const double m = P.m[p], I = P.I[p];
     double v2 = 0;
     for (int a = 0; a < 3; a++) {
-      const double dp = P.dP[3 * p + a], dl = P.dL[3 * p + a];
-      P.F[3 * p + a] = -dp;
+      const double dp = P.dP[3 * p + a], dl = P.dL[3 * p + a], fc = P.fc[3 * p + a];
+      P.F[3 * p + a] = -dp + fc;
       P.T[3 * p + a] = -dl;
       double u = P.u[3 * p + a];
-      if (!isinf(m)) u = u + (P.fext[3 * p + a] - dp) / m;
+      if (!isinf(m)) u = u + (P.fext[3 * p + a] - dp + fc) / m;
       P.u[3 * p + a] = u;
       if (!isinf(I)) P.om[3 * p + a] = P.om[3 * p + a] - dl / I;
       v2 += u * u;
@@ -589,7 +593,7 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int np, int di
 __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own, int* __restrict__ ball,
                                                             const double* __restrict__ slot,
                                                             DevParticles P, DevEntries E, Boxes BX,
-                                                            double rho0, int* status) {
+                                                            double rho0, double margin, int* status) {
   constexpr int kWaves = kBoundaryBlock / 64;
   __shared__ double s_part[kWaves][6];
   __shared__ int s_cnt[kWaves];
@@ -666,7 +670,8 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
   // Close neighbours j > p in the same box (positions before translation),
   // listed in increasing j: the only pairs that can pass the collision test
   // this step while every speed stays below kMargin / 2 (checked in the
-  // particle update).
+  // particle update), and, with margin >= the closure's gap, every pair the
+  // closure acts on.
   const double xpx = P.x[3 * p], xpy = P.x[3 * p + 1], xpz = P.x[3 * p + 2];
   const double rp = P.rad[p];
   const int np = G.p1;
@@ -679,7 +684,7 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
       dx -= G.nx * floor(dx / G.nx + 0.5);
       dy -= G.ny * floor(dy / G.ny + 0.5);
       if (G.nz > 1) dz -= G.nz * floor(dz / G.nz + 0.5);
-      const double lim = rp + P.rad[j] + kMargin;
+      const double lim = rp + P.rad[j] + margin;
       close = dx * dx + dy * dy + dz * dz <= lim * lim;
     }
     const unsigned long long bal = __ballot(close);
@@ -726,6 +731,126 @@ __global__ __launch_bounds__(256) void k_stamp(int* __restrict__ own, int* __res
   const int kind = entry_kind(pk);
   // wall sites belong to the wall
   if (kind != 3 && !wall_site(G, x, y, z)) atomicMin(&own[s], 2 * e + (kind == 2));
+}
+
+// ---------------------------------------------------------------------------
+// Near-contact closure (2D; not in the paper, which leaves lubrication
+// untreated, section 2.3): one workgroup.  Pairs i < j of a box whose surface
+// gap is below h_max at the start of the step are listed in lexicographic
+// order (from the candidate lists), the network gives (a_n, a_t) for each
+// pair on the matrix cores, 16 pairs per wave tile, and every particle sums
+// mu U (a_n n + a_t t) over its pairs in list order (+ as i, - as j), with U
+// = (u_i - u_j).n the approach speed.  The particle update adds it to the
+// hydrodynamic force.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_closure(DevParticles P, int np, Boxes BX, const float* __restrict__ params,
+                                                  double h_max, double mu, double tau, int* status) {
+  __shared__ mlp::Weights w;
+  __shared__ int s_i[kClosurePairs], s_j[kClosurePairs];
+  __shared__ float s_a[kClosurePairs][2];
+  __shared__ int s_scan[256];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  mlp::load_weights(w, params, tid, 256);
+  __syncthreads();
+  // list of close pairs
+  int total = 0;
+  for (int b = 0; b < np; b += 256) {
+    const int p = b + tid;
+    int c = 0;
+    if (p < np) {
+      const Geo G = geo_of(BX, P, p);
+      for (int t = 0; t < P.cand_n[p]; t++) {
+        const int j = P.cand[p * kCandMax + t];
+        double dx = P.x[3 * j] - P.x[3 * p], dy = P.x[3 * j + 1] - P.x[3 * p + 1];
+        dx -= G.nx * floor(dx / G.nx + 0.5);
+        dy -= G.ny * floor(dy / G.ny + 0.5);
+        c += sqrt(dx * dx + dy * dy) - P.rad[p] - P.rad[j] < h_max;
+      }
+    }
+    s_scan[tid] = c;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const int v = tid >= off ? s_scan[tid - off] : 0;
+      __syncthreads();
+      s_scan[tid] += v;
+      __syncthreads();
+    }
+    int at = total + s_scan[tid] - c;
+    if (c) {
+      const Geo G = geo_of(BX, P, p);
+      for (int t = 0; t < P.cand_n[p]; t++) {
+        const int j = P.cand[p * kCandMax + t];
+        double dx = P.x[3 * j] - P.x[3 * p], dy = P.x[3 * j + 1] - P.x[3 * p + 1];
+        dx -= G.nx * floor(dx / G.nx + 0.5);
+        dy -= G.ny * floor(dy / G.ny + 0.5);
+        if (sqrt(dx * dx + dy * dy) - P.rad[p] - P.rad[j] < h_max) {
+          if (at < kClosurePairs) {
+            s_i[at] = p;
+            s_j[at] = j;
+          }
+          at++;
+        }
+      }
+    }
+    total += s_scan[255];
+    __syncthreads();
+  }
+  if (total > kClosurePairs) {
+    if (tid == 0) atomicOr(status, kStatusClosure);
+    total = kClosurePairs;
+  }
+  // the network on tiles of 16 pairs
+  const int r = lane & 15, g = lane >> 4;
+  for (int t0 = 16 * wv; t0 < total; t0 += 16 * 4) {
+    const int t = t0 + r;
+    mlp::h4 xb = {(_Float16)0.0f, (_Float16)0.0f, (_Float16)0.0f, (_Float16)0.0f};
+    if (t < total && g < 2) {
+      const int i = s_i[t], j = s_j[t];
+      const Geo G = geo_of(BX, P, i);
+      double dx = P.x[3 * j] - P.x[3 * i], dy = P.x[3 * j + 1] - P.x[3 * i + 1];
+      dx -= G.nx * floor(dx / G.nx + 0.5);
+      dy -= G.ny * floor(dy / G.ny + 0.5);
+      float in[8];
+      mlp::closure_inputs(P.x[3 * i], P.x[3 * i + 1], P.rad[i], P.rad[j], dx, dy, tau, in);
+#pragma unroll
+      for (int k = 0; k < 4; k++) xb[k] = (_Float16)in[4 * g + k];
+    }
+    mlp::h4 h1[4], h2[4];
+    mlp::f4 y;
+    mlp::forward_tile(w, xb, h1, h2, y, lane);
+    if (g == 0 && t < total) {
+      s_a[t][0] = y[0] + w.b3[0];
+      s_a[t][1] = y[1] + w.b3[1];
+    }
+  }
+  __syncthreads();
+  // per-particle sums in list order
+  for (int p = tid; p < np; p += 256) {
+    double fx = 0, fy = 0;
+    for (int t = 0; t < total; t++) {
+      const int i = s_i[t], j = s_j[t];
+      if (i != p && j != p) continue;
+      const Geo G = geo_of(BX, P, i);
+      double dx = P.x[3 * j] - P.x[3 * i], dy = P.x[3 * j + 1] - P.x[3 * i + 1];
+      dx -= G.nx * floor(dx / G.nx + 0.5);
+      dy -= G.ny * floor(dy / G.ny + 0.5);
+      const double dist = sqrt(dx * dx + dy * dy);
+      const double nx = dx / dist, ny = dy / dist;
+      const double U = (P.u[3 * i] - P.u[3 * j]) * nx + (P.u[3 * i + 1] - P.u[3 * j + 1]) * ny;
+      const double an = (double)s_a[t][0], at = (double)s_a[t][1];
+      const double ffx = mu * U * (an * nx + at * -ny), ffy = mu * U * (an * ny + at * nx);
+      if (i == p) {
+        fx += ffx;
+        fy += ffy;
+      } else {
+        fx -= ffx;
+        fy -= ffy;
+      }
+    }
+    P.fc[3 * p] = fx;
+    P.fc[3 * p + 1] = fy;
+    P.fc[3 * p + 2] = 0.0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1048,7 +1173,7 @@ struct Layout {
   size_t x, x0, u, om, phi, fext, dP, dL, F, T, m, I, rad, b0, k, org, ent0, nbs, nis, nin, jump, box, cand_n, cand,
       pairs;
   size_t off, pid, slot, hdr, vel, sub;
-  size_t boxes, fbt, tiles;
+  size_t boxes, fbt, tiles, fc, clo;
   int64_t max_ent, max_tiles;
   size_t total;
 };
@@ -1122,6 +1247,8 @@ Layout make_layout(const lbm_params& p, const BoxSet& bs) {
   L.fbt = take(sizeof(double) * p.lattice * nbox);
   L.max_tiles = bs.max_tiles;
   L.tiles = take(sizeof(int4) * bs.max_tiles);
+  L.fc = take(sizeof(double) * 3 * np);
+  L.clo = take(sizeof(float) * mlp::kParams);
   L.total = cur;
   return L;
 }
@@ -1202,6 +1329,9 @@ struct lbm_ctx {
   int g_steps, g_cur, g_w, g_grid;
   int64_t g_np, g_nent;
   int graph_steps;          // 0: eager launches
+  int closure;              // near-contact closure network on
+  double clo_h;             // gap below which it acts
+  float* d_clo;             // its parameters
   hipStream_t stream;
   char* ws;
   Layout L;
@@ -1365,8 +1495,12 @@ int launch_step(lbm_ctx* c) {
   }
   if (c->np > 0) {
     const Boxes bx = boxes_arg(c);
-    k_reduce<<<c->np, kBoundaryBlock, 0, c->stream>>>(c->own, c->ball, c->slot, c->P, c->E, bx, c->prm.rho0,
+    const double margin = c->closure ? std::max(kMargin, c->clo_h) : kMargin;
+    k_reduce<<<c->np, kBoundaryBlock, 0, c->stream>>>(c->own, c->ball, c->slot, c->P, c->E, bx, c->prm.rho0, margin,
                                                       c->status);
+    if (c->closure)
+      k_closure<<<1, 256, 0, c->stream>>>(c->P, c->np, bx, c->d_clo, c->clo_h,
+                                          c->prm.rho0 * (c->prm.tau - 0.5) / 3.0, c->prm.tau, c->status);
     k_particles<kParticleBlock><<<1, kParticleBlock, 0, c->stream>>>(c->P, c->np, c->dim, bx, c->status);
     k_stamp<<<blocks_for(c->nent), 256, 0, c->stream>>>(c->own, c->ball, c->P, c->E, bx, 0, (int)c->nent);
     HIP_TRY(hipGetLastError());
@@ -1479,6 +1613,7 @@ int check_status(lbm_ctx* c) {
     HIP_TRY(hipMemcpyAsync(c->status, zero, sizeof(zero), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (st[0] & kStatusCollision) return LBM_ECOLLISION;
+    if (st[0] & kStatusClosure) return LBM_ECAPACITY;
   }
   return LBM_OK;
 }
@@ -1607,8 +1742,11 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
                       (int*)(w + L.org),
                       (int*)(w + L.ent0),    (int*)(w + L.nbs),    (int*)(w + L.nis),
                       (int*)(w + L.nin),     (int*)(w + L.cand_n), (int*)(w + L.jump),
-                      (int*)(w + L.box),
+                      (int*)(w + L.box),     (double*)(w + L.fc),
                       (int*)(w + L.cand),    (int*)(w + L.pairs)};
+  c->d_clo = (float*)(w + L.clo);
+  c->closure = 0;
+  c->clo_h = 0.0;
   c->E = DevEntries{(int*)(w + L.off), (int*)(w + L.pid)};
   c->np = 0;
   c->nent = 0;
@@ -1779,6 +1917,7 @@ static int add_impl(lbm_ctx* c, int32_t bx, int32_t n, const double* x, const do
   std::vector<double> zero(3 * (size_t)n, 0.0);
   HIP_TRY(hipMemcpyAsync(c->P.F + 3 * p0, zero.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipMemcpyAsync(c->P.T + 3 * p0, zero.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->P.fc + 3 * p0, zero.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
   // stamp the new entries into the current map (existing owners have lower ids)
   const int64_t e0 = c->nent, e1 = c->nent + (int64_t)hoff.size();
   for (int b = bx; b < c->nbox; b++) c->boxes[b].p1 = c->np + n;  // later boxes are still empty
@@ -1966,6 +2105,30 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* width, int32_t* grid, double
   if (width) *width = win.w;
   if (grid) *grid = win.g;
   if (best_ms) *best_ms = best;
+  return LBM_OK;
+}
+
+int lbm_set_closure(lbm_ctx* c, const float* d_params, double h_max) {
+  if (!c || !std::isfinite(h_max) || h_max < 0) return LBM_EINVAL;
+  if (c->dim != 2) return LBM_EUNSUPPORTED;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->closure = d_params != nullptr && h_max > 0;
+  c->clo_h = h_max;
+  if (d_params)
+    HIP_TRY(hipMemcpyAsync(c->d_clo, d_params, sizeof(float) * mlp::kParams, hipMemcpyDeviceToDevice, c->stream));
+  if (!c->closure && c->np > 0)
+    k_fill<double><<<blocks_for(3 * (int64_t)c->np), 256, 0, c->stream>>>(c->P.fc, 3 * (int64_t)c->np, 0.0);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  drop_graph(c);
+  return LBM_OK;
+}
+
+int lbm_closure_inputs(int32_t n, const double* xi, const double* d, const double* ri, const double* rj, double tau,
+                       float* out) {
+  if (n < 0 || (n > 0 && (!xi || !d || !ri || !rj || !out))) return LBM_EINVAL;
+  for (int32_t k = 0; k < n; k++) mlp::closure_inputs(xi[2 * k], xi[2 * k + 1], ri[k], rj[k], d[2 * k], d[2 * k + 1],
+                                                     tau, out + 8 * (size_t)k);
   return LBM_OK;
 }
 

@@ -117,4 +117,26 @@ __device__ __forceinline__ void forward_tile(const Weights& s, h4 xb, h4 (&h1)[4
   y = acc;
 }
 
+// Inputs of the near-contact closure for a pair i < j of a 2D box: centre of
+// i (xi, yi), radii, minimum-image separation (dx, dy) from i to j, and the
+// relaxation time: gap h, (r_i - 9)/3, (r_j - 9)/3, the unit normal n, the
+// offset of the gap midpoint x_i + n (r_i + h/2) from its nearest site, and
+// (tau - 0.7)/0.1.  FP64 without contraction, rounded to FP32.
+__host__ __device__ inline void closure_inputs(double xi, double yi, double ri, double rj, double dx, double dy,
+                                               double tau, float in[8]) {
+#pragma clang fp contract(off)
+  const double dist = sqrt(dx * dx + dy * dy);
+  const double nx = dx / dist, ny = dy / dist;
+  const double h = dist - ri - rj;
+  const double mx = xi + nx * (ri + 0.5 * h), my = yi + ny * (ri + 0.5 * h);
+  in[0] = (float)h;
+  in[1] = (float)((ri - 9.0) / 3.0);
+  in[2] = (float)((rj - 9.0) / 3.0);
+  in[3] = (float)nx;
+  in[4] = (float)ny;
+  in[5] = (float)(mx - floor(mx + 0.5));
+  in[6] = (float)(my - floor(my + 0.5));
+  in[7] = (float)((tau - 0.7) / 0.1);
+}
+
 }  // namespace mlp

@@ -75,6 +75,8 @@ def lib():
             "lbm_get_sweep_config": [vp, _ip, _ip],
             "lbm_autotune": [vp, ctypes.c_int32, _ip, _ip, _dp],
             "lbm_set_graph": [vp, ctypes.c_int32],
+            "lbm_set_closure": [vp, vp, ctypes.c_double],
+            "lbm_closure_inputs": [ctypes.c_int32, _dp, _dp, _dp, _dp, ctypes.c_double, vp],
             "lbm_mlp_param_count": [_ip],
             "lbm_mlp_forward": [vp, vp, vp, ctypes.c_int64, vp],
             "lbm_mlp_gradient": [vp, vp, vp, ctypes.c_int32, ctypes.c_float, vp, vp, vp],
@@ -254,6 +256,12 @@ class Simulation:
                "lbm_autotune")
         return w.value, g.value, ms.value
 
+    def set_closure(self, params, h_max=2.0):
+        """Near-contact closure with the network parameters `params` (a float32
+        CUDA tensor) for gaps below h_max; params None switches it off."""
+        p = None if params is None else _ptr(params)
+        _check(lib().lbm_set_closure(self.ctx, p, float(h_max)), "lbm_set_closure")
+
     def set_graph(self, steps_per_graph):
         _check(lib().lbm_set_graph(self.ctx, int(steps_per_graph)), "lbm_set_graph")
 
@@ -359,3 +367,17 @@ def mlp_train(params, adam_m, adam_v, x, t, batch, steps, step0=0, lr=1e-3, loss
                                int(steps), int(step0), float(lr), float(loss_scale), _ptr(losses), _stream(stream)),
            "lbm_mlp_train")
     return losses[:steps]
+
+
+def closure_inputs(xi, d, ri, rj, tau):
+    """Closure inputs [n, 8] (float32) for pairs with centre xi [n, 2] of the
+    first particle, separation d [n, 2], radii ri, rj [n]."""
+    xi = np.ascontiguousarray(xi, dtype=np.float64).reshape(-1, 2)
+    n = xi.shape[0]
+    d = np.ascontiguousarray(d, dtype=np.float64).reshape(n, 2)
+    ri = np.ascontiguousarray(np.broadcast_to(np.asarray(ri, dtype=np.float64), (n,)))
+    rj = np.ascontiguousarray(np.broadcast_to(np.asarray(rj, dtype=np.float64), (n,)))
+    out = np.zeros((n, 8), dtype=np.float32)
+    _check(lib().lbm_closure_inputs(n, _d(xi), _d(d), _d(ri), _d(rj), float(tau),
+                                    out.ctypes.data_as(ctypes.c_void_p)), "lbm_closure_inputs")
+    return out

@@ -111,3 +111,27 @@ def test_product_path_never_uses_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "lbm_oracle" not in text and "ora_" not in text, f
+
+
+def test_closure_inputs_match_the_oracle_bit_for_bit():
+    """The library's closure inputs (host side of the same function the
+    closure kernel uses) equal the oracle's, rounded to FP32, for random pairs
+    including minimum-image ones."""
+    import numpy as np
+    import oracle
+    rng = np.random.Generator(np.random.PCG64(12))
+    for k in range(40):
+        L = (int(rng.integers(40, 90)), int(rng.integers(40, 90)))
+        ri, rj = rng.uniform(6, 12, 2)
+        xi = rng.uniform(0, 1, 2) * L
+        ang = rng.uniform(0, 2 * np.pi)
+        dist = ri + rj + rng.uniform(0.05, 2.0)
+        xj = (xi + dist * np.array([np.cos(ang), np.sin(ang)])) % L
+        tau = rng.uniform(0.55, 1.0)
+        o = oracle.Oracle(9, L[0], L[1], 1, tau)
+        o.add_particles([[xi[0], xi[1], 0], [xj[0], xj[1], 0]], radius=[ri, rj], mass=1.0, inertia=1.0)
+        ref = o.closure_inputs(0, 1).astype(np.float32)
+        d = xj - xi
+        d -= np.array(L) * np.floor(d / np.array(L) + 0.5)
+        ours = lbm.closure_inputs(xi, d, ri, rj, tau)[0]
+        assert np.array_equal(ours, ref), (k, ours, ref)
