@@ -140,6 +140,40 @@ def ensemble_rates(torch, lbm, wl, steps, warmup, graph_steps=20):
             "step_roofline_frac": round(72 * rate(ms_graph) * 1e6 / 1e9 / PEAK_HBM_GBPS, 4)}
 
 
+def closure_mlp_rates(torch, lbm, rows=1 << 22, reps=20, train_steps=2000):
+    """Forward rate of the closure network's MFMA kernel on `rows` random
+    inputs, and Adam steps per second of the training kernel (256-row
+    batches).  Algorithmic FLOPs per row: 2 (8*64 + 64*64 + 64*2) = 9472."""
+    from paper_1105_2904_amd import workloads as wl
+    g = torch.Generator(device="cuda").manual_seed(5)
+    x = (torch.rand((rows, 8), device="cuda", generator=g) * 2 - 1).contiguous()
+    t = (torch.rand((rows, 2), device="cuda", generator=g) - 0.5).contiguous()
+    p = torch.tensor(wl.mlp_init(3).astype(np.float32), device="cuda")
+    lbm.mlp_forward(p, x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        lbm.mlp_forward(p, x)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    xs, ts = x[:65536].contiguous(), t[:65536].contiguous()
+    lbm.mlp_train(p, m, v, xs, ts, batch=256, steps=10)
+    torch.cuda.synchronize()
+    e0.record()
+    lbm.mlp_train(p, m, v, xs, ts, batch=256, steps=train_steps, step0=10)
+    e1.record()
+    e1.synchronize()
+    tms = e0.elapsed_time(e1)
+    tflops = 9472.0 * rows / (ms * 1e-3) / 1e12
+    return {"kernel": "k_mlp_forward", "rows": rows, "forward_ms": round(ms, 4),
+            "rows_per_s": round(rows / (ms * 1e-3), 1), "achieved_tflops": round(tflops, 2),
+            "peak_tflops_fp16_mfma": 2500.0, "frac_of_mfma_peak": round(tflops / 2500.0, 4),
+            "train_steps_per_s": round(train_steps / (tms * 1e-3), 1), "train_batch": 256}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,6 +301,8 @@ def main():
             v.close()
             print("variant %s timed" % st, file=sys.stderr, flush=True)
     if not args.no_batched and args.storage == "fp32" and args.workload == "spheres-3d":
+        out["closure_mlp"] = closure_mlp_rates(torch, lbm)
+        print("closure network timed", file=sys.stderr, flush=True)
         out["batched"] = ensemble_rates(torch, lbm, wl, args.batched_steps, args.warmup)
         print("batched ensemble timed", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline and args.workload == "spheres-3d":

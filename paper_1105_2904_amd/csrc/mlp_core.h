@@ -42,9 +42,12 @@ __device__ __forceinline__ f4 mma(h4 a, h4 b, f4 c) { return __builtin_amdgcn_mf
 
 __device__ __forceinline__ h4 ld4(const _Float16* p) { return *(const h4*)p; }
 
-// tanh(z) = 1 - 2 / (exp(2z) + 1): one exponential and one reciprocal
-// (saturates to +-1 for large |z|).
-__device__ __forceinline__ float tanh_fast(float z) { return 1.0f - 2.0f / (__expf(2.0f * z) + 1.0f); }
+// tanh(z) = 1 - 2 / (exp(2z) + 1) with the hardware exponential and
+// reciprocal (about 1 ulp in FP32, far below the FP16 rounding that follows;
+// saturates to +-1 for large |z|).
+__device__ __forceinline__ float tanh_fast(float z) {
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__expf(2.0f * z) + 1.0f);
+}
 
 // Parameter k of the flat vector into the weight tiles.
 __device__ __forceinline__ void put_param(Weights& s, int k, float v) {
