@@ -20,17 +20,16 @@
 //              the ball map (lowest entry of any kind: one representative
 //              entry per ball site).
 //                                                                    eq. 14-15
-//   prepare    one thread per ball site: the record the next sweep needs there
-//              -- which incoming populations leave a pending IS site, their
-//              values f^eq_i(rho_I, u_p' + omega_p' x r) (IS substep at the new
-//              positions, eq. 12), and for an owned BS site its rigid-body
-//              velocity u_p + omega x r (eq. 5).
+//   prepare    one workgroup per particle: the IS substep at the new
+//              positions (eq. 12) written in place into the post-collision
+//              state -- f^eq_i(rho_I, u_p' + omega_p' x r) at every owned IS
+//              site -- and, for every owned BS site, the ball-map flag and the
+//              rigid-body velocity u_p + omega x r of its next BS substep
+//              (eq. 5).
 // The IS substep of step t acts on the post-collision populations of IS sites
-// just before they propagate, so the sweep of step t+1 applies it while
-// pulling.  Every link of an IS site stays inside its particle's ball, so only
-// ball sites receive such populations; everywhere else the sweep reads one
-// map word and nothing more.  Read-outs first write the pending values into
-// the state (k_materialize).
+// just before they propagate; written into the state, it is what the sweep of
+// step t+1 pulls.  Outside every ball the sweep reads one map word and
+// nothing more.
 // The populations are stored as deviations g_i = f_i - w_i rho0 so that the
 // momentum differences behind the particle forces survive FP32 storage.
 #include <hip/hip_runtime.h>
@@ -51,6 +50,8 @@ namespace {
 
 constexpr int kEmpty = 0x7fffffff;  // map value of a site no entry claims
 constexpr int64_t kMaxEntries = (int64_t)1 << 29;  // owner map stores 2e + 1 < kEmpty
+constexpr int kBallBS = 1 << 29;                   // ball map flag: the site is an owned BS site
+constexpr int kEntryMask = kBallBS - 1;
 constexpr int kCandMax = 64;        // close neighbours listed per particle
 constexpr double kMargin = 1.0;     // candidate search margin (lattice units)
 constexpr int kSweepBlock = 256;
@@ -224,50 +225,42 @@ __device__ __forceinline__ int entry_site(const DevParticles& P, const Geo& G, i
 }
 
 // ---------------------------------------------------------------------------
-// Ball-site records.  ball[s] holds the lowest entry index of any kind stamped
-// at s (kEmpty outside every ball); the record of that representative entry
-// b describes site s for the next sweep:
-//   hdr[b] = {mask, bs}: bit i of mask set if population i arrives from a
-//            pending IS site, its value being sub[i*stride + b]; bs = the BS
-//            entry that owns s (-1 if none), whose rigid-body velocity is
-//            vel[b].
+// Ball sites.  ball[s] holds an entry of any kind stamped at s (kEmpty
+// outside every ball), flagged with kBallBS when s is an owned BS site; then
+// vel[4b..4b+2] is the rigid-body velocity of its next BS substep and
+// vel[4b+3] the index of the owning BS entry, whose slot receives the site's
+// post-collision moments.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct SiteArgs {
   const int* ball;
-  const int2* hdr;
   const typename Store<T>::C* vel;  // [entry][4]
-  const T* sub;                     // [q][stride]
-  int64_t stride;                   // entries per direction plane of sub
   double* slot;                     // [entry][4]: post-collision drho, j of an owned BS site
-  typename Store<T>::C* drho;       // density deviation of every site (this sweep)
+  typename Store<T>::C* drho;       // density deviation of every ball site (this sweep)
 };
 
-// Deviation f^eq_i(rho, u) - w_i rho0 at the velocity u_p + omega_p x r of
-// entry e: the IS imposition (eq. 12, fourth substep) when e is an IS entry.
-template <int Q>
-__device__ __forceinline__ double rigid_feq(int i, int e, double drho, const DevParticles& P,
-                                            const DevEntries& E, double rho0) {
-  using L = Lattice<Q>;
-  const int p = E.pid[e];
-  const int pk = E.off[e];
-  const double rx = (double)off_x(pk) - P.phi[3 * p], ry = (double)off_y(pk) - P.phi[3 * p + 1],
-               rz = (double)off_z(pk) - P.phi[3 * p + 2];
-  const double wx = P.om[3 * p], wy = P.om[3 * p + 1], wz = P.om[3 * p + 2];
-  const double vx = P.u[3 * p] + (wy * rz - wz * ry);
-  const double vy = P.u[3 * p + 1] + (wz * rx - wx * rz);
-  const double vz = P.u[3 * p + 2] + (wx * ry - wy * rx);
-  const double rho = rho0 + drho;
-  const double usq = 1.5 * (vx * vx + vy * vy + vz * vz);
-  const double cu = L::cx(i) * vx + L::cy(i) * vy + L::cz(i) * vz;
-  return L::w(i) * (drho + rho * (3.0 * cu + 4.5 * cu * cu - usq));
+// An entry index carried in a velocity record's fourth slot (bit pattern in
+// FP32, exact value in FP64).
+template <typename C>
+__device__ __forceinline__ C idx_as(int v) {
+  if constexpr (std::is_same<C, float>::value)
+    return __int_as_float(v);
+  else
+    return (C)v;
+}
+template <typename C>
+__device__ __forceinline__ int as_idx(C v) {
+  if constexpr (std::is_same<C, float>::value)
+    return __float_as_int(v);
+  else
+    return (int)v;
 }
 
 // ---------------------------------------------------------------------------
-// K1: one pass over every site = propagation of the previous step (pull), the
-// pending IS substep of the previous step folded into that pull, BGK
+// K1: one pass over every site = propagation of the previous step (pull; the
+// previous step's IS substep is already in the state it pulls from), BGK
 // collision with body force (eq. 1-3), and the BS substep at owned BS sites
-// (eq. 5-7) with dp, dl written to the entry's slot.
+// (eq. 5-7) with the post-collision moments written to the owner's slot.
 // ---------------------------------------------------------------------------
 template <int Q, typename C>
 struct SweepArgs {
@@ -322,10 +315,7 @@ __device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restric
   const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
   const int s = off + x + nx * (y + ny * z);
 
-  // ball sites first: their record is needed before the collision
-  const int b = PART ? sa.ball[s] : kEmpty;
-  int2 h = make_int2(0, -1);
-  if (PART && b != kEmpty) h = sa.hdr[b];
+  const int bv = PART ? sa.ball[s] : kEmpty;
   C g[Q];
 #pragma unroll
   for (int i = 0; i < Q; i++) {
@@ -334,15 +324,6 @@ __device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restric
     const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
     const int sz = L::cz(i) > 0 ? zm : (L::cz(i) < 0 ? zp : z);
     g[i] = pop_ld<Q, T>(A + (size_t)i * a.N + (off + sx + nx * (sy + ny * sz)), i);
-  }
-  const int bs = h.y;
-  if (PART && h.x) {
-    // populations arriving from a pending internal site left it as the
-    // imposed equilibrium
-    const unsigned mask = (unsigned)h.x;
-#pragma unroll
-    for (int i = 0; i < Q; i++)
-      if (mask & (1u << i)) g[i] = pop_ld<Q, T>(sa.sub + (size_t)i * sa.stride + b, i);
   }
   C drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
@@ -365,12 +346,15 @@ __device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restric
     const C geq = C(L::w(i)) * (drho + rho * (C(3) * cu + C(4.5) * cu * cu - usq));
     g[i] = g[i] + a.omega * (geq - g[i]) + fbt[i];
   }
-  if (PART && b != kEmpty) {
+  if (PART && bv != kEmpty) {
     sa.drho[s] = drho;
-    if (bs >= 0) {
-      // BS substep at a site entry bs owns: its post-collision moments go to
-      // the slot (FP64 sums), and the populations become f^eq(rho_B, u_B')
-      // with the rigid-body velocity u_B' = u_p + omega x r of the site
+    if (bv & kBallBS) {
+      // BS substep at an owned BS site: its post-collision moments go to the
+      // owner's slot (FP64 sums), and the populations become f^eq(rho_B,
+      // u_B') with the rigid-body velocity u_B' = u_p + omega x r of the site
+      const size_t b = (size_t)(bv & kEntryMask);
+      const C vx = sa.vel[4 * b], vy = sa.vel[4 * b + 1], vz = sa.vel[4 * b + 2];
+      const int bs = as_idx<C>(sa.vel[4 * b + 3]);
       double dr = 0, bx = 0, by = 0, bz = 0;
 #pragma unroll
       for (int i = 0; i < Q; i++) {
@@ -385,7 +369,6 @@ __device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restric
       sl[1] = bx;
       sl[2] = by;
       sl[3] = bz;
-      const C vx = sa.vel[4 * (size_t)b], vy = sa.vel[4 * (size_t)b + 1], vz = sa.vel[4 * (size_t)b + 2];
       const C drB = (C)dr;
       const C rhoB = a.rho0 + drB;
       const C usqB = C(1.5) * (vx * vx + vy * vy + vz * vz);
@@ -854,83 +837,104 @@ __global__ __launch_bounds__(256) void k_closure(DevParticles P, int np, Boxes B
 }
 
 // ---------------------------------------------------------------------------
-// K5: record of every ball site for the next sweep.  With pending = 1 the IS
-// substep at the new positions (eq. 12) is prepared: population i of site s
-// arrives from s - c_i, and if that site is an owned IS site it arrives as
-// f^eq_i(rho_I, u_p' + omega_p' x r), with rho_I the density this step's
-// sweep found there (ball sites), or the sum of its populations when its
-// particle jumped along all three axes at once (the site may then lie outside
-// the ball the sweep kept densities for).  For an owned BS site the
-// rigid-body velocity of the next BS substep is stored (eq. 5).
+// K5: the IS substep of the step that just ran (pending = 1) and the ball-site
+// records of the next sweep.
+//  - IS substep at the new positions (eq. 12, fourth substep): every owned IS
+//    site gets f^eq_i(rho_I, u_p' + omega_p' x r) for all i, written in place
+//    into the post-collision state the next sweep pulls from.  rho_I is the
+//    density this step's sweep kept at ball sites, or the sum of the site's
+//    populations when its particle jumped along all three axes at once (the
+//    site may then lie outside the ball the sweep kept densities for); the
+//    owner reads them before it overwrites them, and no other thread touches
+//    that site.
+//  - Records: the entry representing a ball site flags it in the ball map
+//    when the site is an owned BS site and stores the rigid-body velocity of
+//    the next BS substep (eq. 5) with the owner entry's index.
 // ---------------------------------------------------------------------------
+// IS values of site s (offset o of particle p with the particle's velocities
+// in the compute type; the value is stored in it).
 template <int Q, typename T>
-__global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own, const int* __restrict__ ball,
-                                                  int2* __restrict__ hdr, typename Store<T>::C* __restrict__ vel,
-                                                  T* __restrict__ sub, const typename Store<T>::C* __restrict__ drho,
-                                                  const T* __restrict__ B, DevParticles P, DevEntries E, Boxes BX,
-                                                  int nent, int64_t stride, double rho0, int pending) {
+__device__ __forceinline__ void impose_is(T* __restrict__ S, int64_t NT, int s, double dr, typename Store<T>::C rx,
+                                          typename Store<T>::C ry, typename Store<T>::C rz,
+                                          typename Store<T>::C upx, typename Store<T>::C upy,
+                                          typename Store<T>::C upz, typename Store<T>::C wx,
+                                          typename Store<T>::C wy, typename Store<T>::C wz, double rho0) {
   using L = Lattice<Q>;
+  using C = typename Store<T>::C;
+  const C vx = upx + (wy * rz - wz * ry);
+  const C vy = upy + (wz * rx - wx * rz);
+  const C vz = upz + (wx * ry - wy * rx);
+  const C dc = (C)dr;
+  const C rho = (C)rho0 + dc;
+  const C usq = C(1.5) * (vx * vx + vy * vy + vz * vz);
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    const C cu = C(L::cx(i)) * vx + C(L::cy(i)) * vy + C(L::cz(i)) * vz;
+    S[(size_t)i * NT + s] = pop_enc<Q, T>(i, (double)(C(L::w(i)) * (dc + rho * (C(3) * cu + C(4.5) * cu * cu - usq))));
+  }
+}
+
+// Rigid-body velocity u_q + omega_q x r of BS entry bs into vel[4e..4e+3].
+template <typename C>
+__device__ __forceinline__ void store_bs_velocity(C* __restrict__ vel, int e, int bs, const DevParticles& P,
+                                                  const DevEntries& E) {
+  const int q = E.pid[bs];
+  const int ok = E.off[bs];
+  const double rx = (double)off_x(ok) - P.phi[3 * q], ry = (double)off_y(ok) - P.phi[3 * q + 1],
+               rz = (double)off_z(ok) - P.phi[3 * q + 2];
+  const double ax = P.om[3 * q], ay = P.om[3 * q + 1], az = P.om[3 * q + 2];
+  vel[4 * (size_t)e] = (C)(P.u[3 * q] + (ay * rz - az * ry));
+  vel[4 * (size_t)e + 1] = (C)(P.u[3 * q + 1] + (az * rx - ax * rz));
+  vel[4 * (size_t)e + 2] = (C)(P.u[3 * q + 2] + (ax * ry - ay * rx));
+  vel[4 * (size_t)e + 3] = idx_as<C>(bs);
+}
+
+template <int Q, typename T>
+__global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own, int* __restrict__ ball,
+                                                  typename Store<T>::C* __restrict__ vel,
+                                                  const typename Store<T>::C* __restrict__ drho, T* __restrict__ S,
+                                                  DevParticles P, DevEntries E, Boxes BX, int nent, double rho0,
+                                                  int pending) {
   using C = typename Store<T>::C;
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= nent) return;
-  const Geo G = geo_of(BX, P, E.pid[e]);
+  const int p = E.pid[e];
+  const Geo G = geo_of(BX, P, p);
+  const int pk = E.off[e];
   int x, y, z;
-  entry_xyz(P, G, E.pid[e], E.off[e], x, y, z);
+  entry_xyz(P, G, p, pk, x, y, z);
   const int s = site_of(G, x, y, z);
-  if (ball[s] != e) return;  // another entry represents this site
-  unsigned mask = 0;
-  if (pending) {
-    const int xm = x == 0 ? G.nx - 1 : x - 1, xp = x == G.nx - 1 ? 0 : x + 1;
-    const int ym = y == 0 ? G.ny - 1 : y - 1, yp = y == G.ny - 1 ? 0 : y + 1;
-    const int zm = z == 0 ? G.nz - 1 : z - 1, zp = z == G.nz - 1 ? 0 : z + 1;
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-      const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
-      const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
-      const int sz = L::cz(i) > 0 ? zm : (L::cz(i) < 0 ? zp : z);
-      const int src = site_of(G, sx, sy, sz);
-      const int o = own[src];
-      if (o == kEmpty || !(o & 1)) continue;  // not an owned IS site
-      const int ie = o >> 1;
-      double dr;
-      if (P.jump[E.pid[ie]]) {
-        dr = 0;
-        for (int j = 0; j < Q; j++) dr += (double)pop_ld<Q, T>(B + (size_t)j * BX.NT + src, j);
-      } else {
-        dr = (double)drho[src];
-      }
-      mask |= 1u << i;
-      sub[(size_t)i * stride + e] = pop_enc<Q, T>(i, rigid_feq<Q>(i, ie, dr, P, E, rho0));
-    }
-  }
-  int bs = -1;
   const int o = own[s];
-  if (o != kEmpty && !(o & 1)) {  // an owned BS site
-    bs = o >> 1;
-    const int q = E.pid[bs];
-    const int ok = E.off[bs];
-    const double rx = (double)off_x(ok) - P.phi[3 * q], ry = (double)off_y(ok) - P.phi[3 * q + 1],
-                 rz = (double)off_z(ok) - P.phi[3 * q + 2];
-    const double wx = P.om[3 * q], wy = P.om[3 * q + 1], wz = P.om[3 * q + 2];
-    vel[4 * (size_t)e] = (C)(P.u[3 * q] + (wy * rz - wz * ry));
-    vel[4 * (size_t)e + 1] = (C)(P.u[3 * q + 1] + (wz * rx - wx * rz));
-    vel[4 * (size_t)e + 2] = (C)(P.u[3 * q + 2] + (wx * ry - wy * rx));
+  if (pending && o == 2 * e + 1) {
+    double dr;
+    if (P.jump[p]) {
+      dr = 0;
+      for (int j = 0; j < Q; j++) dr += (double)pop_ld<Q, T>(S + (size_t)j * BX.NT + s, j);
+    } else {
+      dr = (double)drho[s];
+    }
+    impose_is<Q, T>(S, BX.NT, s, dr, (C)((double)off_x(pk) - P.phi[3 * p]), (C)((double)off_y(pk) - P.phi[3 * p + 1]),
+                    (C)((double)off_z(pk) - P.phi[3 * p + 2]), (C)P.u[3 * p], (C)P.u[3 * p + 1], (C)P.u[3 * p + 2],
+                    (C)P.om[3 * p], (C)P.om[3 * p + 1], (C)P.om[3 * p + 2], rho0);
   }
-  hdr[e] = make_int2((int)mask, bs);
+  if ((ball[s] & kEntryMask) != e) return;  // another entry represents this site
+  if (o != kEmpty && !(o & 1)) {            // an owned BS site
+    store_bs_velocity<C>(vel, e, o >> 1, P, E);
+    ball[s] = e | kBallBS;
+  } else {
+    ball[s] = e;
+  }
 }
 
-// The same records built per particle (one workgroup each) from a window of
-// the owner map and densities around the ball, staged in LDS: row-coalesced
-// loads instead of scattered neighbour lookups.  The window has half-width
-// hw = floor(r + 1/2) + 1 (ball offsets plus one link).  Sites claimed by
-// another particle fall back to global lookups.
+// The same per particle (one workgroup each), with the owner map and the
+// densities of a window around the ball staged in LDS: row-coalesced loads
+// instead of scattered lookups.  Half-width hw = floor(r + 1/2) + 1.
 template <int Q, typename T>
-__global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ own, const int* __restrict__ ball,
-                                                        int2* __restrict__ hdr, typename Store<T>::C* __restrict__ vel,
-                                                        T* __restrict__ sub, const typename Store<T>::C* __restrict__ drho,
-                                                        const T* __restrict__ B, DevParticles P, DevEntries E, Boxes BX,
-                                                        int64_t stride, double rho0, int pending, int dim) {
-  using L = Lattice<Q>;
+__global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ own, int* __restrict__ ball,
+                                                        typename Store<T>::C* __restrict__ vel,
+                                                        const typename Store<T>::C* __restrict__ drho,
+                                                        T* __restrict__ S, DevParticles P, DevEntries E, Boxes BX,
+                                                        double rho0, int pending, int dim) {
   using C = typename Store<T>::C;
   extern __shared__ __align__(16) unsigned char smem[];
   const int p = blockIdx.x;
@@ -970,138 +974,54 @@ __global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ o
   }
   __syncthreads();
   const double phx = P.phi[3 * p], phy = P.phi[3 * p + 1], phz = P.phi[3 * p + 2];
-  const double upx = P.u[3 * p], upy = P.u[3 * p + 1], upz = P.u[3 * p + 2];
-  const double wx = P.om[3 * p], wy = P.om[3 * p + 1], wz = P.om[3 * p + 2];
-  const C cupx = (C)upx, cupy = (C)upy, cupz = (C)upz, cwx = (C)wx, cwy = (C)wy, cwz = (C)wz;
+  const C cupx = (C)P.u[3 * p], cupy = (C)P.u[3 * p + 1], cupz = (C)P.u[3 * p + 2];
+  const C cwx = (C)P.om[3 * p], cwy = (C)P.om[3 * p + 1], cwz = (C)P.om[3 * p + 2];
   const int e0 = P.ent0[p], ne = P.nbs[p] + P.nis[p] + P.nin[p];
   const bool jump = P.jump[p] != 0;
   constexpr int kEnt = 4;
   for (int tb = 0; tb < ne; tb += 256 * kEnt) {
-  int rep[kEnt], pkv[kEnt];
+    int rep[kEnt], pkv[kEnt];
 #pragma unroll
-  for (int j = 0; j < kEnt; j++) {
-    const int t = tb + j * 256 + tid;
-    rep[j] = -1;
-    if (t < ne) {
-      pkv[j] = E.off[e0 + t];
-      const int x = wrap1(ox0 + off_x(pkv[j]), G.nx), y = wrap1(oy0 + off_y(pkv[j]), G.ny),
-                z = wrap1(oz0 + off_z(pkv[j]), G.nz);
-      rep[j] = ball[site_of(G, x, y, z)];
+    for (int j = 0; j < kEnt; j++) {
+      const int t = tb + j * 256 + tid;
+      rep[j] = -1;
+      if (t < ne) {
+        pkv[j] = E.off[e0 + t];
+        const int x = wrap1(ox0 + off_x(pkv[j]), G.nx), y = wrap1(oy0 + off_y(pkv[j]), G.ny),
+                  z = wrap1(oz0 + off_z(pkv[j]), G.nz);
+        rep[j] = ball[site_of(G, x, y, z)] & kEntryMask;
+      }
     }
-  }
 #pragma unroll 1
-  for (int j = 0; j < kEnt; j++) {
-    const int t = tb + j * 256 + tid;
-    const int e = e0 + t;
-    if (t >= ne || rep[j] != e) continue;  // another entry represents this site
-    const int pk = pkv[j];
-    const int ox = off_x(pk), oy = off_y(pk), oz = off_z(pk);
-    const int x = wrap1(ox0 + ox, G.nx), y = wrap1(oy0 + oy, G.ny), z = wrap1(oz0 + oz, G.nz);
-    const int w = (ox + hw) + W * ((oy + hw) + W * (oz + hz));
-    unsigned mask = 0;
-    if (pending) {
-#pragma unroll
-      for (int i = 0; i < Q; i++) {
-        const int wn = w - (L::cx(i) + W * (L::cy(i) + W * L::cz(i)));  // site s - c_i
-        const int o = s_own[wn];
-        if (o == kEmpty || !(o & 1)) continue;  // not an owned IS site
-        const int ie = o >> 1;
-        double val;
-        if (ie >= e0 && ie < e0 + ne) {
-          // an IS site of this particle: lever arm (o - c_i) - phi
-          double dr;
-          if (jump) {
-            const int src = site_of(G, wrap1(x - L::cx(i), G.nx), wrap1(y - L::cy(i), G.ny), wrap1(z - L::cz(i), G.nz));
-            dr = 0;
-            for (int j = 0; j < Q; j++) dr += (double)pop_ld<Q, T>(B + (size_t)j * BX.NT + src, j);
-          } else {
-            dr = (double)s_drho[wn];
-          }
-          // in the compute precision of the storage (the value is stored in it)
-          const C rx = (C)((double)(ox - L::cx(i)) - phx), ry = (C)((double)(oy - L::cy(i)) - phy),
-                  rz = (C)((double)(oz - L::cz(i)) - phz);
-          const C vx = cupx + (cwy * rz - cwz * ry);
-          const C vy = cupy + (cwz * rx - cwx * rz);
-          const C vz = cupz + (cwx * ry - cwy * rx);
-          const C dc = (C)dr;
-          const C rho = (C)rho0 + dc;
-          const C usq = C(1.5) * (vx * vx + vy * vy + vz * vz);
-          const C cu = C(L::cx(i)) * vx + C(L::cy(i)) * vy + C(L::cz(i)) * vz;
-          val = (double)(C(L::w(i)) * (dc + rho * (C(3) * cu + C(4.5) * cu * cu - usq)));
+    for (int j = 0; j < kEnt; j++) {
+      const int t = tb + j * 256 + tid;
+      if (t >= ne) continue;
+      const int e = e0 + t;
+      const int pk = pkv[j];
+      const int ox = off_x(pk), oy = off_y(pk), oz = off_z(pk);
+      const int s = site_of(G, wrap1(ox0 + ox, G.nx), wrap1(oy0 + oy, G.ny), wrap1(oz0 + oz, G.nz));
+      const int w = (ox + hw) + W * ((oy + hw) + W * (oz + hz));
+      const int o = s_own[w];
+      if (pending && o == 2 * e + 1) {
+        double dr;
+        if (jump) {
+          dr = 0;
+          for (int k = 0; k < Q; k++) dr += (double)pop_ld<Q, T>(S + (size_t)k * BX.NT + s, k);
         } else {
-          // an IS site of another particle (balls overlap)
-          const int src = site_of(G, wrap1(x - L::cx(i), G.nx), wrap1(y - L::cy(i), G.ny), wrap1(z - L::cz(i), G.nz));
-          double dr;
-          if (P.jump[E.pid[ie]]) {
-            dr = 0;
-            for (int j = 0; j < Q; j++) dr += (double)pop_ld<Q, T>(B + (size_t)j * BX.NT + src, j);
-          } else {
-            dr = (double)drho[src];
-          }
-          val = rigid_feq<Q>(i, ie, dr, P, E, rho0);
+          dr = (double)s_drho[w];
         }
-        mask |= 1u << i;
-        sub[(size_t)i * stride + e] = pop_enc<Q, T>(i, val);
+        impose_is<Q, T>(S, BX.NT, s, dr, (C)((double)ox - phx), (C)((double)oy - phy), (C)((double)oz - phz), cupx,
+                        cupy, cupz, cwx, cwy, cwz, rho0);
       }
-    }
-    int bs = -1;
-    const int o = s_own[w];
-    if (o != kEmpty && !(o & 1)) {  // an owned BS site
-      bs = o >> 1;
-      double vx, vy, vz;
-      if (bs == e) {
-        const double rx = (double)ox - phx, ry = (double)oy - phy, rz = (double)oz - phz;
-        vx = upx + (wy * rz - wz * ry);
-        vy = upy + (wz * rx - wx * rz);
-        vz = upz + (wx * ry - wy * rx);
+      if (rep[j] != e) continue;  // another entry represents this site
+      if (o != kEmpty && !(o & 1)) {
+        store_bs_velocity<C>(vel, e, o >> 1, P, E);
+        ball[s] = e | kBallBS;
       } else {
-        const int q = E.pid[bs];
-        const int ok = E.off[bs];
-        const double rx = (double)off_x(ok) - P.phi[3 * q], ry = (double)off_y(ok) - P.phi[3 * q + 1],
-                     rz = (double)off_z(ok) - P.phi[3 * q + 2];
-        const double ax = P.om[3 * q], ay = P.om[3 * q + 1], az = P.om[3 * q + 2];
-        vx = P.u[3 * q] + (ay * rz - az * ry);
-        vy = P.u[3 * q + 1] + (az * rx - ax * rz);
-        vz = P.u[3 * q + 2] + (ax * ry - ay * rx);
+        ball[s] = e;
       }
-      vel[4 * (size_t)e] = (C)vx;
-      vel[4 * (size_t)e + 1] = (C)vy;
-      vel[4 * (size_t)e + 2] = (C)vz;
     }
-    hdr[e] = make_int2((int)mask, bs);
   }
-  }
-}
-
-// Read-outs and overwrites: retire the pending IS substep.  write = 1 puts the
-// prepared populations into the state in place (exactly what the next sweep
-// would have pulled); write = 0 drops them (the state was replaced).
-template <int Q, typename T>
-__global__ __launch_bounds__(256) void k_materialize(T* __restrict__ S, const int* __restrict__ ball,
-                                                      int2* __restrict__ hdr, const T* __restrict__ sub,
-                                                      DevParticles P, DevEntries E, Boxes BX, int nent, int64_t stride,
-                                                      int write) {
-  using L = Lattice<Q>;
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= nent) return;
-  const Geo G = geo_of(BX, P, E.pid[e]);
-  int x, y, z;
-  entry_xyz(P, G, E.pid[e], E.off[e], x, y, z);
-  const int s = site_of(G, x, y, z);
-  if (ball[s] != e) return;
-  int2 h = hdr[e];
-  if (h.x == 0) return;
-  if (write) {
-    // the pulled population i of s is the state's population i at s - c_i
-#pragma unroll
-    for (int i = 0; i < Q; i++)
-      if (h.x & (1 << i)) {
-        const int src = site_of(G, wrap1(x - L::cx(i), G.nx), wrap1(y - L::cy(i), G.ny), wrap1(z - L::cz(i), G.nz));
-        S[(size_t)i * BX.NT + src] = sub[(size_t)i * stride + e];
-      }
-  }
-  h.x = 0;
-  hdr[e] = h;
 }
 
 // ---------------------------------------------------------------------------
@@ -1172,7 +1092,7 @@ struct Layout {
   size_t f[2], drho, own, ball, status;
   size_t x, x0, u, om, phi, fext, dP, dL, F, T, m, I, rad, b0, k, org, ent0, nbs, nis, nin, jump, box, cand_n, cand,
       pairs;
-  size_t off, pid, slot, hdr, vel, sub;
+  size_t off, pid, slot, vel;
   size_t boxes, fbt, tiles, fc, clo;
   int64_t max_ent, max_tiles;
   size_t total;
@@ -1240,9 +1160,7 @@ Layout make_layout(const lbm_params& p, const BoxSet& bs) {
   L.off = take(sizeof(int) * L.max_ent);
   L.pid = take(sizeof(int) * L.max_ent);
   L.slot = take(sizeof(double) * 4 * L.max_ent);
-  L.hdr = take(sizeof(int) * 2 * L.max_ent);
   L.vel = take((p.storage == LBM_FP64 ? 8 : 4) * 4 * L.max_ent);
-  L.sub = take((size_t)p.lattice * store_size(p.storage) * L.max_ent);
   L.boxes = take(sizeof(Geo) * nbox);
   L.fbt = take(sizeof(double) * p.lattice * nbox);
   L.max_tiles = bs.max_tiles;
@@ -1339,9 +1257,7 @@ struct lbm_ctx {
   int cur;  // f[cur] holds the post-collision state of the last step
   void* drho;
   double* slot;
-  int2* hdr;
   void* vel;
-  void* sub;
   int* own;   // owner map: lowest BS/IS entry per site
   int* ball;  // ball map: lowest entry of any kind per site
   int* status;
@@ -1368,10 +1284,7 @@ template <int Q, typename T>
 SiteArgs<T> site_args(lbm_ctx* c) {
   SiteArgs<T> sa;
   sa.ball = c->ball;
-  sa.hdr = c->hdr;
   sa.vel = (const typename Store<T>::C*)c->vel;
-  sa.sub = (const T*)c->sub;
-  sa.stride = c->L.max_ent;
   sa.slot = c->slot;
   sa.drho = (typename Store<T>::C*)c->drho;
   return sa;
@@ -1386,21 +1299,21 @@ Boxes boxes_arg(const lbm_ctx* c) {
   return b;
 }
 
-// Records of every ball site for the next sweep; with pending = 1 the IS
-// substep of the step that just ran is prepared.  Per-particle LDS windows
-// when they fit, one thread per entry otherwise.
+// The IS substep of the step that just ran (pending = 1) and the records of
+// every ball site for the next sweep.  Per-particle LDS windows when they fit,
+// one thread per entry otherwise.
 template <int Q, typename T>
 int launch_prepare(lbm_ctx* c, int pending) {
   if (c->nent == 0) return LBM_OK;
   using C = typename Store<T>::C;
   if (c->lds_window > 0) {
     k_prepare_local<Q, T><<<c->np, 256, c->lds_window, c->stream>>>(
-        c->own, c->ball, c->hdr, (C*)c->vel, (T*)c->sub, (const C*)c->drho, (const T*)c->f[c->cur], c->P, c->E,
-        boxes_arg(c), c->L.max_ent, c->prm.rho0, pending, c->dim);
+        c->own, c->ball, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c), c->prm.rho0,
+        pending, c->dim);
   } else {
     k_prepare<Q, T><<<blocks_for(c->nent), 256, 0, c->stream>>>(
-        c->own, c->ball, c->hdr, (C*)c->vel, (T*)c->sub, (const C*)c->drho, (const T*)c->f[c->cur], c->P, c->E,
-        boxes_arg(c), (int)c->nent, c->L.max_ent, c->prm.rho0, pending);
+        c->own, c->ball, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c), (int)c->nent,
+        c->prm.rho0, pending);
   }
   HIP_TRY(hipGetLastError());
   return LBM_OK;
@@ -1507,19 +1420,6 @@ int launch_step(lbm_ctx* c) {
   }
   c->cur = 1 - c->cur;  // f[cur] now holds this step's post-collision state
   if (c->np > 0) return launch_prepare<Q, T>(c, 1);
-  return LBM_OK;
-}
-
-// Retire the pending IS substep: write = 1 puts it into the current state
-// (read-outs), write = 0 drops it (the state is being replaced).
-template <int Q, typename T>
-int launch_materialize(lbm_ctx* c, int write) {
-  if (c->nent > 0) {
-    k_materialize<Q, T><<<blocks_for(c->nent), 256, 0, c->stream>>>(
-        (T*)c->f[c->cur], c->ball, c->hdr, (const T*)c->sub, c->P, c->E, boxes_arg(c), (int)c->nent, c->L.max_ent,
-        write);
-    HIP_TRY(hipGetLastError());
-  }
   return LBM_OK;
 }
 
@@ -1715,9 +1615,7 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
   c->cur = 0;
   c->drho = c->ws + L.drho;
   c->slot = (double*)(c->ws + L.slot);
-  c->hdr = (int2*)(c->ws + L.hdr);
   c->vel = c->ws + L.vel;
-  c->sub = c->ws + L.sub;
   c->own = (int*)(c->ws + L.own);
   c->ball = (int*)(c->ws + L.ball);
   c->status = (int*)(c->ws + L.status);
@@ -1883,9 +1781,6 @@ static int add_impl(lbm_ctx* c, int32_t bx, int32_t n, const double* x, const do
     hpid.insert(hpid.end(), (size_t)(nb + ni + nn), c->np + j);
   }
   if (c->nent + (int64_t)hoff.size() > c->L.max_ent) return LBM_ECAPACITY;
-  // the pending IS substep of the particles already present goes into the state
-  const int mrc = DISPATCH(c, launch_materialize, c, 1);
-  if (mrc != LBM_OK) return mrc;
   const int p0 = c->np;
   int rc;
 #define UP(dst, src, cnt) \
@@ -2168,8 +2063,6 @@ int lbm_forces(lbm_ctx* c, double* F, double* T, double* x, double* u, double* o
 int lbm_fields(lbm_ctx* c, double* rho, double* u, int32_t* owner) {
   if (!c) return LBM_EINVAL;
   if (rho || u) {
-    const int mrc = DISPATCH(c, launch_materialize, c, 1);
-    if (mrc != LBM_OK) return mrc;
     // the other population buffer is free between steps: stage moments there
     const size_t stage = (size_t)c->q * c->NT * store_size(c->prm.storage);
     const int64_t chunk = (int64_t)(stage / (4 * sizeof(double)));
@@ -2224,9 +2117,7 @@ int lbm_particle_info(lbm_ctx* c, int32_t p, int32_t* nbs, int32_t* nis) {
 int lbm_get_distributions(lbm_ctx* c, double* f) {
   if (!c || !f) return LBM_EINVAL;
   void* stage = c->f[1 - c->cur];
-  int rc = DISPATCH(c, launch_materialize, c, 1);
-  if (rc != LBM_OK) return rc;
-  rc = DISPATCH(c, launch_shift, c, c->f[c->cur], stage, 1);
+  int rc = DISPATCH(c, launch_shift, c, c->f[c->cur], stage, 1);
   if (rc != LBM_OK) return rc;
   const int64_t n = (int64_t)c->q * c->NT;
   const int ss = (int)store_size(c->prm.storage);
@@ -2275,10 +2166,8 @@ int lbm_set_distributions(lbm_ctx* c, const double* f) {
   }
   HIP_TRY(hipMemcpyAsync(stage, h.data(), (size_t)n * ss, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  int rc = DISPATCH(c, launch_shift, c, stage, c->f[c->cur], -1);
-  if (rc != LBM_OK) return rc;
   // the given populations are the complete post-propagation state
-  rc = DISPATCH(c, launch_materialize, c, 0);
+  const int rc = DISPATCH(c, launch_shift, c, stage, c->f[c->cur], -1);
   if (rc != LBM_OK) return rc;
   HIP_TRY(hipStreamSynchronize(c->stream));
   return LBM_OK;
