@@ -233,6 +233,7 @@ __device__ __forceinline__ int entry_site(const DevParticles& P, const Geo& G, i
 // ---------------------------------------------------------------------------
 template <typename T>
 struct SiteArgs {
+  const uint8_t* bm;  // one byte per site: 1 where some ball covers it
   const int* ball;
   const typename Store<T>::C* vel;  // [entry][4]
   double* slot;                     // [entry][4]: post-collision drho, j of an owned BS site
@@ -315,7 +316,14 @@ __device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restric
   const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
   const int s = off + x + nx * (y + ny * z);
 
-  const int bv = PART ? sa.ball[s] : kEmpty;
+  // the bitmap first: sites outside every ball read 1 bit, not a map word
+  const int bv = PART && sa.bm[s] ? sa.ball[s] : kEmpty;
+  // 16-bit storage collides on the stored numbers h_i = g_i / (w_i sigma):
+  // there the weight cancels from the equilibrium, h_i^eq = (drho + rho (3cu
+  // + 9/2 cu^2 - 3/2 u^2)) / sigma, which saves the per-direction scalings;
+  // FP32/FP64 collide on the deviations g_i.
+  constexpr bool kRaw = std::is_same<T, _Float16>::value || std::is_same<T, bf16s>::value;
+  const C inv_sig = (C)(1.0 / pop_unit<T>(1.0));
   C g[Q];
 #pragma unroll
   for (int i = 0; i < Q; i++) {
@@ -323,28 +331,40 @@ __device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restric
     const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
     const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
     const int sz = L::cz(i) > 0 ? zm : (L::cz(i) < 0 ? zp : z);
-    g[i] = pop_ld<Q, T>(A + (size_t)i * a.N + (off + sx + nx * (sy + ny * sz)), i);
+    const T* src = A + (size_t)i * a.N + (off + sx + nx * (sy + ny * sz));
+    g[i] = kRaw ? Store<T>::ld(src) : pop_ld<Q, T>(src, i);
   }
   C drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int i = 0; i < Q; i++) {
-    drho += g[i];
-    if (L::cx(i) > 0) jx += g[i];
-    if (L::cx(i) < 0) jx -= g[i];
-    if (L::cy(i) > 0) jy += g[i];
-    if (L::cy(i) < 0) jy -= g[i];
-    if (L::cz(i) > 0) jz += g[i];
-    if (L::cz(i) < 0) jz -= g[i];
+    const C v = kRaw ? g[i] * (C)pop_unit<T>(L::w(i)) : g[i];
+    drho += v;
+    if (L::cx(i) > 0) jx += v;
+    if (L::cx(i) < 0) jx -= v;
+    if (L::cy(i) > 0) jy += v;
+    if (L::cy(i) < 0) jy -= v;
+    if (L::cz(i) > 0) jz += v;
+    if (L::cz(i) < 0) jz -= v;
   }
   const C rho = a.rho0 + drho;
   const C inv = C(1) / rho;
   const C ux = jx * inv, uy = jy * inv, uz = jz * inv;
   const C usq = C(1.5) * (ux * ux + uy * uy + uz * uz);
+  if constexpr (kRaw) {
+    const C kA = inv_sig * (drho - rho * usq), kB = inv_sig * C(3) * rho, kC = inv_sig * C(4.5) * rho;
 #pragma unroll
-  for (int i = 0; i < Q; i++) {
-    const C cu = C(L::cx(i)) * ux + C(L::cy(i)) * uy + C(L::cz(i)) * uz;
-    const C geq = C(L::w(i)) * (drho + rho * (C(3) * cu + C(4.5) * cu * cu - usq));
-    g[i] = g[i] + a.omega * (geq - g[i]) + fbt[i];
+    for (int i = 0; i < Q; i++) {
+      const C cu = C(L::cx(i)) * ux + C(L::cy(i)) * uy + C(L::cz(i)) * uz;
+      const C he = fmaf(fmaf(kC, cu, kB), cu, kA);
+      g[i] = fmaf(a.omega, he - g[i], g[i]) + fbt[i] * (C)(1.0 / pop_unit<T>(L::w(i)));
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+      const C cu = C(L::cx(i)) * ux + C(L::cy(i)) * uy + C(L::cz(i)) * uz;
+      const C geq = C(L::w(i)) * (drho + rho * (C(3) * cu + C(4.5) * cu * cu - usq));
+      g[i] = g[i] + a.omega * (geq - g[i]) + fbt[i];
+    }
   }
   if (PART && bv != kEmpty) {
     sa.drho[s] = drho;
@@ -358,7 +378,7 @@ __device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restric
       double dr = 0, bx = 0, by = 0, bz = 0;
 #pragma unroll
       for (int i = 0; i < Q; i++) {
-        const double v = (double)g[i];
+        const double v = kRaw ? (double)g[i] * pop_unit<T>(L::w(i)) : (double)g[i];
         dr += v;
         bx += L::cx(i) * v;
         by += L::cy(i) * v;
@@ -375,7 +395,8 @@ __device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restric
 #pragma unroll
       for (int i = 0; i < Q; i++) {
         const C cu = C(L::cx(i)) * vx + C(L::cy(i)) * vy + C(L::cz(i)) * vz;
-        g[i] = C(L::w(i)) * (drB + rhoB * (C(3) * cu + C(4.5) * cu * cu - usqB));
+        const C e = drB + rhoB * (C(3) * cu + C(4.5) * cu * cu - usqB);
+        g[i] = kRaw ? inv_sig * e : C(L::w(i)) * e;
       }
     }
   }
@@ -388,12 +409,19 @@ __device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restric
 #pragma unroll
       for (int i = 0; i < Q; i++) {
         const C cu = C(L::cx(i)) * vx + C(L::cy(i)) * vy + C(L::cz(i)) * vz;
-        g[i] = C(L::w(i)) * (drho + rho * (C(3) * cu + C(4.5) * cu * cu - usqW));
+        const C e = drho + rho * (C(3) * cu + C(4.5) * cu * cu - usqW);
+        g[i] = kRaw ? inv_sig * e : C(L::w(i)) * e;
       }
     }
   }
 #pragma unroll
-  for (int i = 0; i < Q; i++) pop_st<Q, T>(B + (size_t)i * a.N + s, i, g[i]);
+  for (int i = 0; i < Q; i++) {
+    T* dst = B + (size_t)i * a.N + s;
+    if constexpr (kRaw)
+      Store<T>::st(dst, g[i]);
+    else
+      pop_st<Q, T>(dst, i, g[i]);
+  }
 }
 
 // One box: workgroup b covers kSweepBlock sites of row b / nxb.
@@ -408,23 +436,24 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, 
 }
 
 // Any number of boxes: a tile is a run of blockDim.x sites of one row of
-// one box, {box, y, z, x0}; a persistent grid walks the tile list (the
-// workgroup width and grid size are the tunable launch shape).
+// one box, {box, y, z, x0} followed by the box's {nx, ny, nz, first site}
+// (one record, so the pull addresses depend on one load); a persistent grid
+// walks the tile list (the workgroup width and grid size are the tunable
+// launch shape).
 template <int Q, typename T, bool PART>
 __global__ __launch_bounds__(kTileMax) void k_sweep_tiles(const T* __restrict__ A, T* __restrict__ B,
                                                            SweepArgs<Q, typename Store<T>::C> a, SiteArgs<T> sa,
-                                                           const Geo* __restrict__ tab, const int4* __restrict__ tiles,
-                                                           int ntiles, const typename Store<T>::C* __restrict__ fbt_tab) {
+                                                           const int4* __restrict__ tiles, int ntiles,
+                                                           const typename Store<T>::C* __restrict__ fbt_tab) {
   using C = typename Store<T>::C;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int4 tl = tiles[t];
-    const Geo g = tab[tl.x];
+    const int4 tl = tiles[2 * t], tg = tiles[2 * t + 1];
     const int x = tl.w + (int)threadIdx.x;
-    if (x >= g.nx) continue;
+    if (x >= tg.x) continue;
     C fb[Q];
 #pragma unroll
     for (int i = 0; i < Q; i++) fb[i] = fbt_tab[tl.x * Q + i];
-    sweep_site<Q, T, PART>(A, B, a, sa, x, tl.y, tl.z, g.nx, g.ny, g.nz, (int)g.off, fb);
+    sweep_site<Q, T, PART>(A, B, a, sa, x, tl.y, tl.z, tg.x, tg.y, tg.z, tg.w, fb);
   }
 }
 
@@ -437,12 +466,38 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Exclusive prefix sum of c over a workgroup of NT threads: a shuffle scan in
+// each wave, then the wave totals (s_w holds NT/64 ints).  Returns this
+// thread's offset; total receives the workgroup's sum.
+template <int NT>
+__device__ __forceinline__ int block_excl_scan(int c, int* s_w, int& total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int v = c;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(v, o);
+    if (lane >= o) v += u;
+  }
+  if (lane == 63) s_w[wv] = v;
+  __syncthreads();
+  int before = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; w++) {
+    const int t = s_w[w];
+    before += w < wv ? t : 0;
+    tot += t;
+  }
+  __syncthreads();  // s_w is free again
+  total = tot;
+  return before + v - c;
+}
+
 // ---------------------------------------------------------------------------
 // K3: particle update, one workgroup (eq. 10-11, 16-19, 13).
 // ---------------------------------------------------------------------------
 template <int NT>
 __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int np, int dim, Boxes BX, int* status) {
-  __shared__ int s_scan[NT];
+  __shared__ int s_scan[NT / 64];
   __shared__ double s_vmax[NT / 64];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
@@ -471,29 +526,26 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int np, int di
     const int p = b + tid;
     const int c = p < np ? P.cand_n[p] : 0;
     if (!__syncthreads_or(c)) continue;  // no close pair in this chunk
-    s_scan[tid] = c;
-    __syncthreads();
-    for (int off = 1; off < NT; off <<= 1) {
-      const int v = tid >= off ? s_scan[tid - off] : 0;
-      __syncthreads();
-      s_scan[tid] += v;
-      __syncthreads();
-    }
-    const int excl = total + s_scan[tid] - c;
+    int chunk;
+    const int excl = total + block_excl_scan<NT>(c, s_scan, chunk);
     for (int t = 0; t < c; t++) {
       P.pairs[2 * (excl + t)] = p;
       P.pairs[2 * (excl + t) + 1] = P.cand[p * kCandMax + t];
     }
-    total += s_scan[NT - 1];
-    __syncthreads();
+    total += chunk;
   }
 
   __syncthreads();
-  if (tid == 0) {
-    double vseen = 0;
-    for (int w = 0; w < NT / 64; w++) vseen = fmax(vseen, s_vmax[w]);
-    for (int t = 0; t < total; t++) {
+  // Pairs in lexicographic order, one box after the other (a box holds
+  // consecutive ids): every box's pairs are one segment, walked in order by
+  // one thread, the boxes in parallel.
+  double vseen = 0;
+  for (int t0 = tid; t0 < total; t0 += NT) {
+    const int b0 = BX.nbox == 1 ? 0 : P.box[P.pairs[2 * t0]];
+    if (t0 > 0 && (BX.nbox == 1 || P.box[P.pairs[2 * (t0 - 1)]] == b0)) continue;  // not a segment start
+    for (int t = t0; t < total; t++) {
       const int i = P.pairs[2 * t], j = P.pairs[2 * t + 1];
+      if (t > t0 && BX.nbox > 1 && P.box[i] != b0) break;
       const Geo G = geo_of(BX, P, i);  // pairs never cross boxes
       const int L[3] = {G.nx, G.ny, G.nz};
       const bool infA = isinf(P.m[i]), infB = isinf(P.m[j]);
@@ -538,7 +590,15 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int np, int di
         vseen = fmax(vseen, sqrt(v2));
       }
     }
-    if (2.0 * vseen >= kMargin) atomicOr(status, kStatusCollision);
+  }
+  for (int o = 32; o > 0; o >>= 1) vseen = fmax(vseen, __shfl_xor(vseen, o));
+  __syncthreads();
+  if (lane == 0) s_vmax[wv] = fmax(s_vmax[wv], vseen);
+  __syncthreads();
+  if (tid == 0) {
+    double vm = 0;
+    for (int w = 0; w < NT / 64; w++) vm = fmax(vm, s_vmax[w]);
+    if (2.0 * vm >= kMargin) atomicOr(status, kStatusCollision);
   }
   __syncthreads();
   for (int p = tid; p < np; p += NT) {
@@ -574,7 +634,7 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int np, int di
 // this step.  One workgroup per particle.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own, int* __restrict__ ball,
-                                                            const double* __restrict__ slot,
+                                                            uint8_t* __restrict__ bm, const double* __restrict__ slot,
                                                             DevParticles P, DevEntries E, Boxes BX,
                                                             double rho0, double margin, int* status) {
   constexpr int kWaves = kBoundaryBlock / 64;
@@ -616,6 +676,7 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
       const int kind = entry_kind(pk);
       const int s = sv[j];
       ball[s] = kEmpty;
+      bm[s] = 0;
       if (kind == 2 && ov[j] == 2 * e + 1) own[s] = kEmpty;
       if (kind != 1 || ov[j] != 2 * e) continue;  // BS sites owned by this entry only
       own[s] = kEmpty;                             // only the owner clears its site
@@ -731,7 +792,7 @@ __global__ __launch_bounds__(256) void k_closure(DevParticles P, int np, Boxes B
   __shared__ mlp::Weights w;
   __shared__ int s_i[kClosurePairs], s_j[kClosurePairs];
   __shared__ float s_a[kClosurePairs][2];
-  __shared__ int s_scan[256];
+  __shared__ int s_scan[4];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   mlp::load_weights(w, params, tid, 256);
   __syncthreads();
@@ -750,15 +811,8 @@ __global__ __launch_bounds__(256) void k_closure(DevParticles P, int np, Boxes B
         c += sqrt(dx * dx + dy * dy) - P.rad[p] - P.rad[j] < h_max;
       }
     }
-    s_scan[tid] = c;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-      const int v = tid >= off ? s_scan[tid - off] : 0;
-      __syncthreads();
-      s_scan[tid] += v;
-      __syncthreads();
-    }
-    int at = total + s_scan[tid] - c;
+    int chunk;
+    int at = total + block_excl_scan<256>(c, s_scan, chunk);
     if (c) {
       const Geo G = geo_of(BX, P, p);
       for (int t = 0; t < P.cand_n[p]; t++) {
@@ -775,9 +829,9 @@ __global__ __launch_bounds__(256) void k_closure(DevParticles P, int np, Boxes B
         }
       }
     }
-    total += s_scan[255];
-    __syncthreads();
+    total += chunk;
   }
+  __syncthreads();  // the pair list is complete
   if (total > kClosurePairs) {
     if (tid == 0) atomicOr(status, kStatusClosure);
     total = kClosurePairs;
@@ -891,7 +945,7 @@ __device__ __forceinline__ void store_bs_velocity(C* __restrict__ vel, int e, in
 
 template <int Q, typename T>
 __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own, int* __restrict__ ball,
-                                                  typename Store<T>::C* __restrict__ vel,
+                                                  uint8_t* __restrict__ bm, typename Store<T>::C* __restrict__ vel,
                                                   const typename Store<T>::C* __restrict__ drho, T* __restrict__ S,
                                                   DevParticles P, DevEntries E, Boxes BX, int nent, double rho0,
                                                   int pending) {
@@ -924,6 +978,7 @@ __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own, in
   } else {
     ball[s] = e;
   }
+  bm[s] = 1;
 }
 
 // The same per particle (one workgroup each), with the owner map and the
@@ -931,7 +986,7 @@ __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own, in
 // instead of scattered lookups.  Half-width hw = floor(r + 1/2) + 1.
 template <int Q, typename T>
 __global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ own, int* __restrict__ ball,
-                                                        typename Store<T>::C* __restrict__ vel,
+                                                        uint8_t* __restrict__ bm, typename Store<T>::C* __restrict__ vel,
                                                         const typename Store<T>::C* __restrict__ drho,
                                                         T* __restrict__ S, DevParticles P, DevEntries E, Boxes BX,
                                                         double rho0, int pending, int dim) {
@@ -974,8 +1029,9 @@ __global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ o
   }
   __syncthreads();
   const double phx = P.phi[3 * p], phy = P.phi[3 * p + 1], phz = P.phi[3 * p + 2];
-  const C cupx = (C)P.u[3 * p], cupy = (C)P.u[3 * p + 1], cupz = (C)P.u[3 * p + 2];
-  const C cwx = (C)P.om[3 * p], cwy = (C)P.om[3 * p + 1], cwz = (C)P.om[3 * p + 2];
+  const double upx = P.u[3 * p], upy = P.u[3 * p + 1], upz = P.u[3 * p + 2];
+  const double wx = P.om[3 * p], wy = P.om[3 * p + 1], wz = P.om[3 * p + 2];
+  const C cupx = (C)upx, cupy = (C)upy, cupz = (C)upz, cwx = (C)wx, cwy = (C)wy, cwz = (C)wz;
   const int e0 = P.ent0[p], ne = P.nbs[p] + P.nis[p] + P.nin[p];
   const bool jump = P.jump[p] != 0;
   constexpr int kEnt = 4;
@@ -1014,12 +1070,21 @@ __global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ o
                         cupy, cupz, cwx, cwy, cwz, rho0);
       }
       if (rep[j] != e) continue;  // another entry represents this site
-      if (o != kEmpty && !(o & 1)) {
+      if (o == 2 * e) {
+        // owned by this entry: the particle's velocities are at hand
+        const double rx = (double)ox - phx, ry = (double)oy - phy, rz = (double)oz - phz;
+        vel[4 * (size_t)e] = (C)(upx + (wy * rz - wz * ry));
+        vel[4 * (size_t)e + 1] = (C)(upy + (wz * rx - wx * rz));
+        vel[4 * (size_t)e + 2] = (C)(upz + (wx * ry - wy * rx));
+        vel[4 * (size_t)e + 3] = idx_as<C>(e);
+        ball[s] = e | kBallBS;
+      } else if (o != kEmpty && !(o & 1)) {
         store_bs_velocity<C>(vel, e, o >> 1, P, E);
         ball[s] = e | kBallBS;
       } else {
         ball[s] = e;
       }
+      bm[s] = 1;
     }
   }
 }
@@ -1089,7 +1154,7 @@ inline unsigned blocks_for(int64_t n, int per = 256) { return (unsigned)((n + pe
 // Workspace layout
 // ---------------------------------------------------------------------------
 struct Layout {
-  size_t f[2], drho, own, ball, status;
+  size_t f[2], drho, own, ball, bm, status;
   size_t x, x0, u, om, phi, fext, dP, dL, F, T, m, I, rad, b0, k, org, ent0, nbs, nis, nin, jump, box, cand_n, cand,
       pairs;
   size_t off, pid, slot, vel;
@@ -1144,6 +1209,7 @@ Layout make_layout(const lbm_params& p, const BoxSet& bs) {
   L.drho = take((size_t)N * (p.storage == LBM_FP64 ? 8 : 4));
   L.own = take(sizeof(int) * N);
   L.ball = take(sizeof(int) * N);
+  L.bm = take(N);
   L.status = take(64);
   const size_t v3 = sizeof(double) * 3 * np, v1 = sizeof(double) * np;
   L.x = take(v3); L.x0 = take(v3); L.u = take(v3); L.om = take(v3); L.phi = take(v3);
@@ -1164,7 +1230,7 @@ Layout make_layout(const lbm_params& p, const BoxSet& bs) {
   L.boxes = take(sizeof(Geo) * nbox);
   L.fbt = take(sizeof(double) * p.lattice * nbox);
   L.max_tiles = bs.max_tiles;
-  L.tiles = take(sizeof(int4) * bs.max_tiles);
+  L.tiles = take(2 * sizeof(int4) * bs.max_tiles);
   L.fc = take(sizeof(double) * 3 * np);
   L.clo = take(sizeof(float) * mlp::kParams);
   L.total = cur;
@@ -1259,7 +1325,8 @@ struct lbm_ctx {
   double* slot;
   void* vel;
   int* own;   // owner map: lowest BS/IS entry per site
-  int* ball;  // ball map: lowest entry of any kind per site
+  int* ball;  // ball map: representative entry of any kind per site
+  uint8_t* bm;  // one byte per site: 1 where ball[s] != kEmpty
   int* status;
   DevParticles P;
   DevEntries E;
@@ -1283,6 +1350,7 @@ namespace {
 template <int Q, typename T>
 SiteArgs<T> site_args(lbm_ctx* c) {
   SiteArgs<T> sa;
+  sa.bm = c->bm;
   sa.ball = c->ball;
   sa.vel = (const typename Store<T>::C*)c->vel;
   sa.slot = c->slot;
@@ -1308,12 +1376,12 @@ int launch_prepare(lbm_ctx* c, int pending) {
   using C = typename Store<T>::C;
   if (c->lds_window > 0) {
     k_prepare_local<Q, T><<<c->np, 256, c->lds_window, c->stream>>>(
-        c->own, c->ball, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c), c->prm.rho0,
-        pending, c->dim);
+        c->own, c->ball, c->bm, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
+        c->prm.rho0, pending, c->dim);
   } else {
     k_prepare<Q, T><<<blocks_for(c->nent), 256, 0, c->stream>>>(
-        c->own, c->ball, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c), (int)c->nent,
-        c->prm.rho0, pending);
+        c->own, c->ball, c->bm, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
+        (int)c->nent, c->prm.rho0, pending);
   }
   HIP_TRY(hipGetLastError());
   return LBM_OK;
@@ -1327,12 +1395,15 @@ int build_tiles(lbm_ctx* c, int w) {
     const Geo& g = c->boxes[b];
     for (int z = 0; z < g.nz; z++)
       for (int y = 0; y < g.ny; y++)
-        for (int x0 = 0; x0 < g.nx; x0 += w) t.push_back(make_int4(b, y, z, x0));
+        for (int x0 = 0; x0 < g.nx; x0 += w) {
+          t.push_back(make_int4(b, y, z, x0));
+          t.push_back(make_int4(g.nx, g.ny, g.nz, (int)g.off));
+        }
   }
-  if ((int64_t)t.size() > c->L.max_tiles) return LBM_EINVAL;
+  if ((int64_t)t.size() > 2 * c->L.max_tiles) return LBM_EINVAL;
   HIP_TRY(hipMemcpyAsync(c->d_tiles, t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  c->ntiles = (int64_t)t.size();
+  c->ntiles = (int64_t)t.size() / 2;
   c->tiles_w = w;
   return LBM_OK;
 }
@@ -1378,11 +1449,9 @@ int launch_sweep(lbm_ctx* c, int w, int grid) {
     const int64_t nt = c->ntiles;
     const unsigned g = (unsigned)(grid > 0 && grid < nt ? grid : nt);
     if (c->np > 0)
-      k_sweep_tiles<Q, T, true><<<g, w, 0, c->stream>>>(A, B, a, sa, c->d_boxes, c->d_tiles, (int)nt,
-                                                        (const C*)c->d_fbt);
+      k_sweep_tiles<Q, T, true><<<g, w, 0, c->stream>>>(A, B, a, sa, c->d_tiles, (int)nt, (const C*)c->d_fbt);
     else
-      k_sweep_tiles<Q, T, false><<<g, w, 0, c->stream>>>(A, B, a, sa, c->d_boxes, c->d_tiles, (int)nt,
-                                                         (const C*)c->d_fbt);
+      k_sweep_tiles<Q, T, false><<<g, w, 0, c->stream>>>(A, B, a, sa, c->d_tiles, (int)nt, (const C*)c->d_fbt);
   }
   HIP_TRY(hipGetLastError());
   return LBM_OK;
@@ -1409,8 +1478,8 @@ int launch_step(lbm_ctx* c) {
   if (c->np > 0) {
     const Boxes bx = boxes_arg(c);
     const double margin = c->closure ? std::max(kMargin, c->clo_h) : kMargin;
-    k_reduce<<<c->np, kBoundaryBlock, 0, c->stream>>>(c->own, c->ball, c->slot, c->P, c->E, bx, c->prm.rho0, margin,
-                                                      c->status);
+    k_reduce<<<c->np, kBoundaryBlock, 0, c->stream>>>(c->own, c->ball, c->bm, c->slot, c->P, c->E, bx, c->prm.rho0,
+                                                      margin, c->status);
     if (c->closure)
       k_closure<<<1, 256, 0, c->stream>>>(c->P, c->np, bx, c->d_clo, c->clo_h,
                                           c->prm.rho0 * (c->prm.tau - 0.5) / 3.0, c->prm.tau, c->status);
@@ -1618,6 +1687,7 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
   c->vel = c->ws + L.vel;
   c->own = (int*)(c->ws + L.own);
   c->ball = (int*)(c->ws + L.ball);
+  c->bm = (uint8_t*)(c->ws + L.bm);
   c->status = (int*)(c->ws + L.status);
   c->d_boxes = (Geo*)(c->ws + L.boxes);
   c->d_fbt = c->ws + L.fbt;
@@ -1666,6 +1736,7 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
   k_fill<uint32_t><<<blocks_for(nwords), 256, 0, c->stream>>>((uint32_t*)c->f[0], nwords, 0u);
   k_fill<int><<<blocks_for(c->NT), 256, 0, c->stream>>>(c->own, c->NT, kEmpty);
   k_fill<int><<<blocks_for(c->NT), 256, 0, c->stream>>>(c->ball, c->NT, kEmpty);
+  k_fill<uint8_t><<<blocks_for(c->NT), 256, 0, c->stream>>>(c->bm, c->NT, (uint8_t)0);
   k_fill<int><<<1, 256, 0, c->stream>>>(c->status, 16, 0);
   if (hipGetLastError() != hipSuccess || upload_boxes(c) != LBM_OK ||
       (nbox > 1 && build_tiles(c, c->sweep_w) != LBM_OK) || hipStreamSynchronize(c->stream) != hipSuccess) {
