@@ -6,7 +6,7 @@ FP32.  A step is the whole hot path (sweep, BS substep + per-particle sums,
 particle update, map rebuild, IS substep) over the box.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage fp32|fp64|fp16|bf16]
-                  [--no-cpu-baseline] [--no-variants] [--workload spheres-3d|disks-2d]
+                  [--no-cpu-baseline] [--no-variants] [--no-autotune] [--workload spheres-3d|disks-2d]
 
 The FP32 run also times the FP16 and BF16 storage variants of the same
 workload ("variants"), a 64-box D2Q9 ensemble stepped by one launch per
@@ -109,7 +109,7 @@ def ensemble_rates(torch, lbm, wl, steps, warmup, graph_steps=20):
         ens.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"], box=b)
     ens.step(warmup)
     ms_eager = clock(lambda: ens.step(steps))
-    width, grid, _ = ens.autotune(reps=5)
+    width, grid, occ, _ = ens.autotune(reps=5)
     ens.set_graph(graph_steps)
     ens.step(max(warmup, graph_steps))
     ms_graph = clock(lambda: ens.step(steps))
@@ -136,7 +136,8 @@ def ensemble_rates(torch, lbm, wl, steps, warmup, graph_steps=20):
             "eager_one_launch_per_kernel": round(rate(ms_eager), 1),
             "loop_of_single_boxes": round(rate(ms_loop), 1),
             "speedup_vs_loop": round(ms_loop / ms_graph, 2),
-            "tuned_sweep_shape": {"tile_width": width, "grid": grid}, "graph_steps": graph_steps,
+            "tuned_sweep_shape": {"tile_width": width, "grid": grid, "blocks_per_cu": occ},
+            "graph_steps": graph_steps,
             "step_roofline_frac": round(72 * rate(ms_graph) * 1e6 / 1e9 / PEAK_HBM_GBPS, 4)}
 
 
@@ -189,6 +190,8 @@ def main():
     ap.add_argument("--workload", default="spheres-3d", choices=["spheres-3d", "disks-2d"],
                     help="spheres-3d: D3Q19 256^3, 500 spheres (the headline); "
                          "disks-2d: D2Q9 1024^2, 200 disks")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default sweep launch instead of the autotuner's pick")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip timing the 64-box D2Q9 ensemble (batched) variant")
     ap.add_argument("--batched-steps", type=int, default=200)
@@ -221,8 +224,13 @@ def main():
 
     def timed(sim_, steps, warmup, profile):
         """Whole-step time of `steps` steps and, with profiling on, the summed
-        time and count of the sweep launches (HIP events on the sim's stream)."""
+        time and count of the sweep launches (HIP events on the sim's stream).
+        Unless --no-autotune, the library's autotuner picks the sweep launch
+        on the live state after the warm-up, outside the timed region."""
         sim_.step(warmup)
+        if not args.no_autotune:
+            sim_.autotune(reps=5)
+            sim_.step(2)
         torch.cuda.synchronize()
         if profile:
             sim_.set_profiling(True)
@@ -249,7 +257,8 @@ def main():
     sweep_avg_ms = sweep_ms / max(sweeps, 1)
     achieved = bps * N / (sweep_avg_ms * 1e-3) / 1e9
     ceiling = copy_ceiling(torch, lbm, stream)
-    kernel = "k_sweep<%d,%s,%s>" % (q, kname, "true" if args.particles else "false")
+    kernel = "%s<%d,%s,%s>" % ("k_sweep" if sim.sweep_config()[0] == 0 else "k_sweep_tiles", q, kname,
+                                "true" if args.particles else "false")
     traffic = None
     if args.particles == len(cfg["particles"]["radius"]):
         traffic = measured_traffic(kernel.replace(",", ", "), cfg["name"], args.storage)
@@ -270,7 +279,8 @@ def main():
                    "tau": cfg["tau"], "particles": args.particles,
                    "radius": float(np.max(cfg["particles"]["radius"])),
                    "density_ratio": 1.2 if q == 19 else 1.5, "gravity": float(-min(cfg["gravity"])),
-                   "storage": args.storage, "parallelism": "single-gpu"},
+                   "storage": args.storage, "parallelism": "single-gpu",
+                   "sweep_launch": dict(zip(("width", "grid", "blocks_per_cu"), sim.sweep_config()))},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBPS, 4),
                      "traffic": None if traffic is None else traffic["total"],
@@ -296,6 +306,7 @@ def main():
             vm = N / (vms / args.steps * 1e-3) / 1e6
             vs = vsw / max(vn, 1)
             out["variants"][st] = {"value": round(vm, 1), "ms_per_step": round(vms / args.steps, 4),
+                                   "sweep_launch": dict(zip(("width", "grid", "blocks_per_cu"), v.sweep_config())),
                                    "speedup_vs_fp32": round(vm / mlups, 3), "bytes_per_site": vb,
                                    "sweep_avg_ms": round(vs, 4), "sweep_GBps": round(vb * N / (vs * 1e-3) / 1e9, 1)}
             v.close()

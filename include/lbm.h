@@ -203,16 +203,25 @@ int lbm_box_info(lbm_ctx* ctx, int32_t box, int32_t* dims, int64_t* first_site, 
 /* ---- launch shape, autotuning and step graphs ---------------------------
  * The sweep runs either as the one-box row kernel (width 0; one box only) or
  * as a persistent kernel over tiles of `width` sites of one row (64, 128, 256
- * or 512) with `grid` workgroups (0: one per tile).  Every shape computes the
- * same values bit for bit. */
-int lbm_set_sweep_config(lbm_ctx* ctx, int32_t width, int32_t grid);
-int lbm_get_sweep_config(lbm_ctx* ctx, int32_t* width, int32_t* grid);
+ * or 512) with `grid` workgroups (0: one per tile).  blocks_per_cu > 0 caps
+ * the sweep workgroups resident on one compute unit at that number, through
+ * LDS each workgroup reserves (floor(LDS per CU / blocks_per_cu), whole KiB;
+ * LBM_EINVAL if that exceeds what one workgroup may reserve or is below
+ * 1 KiB); 0 leaves residency to the register count.  Fewer resident waves
+ * can stream faster: fewer DRAM rows open at once.  Every shape computes the
+ * same values bit for bit.  Defaults: width 0 (one box) or 128, grid 0, no
+ * cap. */
+int lbm_set_sweep_config(lbm_ctx* ctx, int32_t width, int32_t grid, int32_t blocks_per_cu);
+int lbm_get_sweep_config(lbm_ctx* ctx, int32_t* width, int32_t* grid, int32_t* blocks_per_cu);
 
-/* Time every sweep shape (reps launches each, after one warm-up) on the
- * context's own state and keep the fastest; returns it and its time per
- * sweep in ms.  Sweeping again from the same state recomputes the same
- * values, so the simulation is unchanged.  Synchronises. */
-int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* width, int32_t* grid, double* best_ms);
+/* Time every sweep shape (widths 0 (one box), 64, 128, 256, 512; grids 0 and
+ * 4, 8, 16, 32 per CU; caps none, 6, 5, 4, 3, 2 workgroups per CU; reps
+ * launches each, after one warm-up) on the context's own state and keep the
+ * fastest; returns it and its time per sweep in ms (any output pointer may be
+ * NULL).  Sweeping again from the same state recomputes the same values, so
+ * the simulation is unchanged.  Synchronises. */
+int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* width, int32_t* grid, int32_t* blocks_per_cu,
+                 double* best_ms);
 
 /* steps_per_graph > 0 (even): lbm_step replays a HIP graph of that many
  * steps, captured on the first use and again after the particle set, the

@@ -4,9 +4,9 @@
 // One time step is five launches on the caller's stream:
 //   sweep      one streaming pass over every site, A -> B (HBM bound; SoA,
 //              x fastest, coalesced): pull-propagation of the previous step
-//              with its pending IS substep folded into the pull, BGK collision
-//              with body force, and the BS substep at owned BS sites (the
-//              site's post-collision moments go to the entry's slot).
+//              (whose IS substep is already in A), BGK collision with body
+//              force, and the BS substep at owned BS sites (the site's
+//              post-collision moments go to the owner entry's slot).
 //                                                          eq. 1-5, 12, 3 (left)
 //   reduce     one workgroup per particle: momentum dp and angular momentum dl
 //              of every owned BS site from its slot, deterministic
@@ -17,18 +17,19 @@
 //              translation and integer shift.               eq. 10-11, 13, 16-19
 //   stamp      rebuild the maps at the new shifts: the owner map (lowest BS/IS
 //              entry index, hence lowest particle id; stored as 2e + [IS]) and
-//              the ball map (lowest entry of any kind: one representative
-//              entry per ball site).
+//              the ball map (one representative entry of any kind per ball
+//              site: whichever write lands last).
 //                                                                    eq. 14-15
 //   prepare    one workgroup per particle: the IS substep at the new
 //              positions (eq. 12) written in place into the post-collision
 //              state -- f^eq_i(rho_I, u_p' + omega_p' x r) at every owned IS
-//              site -- and, for every owned BS site, the ball-map flag and the
+//              site -- and, through each ball site's representative entry,
+//              the site flag and, at an owned BS site, its record: the
 //              rigid-body velocity u_p + omega x r of its next BS substep
-//              (eq. 5).
+//              (eq. 5) and the owner entry.
 // The IS substep of step t acts on the post-collision populations of IS sites
 // just before they propagate; written into the state, it is what the sweep of
-// step t+1 pulls.  Outside every ball the sweep reads one map word and
+// step t+1 pulls.  Outside every ball the sweep reads one flag byte and
 // nothing more.
 // The populations are stored as deviations g_i = f_i - w_i rho0 so that the
 // momentum differences behind the particle forces survive FP32 storage.
@@ -50,8 +51,8 @@ namespace {
 
 constexpr int kEmpty = 0x7fffffff;  // map value of a site no entry claims
 constexpr int64_t kMaxEntries = (int64_t)1 << 29;  // owner map stores 2e + 1 < kEmpty
-constexpr int kBallBS = 1 << 29;                   // ball map flag: the site is an owned BS site
-constexpr int kEntryMask = kBallBS - 1;
+constexpr uint8_t kSiteBall = 1;  // site flag: some ball covers the site
+constexpr uint8_t kSiteBS = 2;    // site flag: an owned BS site (its record is valid)
 constexpr int kCandMax = 64;        // close neighbours listed per particle
 constexpr double kMargin = 1.0;     // candidate search margin (lattice units)
 constexpr int kSweepBlock = 256;
@@ -225,20 +226,24 @@ __device__ __forceinline__ int entry_site(const DevParticles& P, const Geo& G, i
 }
 
 // ---------------------------------------------------------------------------
-// Ball sites.  ball[s] holds an entry of any kind stamped at s (kEmpty
-// outside every ball), flagged with kBallBS when s is an owned BS site; then
-// vel[4b..4b+2] is the rigid-body velocity of its next BS substep and
-// vel[4b+3] the index of the owning BS entry, whose slot receives the site's
-// post-collision moments.
+// Ball sites.  flag[s] is 0 outside every ball, kSiteBall inside one and
+// kSiteBS at an owned BS site; there the site's record vel[4s..4s+2] is the
+// rigid-body velocity of its next BS substep and vel[4s+3] the index of the
+// owning BS entry, whose slot receives the site's post-collision moments.
+// The sweep reads the one-byte flag of every site and the record of BS sites
+// only, so it never waits on a map lookup before its own pulls.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct SiteArgs {
-  const uint8_t* bm;  // one byte per site: 1 where some ball covers it
-  const int* ball;
-  const typename Store<T>::C* vel;  // [entry][4]
+  const uint8_t* flag;              // [site]: 0, kSiteBall or kSiteBS
+  const typename Store<T>::C* vel;  // [site][4]: record of a kSiteBS site
   double* slot;                     // [entry][4]: post-collision drho, j of an owned BS site
   typename Store<T>::C* drho;       // density deviation of every ball site (this sweep)
 };
+
+// One site record as a single 16- (FP32) or 32-byte (FP64) load.
+__device__ __forceinline__ float4 ld_rec(const float* p) { return *(const float4*)p; }
+__device__ __forceinline__ double4 ld_rec(const double* p) { return *(const double4*)p; }
 
 // An entry index carried in a velocity record's fourth slot (bit pattern in
 // FP32, exact value in FP64).
@@ -316,8 +321,8 @@ __device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restric
   const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
   const int s = off + x + nx * (y + ny * z);
 
-  // the bitmap first: sites outside every ball read 1 bit, not a map word
-  const int bv = PART && sa.bm[s] ? sa.ball[s] : kEmpty;
+  // the flag is issued first and waited on only after the collision
+  const int fl = PART ? (int)sa.flag[s] : 0;
   // 16-bit storage collides on the stored numbers h_i = g_i / (w_i sigma):
   // there the weight cancels from the equilibrium, h_i^eq = (drho + rho (3cu
   // + 9/2 cu^2 - 3/2 u^2)) / sigma, which saves the per-direction scalings;
@@ -366,15 +371,15 @@ __device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restric
       g[i] = g[i] + a.omega * (geq - g[i]) + fbt[i];
     }
   }
-  if (PART && bv != kEmpty) {
+  if (PART && fl != 0) {
     sa.drho[s] = drho;
-    if (bv & kBallBS) {
+    if (fl == kSiteBS) {
       // BS substep at an owned BS site: its post-collision moments go to the
       // owner's slot (FP64 sums), and the populations become f^eq(rho_B,
       // u_B') with the rigid-body velocity u_B' = u_p + omega x r of the site
-      const size_t b = (size_t)(bv & kEntryMask);
-      const C vx = sa.vel[4 * b], vy = sa.vel[4 * b + 1], vz = sa.vel[4 * b + 2];
-      const int bs = as_idx<C>(sa.vel[4 * b + 3]);
+      const auto rec = ld_rec(sa.vel + 4 * (size_t)s);
+      const C vx = rec.x, vy = rec.y, vz = rec.z;
+      const int bs = as_idx<C>(rec.w);
       double dr = 0, bx = 0, by = 0, bz = 0;
 #pragma unroll
       for (int i = 0; i < Q; i++) {
@@ -634,7 +639,7 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int np, int di
 // this step.  One workgroup per particle.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own, int* __restrict__ ball,
-                                                            uint8_t* __restrict__ bm, const double* __restrict__ slot,
+                                                            uint8_t* __restrict__ flag, const double* __restrict__ slot,
                                                             DevParticles P, DevEntries E, Boxes BX,
                                                             double rho0, double margin, int* status) {
   constexpr int kWaves = kBoundaryBlock / 64;
@@ -676,7 +681,7 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
       const int kind = entry_kind(pk);
       const int s = sv[j];
       ball[s] = kEmpty;
-      bm[s] = 0;
+      flag[s] = 0;
       if (kind == 2 && ov[j] == 2 * e + 1) own[s] = kEmpty;
       if (kind != 1 || ov[j] != 2 * e) continue;  // BS sites owned by this entry only
       own[s] = kEmpty;                             // only the owner clears its site
@@ -901,9 +906,9 @@ __global__ __launch_bounds__(256) void k_closure(DevParticles P, int np, Boxes B
 //    site may then lie outside the ball the sweep kept densities for); the
 //    owner reads them before it overwrites them, and no other thread touches
 //    that site.
-//  - Records: the entry representing a ball site flags it in the ball map
-//    when the site is an owned BS site and stores the rigid-body velocity of
-//    the next BS substep (eq. 5) with the owner entry's index.
+//  - Records: the entry representing a ball site (ball map) sets its flag,
+//    kSiteBS at an owned BS site, whose record then receives the rigid-body
+//    velocity of the next BS substep (eq. 5) and the owner entry's index.
 // ---------------------------------------------------------------------------
 // IS values of site s (offset o of particle p with the particle's velocities
 // in the compute type; the value is stored in it).
@@ -928,24 +933,25 @@ __device__ __forceinline__ void impose_is(T* __restrict__ S, int64_t NT, int s, 
   }
 }
 
-// Rigid-body velocity u_q + omega_q x r of BS entry bs into vel[4e..4e+3].
+// Record of site s owned by BS entry bs: rigid-body velocity u_q + omega_q x r
+// and bs, into vel[4s..4s+3].
 template <typename C>
-__device__ __forceinline__ void store_bs_velocity(C* __restrict__ vel, int e, int bs, const DevParticles& P,
+__device__ __forceinline__ void store_bs_velocity(C* __restrict__ vel, int s, int bs, const DevParticles& P,
                                                   const DevEntries& E) {
   const int q = E.pid[bs];
   const int ok = E.off[bs];
   const double rx = (double)off_x(ok) - P.phi[3 * q], ry = (double)off_y(ok) - P.phi[3 * q + 1],
                rz = (double)off_z(ok) - P.phi[3 * q + 2];
   const double ax = P.om[3 * q], ay = P.om[3 * q + 1], az = P.om[3 * q + 2];
-  vel[4 * (size_t)e] = (C)(P.u[3 * q] + (ay * rz - az * ry));
-  vel[4 * (size_t)e + 1] = (C)(P.u[3 * q + 1] + (az * rx - ax * rz));
-  vel[4 * (size_t)e + 2] = (C)(P.u[3 * q + 2] + (ax * ry - ay * rx));
-  vel[4 * (size_t)e + 3] = idx_as<C>(bs);
+  vel[4 * (size_t)s] = (C)(P.u[3 * q] + (ay * rz - az * ry));
+  vel[4 * (size_t)s + 1] = (C)(P.u[3 * q + 1] + (az * rx - ax * rz));
+  vel[4 * (size_t)s + 2] = (C)(P.u[3 * q + 2] + (ax * ry - ay * rx));
+  vel[4 * (size_t)s + 3] = idx_as<C>(bs);
 }
 
 template <int Q, typename T>
-__global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own, int* __restrict__ ball,
-                                                  uint8_t* __restrict__ bm, typename Store<T>::C* __restrict__ vel,
+__global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own, const int* __restrict__ ball,
+                                                  uint8_t* __restrict__ flag, typename Store<T>::C* __restrict__ vel,
                                                   const typename Store<T>::C* __restrict__ drho, T* __restrict__ S,
                                                   DevParticles P, DevEntries E, Boxes BX, int nent, double rho0,
                                                   int pending) {
@@ -971,22 +977,21 @@ __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own, in
                     (C)((double)off_z(pk) - P.phi[3 * p + 2]), (C)P.u[3 * p], (C)P.u[3 * p + 1], (C)P.u[3 * p + 2],
                     (C)P.om[3 * p], (C)P.om[3 * p + 1], (C)P.om[3 * p + 2], rho0);
   }
-  if ((ball[s] & kEntryMask) != e) return;  // another entry represents this site
-  if (o != kEmpty && !(o & 1)) {            // an owned BS site
-    store_bs_velocity<C>(vel, e, o >> 1, P, E);
-    ball[s] = e | kBallBS;
+  if (ball[s] != e) return;       // another entry represents this site
+  if (o != kEmpty && !(o & 1)) {  // an owned BS site
+    store_bs_velocity<C>(vel, s, o >> 1, P, E);
+    flag[s] = kSiteBS;
   } else {
-    ball[s] = e;
+    flag[s] = kSiteBall;
   }
-  bm[s] = 1;
 }
 
 // The same per particle (one workgroup each), with the owner map and the
 // densities of a window around the ball staged in LDS: row-coalesced loads
 // instead of scattered lookups.  Half-width hw = floor(r + 1/2) + 1.
 template <int Q, typename T>
-__global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ own, int* __restrict__ ball,
-                                                        uint8_t* __restrict__ bm, typename Store<T>::C* __restrict__ vel,
+__global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ own, const int* __restrict__ ball,
+                                                        uint8_t* __restrict__ flag, typename Store<T>::C* __restrict__ vel,
                                                         const typename Store<T>::C* __restrict__ drho,
                                                         T* __restrict__ S, DevParticles P, DevEntries E, Boxes BX,
                                                         double rho0, int pending, int dim) {
@@ -1045,7 +1050,7 @@ __global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ o
         pkv[j] = E.off[e0 + t];
         const int x = wrap1(ox0 + off_x(pkv[j]), G.nx), y = wrap1(oy0 + off_y(pkv[j]), G.ny),
                   z = wrap1(oz0 + off_z(pkv[j]), G.nz);
-        rep[j] = ball[site_of(G, x, y, z)] & kEntryMask;
+        rep[j] = ball[site_of(G, x, y, z)];
       }
     }
 #pragma unroll 1
@@ -1073,18 +1078,17 @@ __global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ o
       if (o == 2 * e) {
         // owned by this entry: the particle's velocities are at hand
         const double rx = (double)ox - phx, ry = (double)oy - phy, rz = (double)oz - phz;
-        vel[4 * (size_t)e] = (C)(upx + (wy * rz - wz * ry));
-        vel[4 * (size_t)e + 1] = (C)(upy + (wz * rx - wx * rz));
-        vel[4 * (size_t)e + 2] = (C)(upz + (wx * ry - wy * rx));
-        vel[4 * (size_t)e + 3] = idx_as<C>(e);
-        ball[s] = e | kBallBS;
+        vel[4 * (size_t)s] = (C)(upx + (wy * rz - wz * ry));
+        vel[4 * (size_t)s + 1] = (C)(upy + (wz * rx - wx * rz));
+        vel[4 * (size_t)s + 2] = (C)(upz + (wx * ry - wy * rx));
+        vel[4 * (size_t)s + 3] = idx_as<C>(e);
+        flag[s] = kSiteBS;
       } else if (o != kEmpty && !(o & 1)) {
-        store_bs_velocity<C>(vel, e, o >> 1, P, E);
-        ball[s] = e | kBallBS;
+        store_bs_velocity<C>(vel, s, o >> 1, P, E);
+        flag[s] = kSiteBS;
       } else {
-        ball[s] = e;
+        flag[s] = kSiteBall;
       }
-      bm[s] = 1;
     }
   }
 }
@@ -1154,7 +1158,7 @@ inline unsigned blocks_for(int64_t n, int per = 256) { return (unsigned)((n + pe
 // Workspace layout
 // ---------------------------------------------------------------------------
 struct Layout {
-  size_t f[2], drho, own, ball, bm, status;
+  size_t f[2], drho, own, ball, flag, status;
   size_t x, x0, u, om, phi, fext, dP, dL, F, T, m, I, rad, b0, k, org, ent0, nbs, nis, nin, jump, box, cand_n, cand,
       pairs;
   size_t off, pid, slot, vel;
@@ -1209,7 +1213,7 @@ Layout make_layout(const lbm_params& p, const BoxSet& bs) {
   L.drho = take((size_t)N * (p.storage == LBM_FP64 ? 8 : 4));
   L.own = take(sizeof(int) * N);
   L.ball = take(sizeof(int) * N);
-  L.bm = take(N);
+  L.flag = take(N);
   L.status = take(64);
   const size_t v3 = sizeof(double) * 3 * np, v1 = sizeof(double) * np;
   L.x = take(v3); L.x0 = take(v3); L.u = take(v3); L.om = take(v3); L.phi = take(v3);
@@ -1226,7 +1230,7 @@ Layout make_layout(const lbm_params& p, const BoxSet& bs) {
   L.off = take(sizeof(int) * L.max_ent);
   L.pid = take(sizeof(int) * L.max_ent);
   L.slot = take(sizeof(double) * 4 * L.max_ent);
-  L.vel = take((p.storage == LBM_FP64 ? 8 : 4) * 4 * L.max_ent);
+  L.vel = take((p.storage == LBM_FP64 ? 8 : 4) * 4 * N);
   L.boxes = take(sizeof(Geo) * nbox);
   L.fbt = take(sizeof(double) * p.lattice * nbox);
   L.max_tiles = bs.max_tiles;
@@ -1304,13 +1308,15 @@ struct lbm_ctx {
   int64_t ntiles;           // tiles of the current tile width
   int tiles_w;              // tile width the table was built for (0: none)
   int sweep_w, sweep_grid;  // sweep launch shape: w = 0 the one-box kernel, else tile width; grid 0 = one per tile
+  int sweep_occ;            // cap on resident sweep workgroups per CU (0: none)
+  int lds_cu, lds_block;    // LDS bytes per CU and the most one workgroup may reserve
   std::vector<int> h_box;   // box of every particle
   std::vector<double> fbb;  // [nbox][3] fluid body force density
   // step graph
   hipStream_t cap;
   hipGraph_t graph;
   hipGraphExec_t gexec;
-  int g_steps, g_cur, g_w, g_grid;
+  int g_steps, g_cur, g_w, g_grid, g_occ;
   int64_t g_np, g_nent;
   int graph_steps;          // 0: eager launches
   int closure;              // near-contact closure network on
@@ -1326,7 +1332,7 @@ struct lbm_ctx {
   void* vel;
   int* own;   // owner map: lowest BS/IS entry per site
   int* ball;  // ball map: representative entry of any kind per site
-  uint8_t* bm;  // one byte per site: 1 where ball[s] != kEmpty
+  uint8_t* flag;  // [site]: 0, kSiteBall or kSiteBS
   int* status;
   DevParticles P;
   DevEntries E;
@@ -1350,8 +1356,7 @@ namespace {
 template <int Q, typename T>
 SiteArgs<T> site_args(lbm_ctx* c) {
   SiteArgs<T> sa;
-  sa.bm = c->bm;
-  sa.ball = c->ball;
+  sa.flag = c->flag;
   sa.vel = (const typename Store<T>::C*)c->vel;
   sa.slot = c->slot;
   sa.drho = (typename Store<T>::C*)c->drho;
@@ -1376,11 +1381,11 @@ int launch_prepare(lbm_ctx* c, int pending) {
   using C = typename Store<T>::C;
   if (c->lds_window > 0) {
     k_prepare_local<Q, T><<<c->np, 256, c->lds_window, c->stream>>>(
-        c->own, c->ball, c->bm, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
+        c->own, c->ball, c->flag, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
         c->prm.rho0, pending, c->dim);
   } else {
     k_prepare<Q, T><<<blocks_for(c->nent), 256, 0, c->stream>>>(
-        c->own, c->ball, c->bm, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
+        c->own, c->ball, c->flag, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
         (int)c->nent, c->prm.rho0, pending);
   }
   HIP_TRY(hipGetLastError());
@@ -1432,9 +1437,19 @@ SweepArgs<Q, typename Store<T>::C> sweep_args(const lbm_ctx* c) {
 }
 
 // One sweep in the context's launch shape.
+// LDS each sweep workgroup reserves so that at most occ of them are resident
+// on one CU (0 for no cap), in whole KiB; occ_ok: the amount fits one
+// workgroup's limit.
+size_t sweep_lds(const lbm_ctx* c, int occ) { return occ > 0 ? (size_t)(c->lds_cu / occ) & ~(size_t)1023 : 0; }
+bool occ_ok(const lbm_ctx* c, int occ) {
+  return occ == 0 || (occ > 0 && occ <= 32 && sweep_lds(c, occ) >= 1024 && sweep_lds(c, occ) <= (size_t)c->lds_block);
+}
+
 template <int Q, typename T>
-int launch_sweep(lbm_ctx* c, int w, int grid) {
+int launch_sweep(lbm_ctx* c, int w, int grid, int occ) {
   using C = typename Store<T>::C;
+  // the occupancy cap: LDS reserved (not used) by every workgroup
+  const size_t lds = sweep_lds(c, occ);
   const SweepArgs<Q, C> a = sweep_args<Q, T>(c);
   const T* A = (const T*)c->f[c->cur];
   T* B = (T*)c->f[1 - c->cur];
@@ -1442,16 +1457,16 @@ int launch_sweep(lbm_ctx* c, int w, int grid) {
   if (w == 0) {
     const unsigned nblk = (unsigned)((int64_t)a.nxb * c->G.ny * c->G.nz);
     if (c->np > 0)
-      k_sweep<Q, T, true><<<nblk, kSweepBlock, 0, c->stream>>>(A, B, a, sa);
+      k_sweep<Q, T, true><<<nblk, kSweepBlock, lds, c->stream>>>(A, B, a, sa);
     else
-      k_sweep<Q, T, false><<<nblk, kSweepBlock, 0, c->stream>>>(A, B, a, sa);
+      k_sweep<Q, T, false><<<nblk, kSweepBlock, lds, c->stream>>>(A, B, a, sa);
   } else {
     const int64_t nt = c->ntiles;
     const unsigned g = (unsigned)(grid > 0 && grid < nt ? grid : nt);
     if (c->np > 0)
-      k_sweep_tiles<Q, T, true><<<g, w, 0, c->stream>>>(A, B, a, sa, c->d_tiles, (int)nt, (const C*)c->d_fbt);
+      k_sweep_tiles<Q, T, true><<<g, w, lds, c->stream>>>(A, B, a, sa, c->d_tiles, (int)nt, (const C*)c->d_fbt);
     else
-      k_sweep_tiles<Q, T, false><<<g, w, 0, c->stream>>>(A, B, a, sa, c->d_tiles, (int)nt, (const C*)c->d_fbt);
+      k_sweep_tiles<Q, T, false><<<g, w, lds, c->stream>>>(A, B, a, sa, c->d_tiles, (int)nt, (const C*)c->d_fbt);
   }
   HIP_TRY(hipGetLastError());
   return LBM_OK;
@@ -1469,7 +1484,7 @@ int launch_step(lbm_ctx* c) {
     }
     HIP_TRY(hipEventRecord(c->ev[c->ev_used], c->stream));
   }
-  const int rc = launch_sweep<Q, T>(c, c->sweep_w, c->sweep_grid);
+  const int rc = launch_sweep<Q, T>(c, c->sweep_w, c->sweep_grid, c->sweep_occ);
   if (rc != LBM_OK) return rc;
   if (c->prof) {
     HIP_TRY(hipEventRecord(c->ev[c->ev_used + 1], c->stream));
@@ -1478,7 +1493,7 @@ int launch_step(lbm_ctx* c) {
   if (c->np > 0) {
     const Boxes bx = boxes_arg(c);
     const double margin = c->closure ? std::max(kMargin, c->clo_h) : kMargin;
-    k_reduce<<<c->np, kBoundaryBlock, 0, c->stream>>>(c->own, c->ball, c->bm, c->slot, c->P, c->E, bx, c->prm.rho0,
+    k_reduce<<<c->np, kBoundaryBlock, 0, c->stream>>>(c->own, c->ball, c->flag, c->slot, c->P, c->E, bx, c->prm.rho0,
                                                       margin, c->status);
     if (c->closure)
       k_closure<<<1, 256, 0, c->stream>>>(c->P, c->np, bx, c->d_clo, c->clo_h,
@@ -1687,7 +1702,7 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
   c->vel = c->ws + L.vel;
   c->own = (int*)(c->ws + L.own);
   c->ball = (int*)(c->ws + L.ball);
-  c->bm = (uint8_t*)(c->ws + L.bm);
+  c->flag = (uint8_t*)(c->ws + L.flag);
   c->status = (int*)(c->ws + L.status);
   c->d_boxes = (Geo*)(c->ws + L.boxes);
   c->d_fbt = c->ws + L.fbt;
@@ -1697,6 +1712,16 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
   // one box: the row kernel; an ensemble: tiles of 128 sites, one workgroup each
   c->sweep_w = nbox == 1 ? 0 : 128;
   c->sweep_grid = 0;
+  c->sweep_occ = 0;
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&c->lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&c->lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+      delete c;
+      return LBM_EHIP;
+    }
+  }
   c->cap = nullptr;
   c->graph = nullptr;
   c->gexec = nullptr;
@@ -1736,7 +1761,7 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
   k_fill<uint32_t><<<blocks_for(nwords), 256, 0, c->stream>>>((uint32_t*)c->f[0], nwords, 0u);
   k_fill<int><<<blocks_for(c->NT), 256, 0, c->stream>>>(c->own, c->NT, kEmpty);
   k_fill<int><<<blocks_for(c->NT), 256, 0, c->stream>>>(c->ball, c->NT, kEmpty);
-  k_fill<uint8_t><<<blocks_for(c->NT), 256, 0, c->stream>>>(c->bm, c->NT, (uint8_t)0);
+  k_fill<uint8_t><<<blocks_for(c->NT), 256, 0, c->stream>>>(c->flag, c->NT, (uint8_t)0);
   k_fill<int><<<1, 256, 0, c->stream>>>(c->status, 16, 0);
   if (hipGetLastError() != hipSuccess || upload_boxes(c) != LBM_OK ||
       (nbox > 1 && build_tiles(c, c->sweep_w) != LBM_OK) || hipStreamSynchronize(c->stream) != hipSuccess) {
@@ -1942,7 +1967,7 @@ int lbm_ensemble_add_particles(lbm_ctx* c, int32_t box, int32_t n, const double*
 // particle set, the buffer roles or the sweep launch shape changed.
 static int ensure_graph(lbm_ctx* c) {
   if (c->gexec && c->g_steps == c->graph_steps && c->g_cur == c->cur && c->g_np == c->np &&
-      c->g_nent == c->nent && c->g_w == c->sweep_w && c->g_grid == c->sweep_grid)
+      c->g_nent == c->nent && c->g_w == c->sweep_w && c->g_grid == c->sweep_grid && c->g_occ == c->sweep_occ)
     return LBM_OK;
   drop_graph(c);
   if (!c->cap) HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
@@ -1973,6 +1998,7 @@ static int ensure_graph(lbm_ctx* c) {
   c->g_nent = c->nent;
   c->g_w = c->sweep_w;
   c->g_grid = c->sweep_grid;
+  c->g_occ = c->sweep_occ;
   return LBM_OK;
 }
 
@@ -2005,8 +2031,8 @@ int lbm_set_graph(lbm_ctx* c, int32_t steps_per_graph) {
   return LBM_OK;
 }
 
-int lbm_set_sweep_config(lbm_ctx* c, int32_t width, int32_t grid) {
-  if (!c || grid < 0) return LBM_EINVAL;
+int lbm_set_sweep_config(lbm_ctx* c, int32_t width, int32_t grid, int32_t blocks_per_cu) {
+  if (!c || grid < 0 || !occ_ok(c, blocks_per_cu)) return LBM_EINVAL;
   if (width != 0 && width != 64 && width != 128 && width != 256 && width != 512) return LBM_EINVAL;
   if (width == 0 && c->nbox != 1) return LBM_EINVAL;  // the row kernel covers one box
   if (width > 0) {
@@ -2015,17 +2041,20 @@ int lbm_set_sweep_config(lbm_ctx* c, int32_t width, int32_t grid) {
   }
   c->sweep_w = width;
   c->sweep_grid = width > 0 ? grid : 0;
+  c->sweep_occ = blocks_per_cu;
   return LBM_OK;
 }
 
-int lbm_get_sweep_config(lbm_ctx* c, int32_t* width, int32_t* grid) {
+int lbm_get_sweep_config(lbm_ctx* c, int32_t* width, int32_t* grid, int32_t* blocks_per_cu) {
   if (!c) return LBM_EINVAL;
   if (width) *width = c->sweep_w;
   if (grid) *grid = c->sweep_grid;
+  if (blocks_per_cu) *blocks_per_cu = c->sweep_occ;
   return LBM_OK;
 }
 
-int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* width, int32_t* grid, double* best_ms) {
+int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* width, int32_t* grid, int32_t* blocks_per_cu,
+                 double* best_ms) {
   if (!c || reps < 1) return LBM_EINVAL;
   // a sweep recomputes B and the ball-site scratch from A and the records,
   // so repeating it leaves the state as one sweep does: time the candidates
@@ -2034,23 +2063,27 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* width, int32_t* grid, double
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   struct Cand {
-    int w, g;
+    int w, g, occ;
   };
+  // shapes x occupancy caps (fewer resident waves can stream faster)
   std::vector<Cand> cands;
-  if (c->nbox == 1) cands.push_back({0, 0});
-  for (int w : {64, 128, 256, 512})
-    for (int k : {0, 4, 8, 16, 32}) cands.push_back({w, k * ncu});
+  for (int occ : {0, 6, 5, 4, 3, 2}) {
+    if (!occ_ok(c, occ)) continue;
+    if (c->nbox == 1) cands.push_back({0, 0, occ});
+    for (int w : {64, 128, 256, 512})
+      for (int k : {0, 4, 8, 16, 32}) cands.push_back({w, k * ncu, occ});
+  }
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   int rc = LBM_OK;
   double best = 1e300;
-  Cand win = {c->sweep_w, c->sweep_grid};
+  Cand win = {c->sweep_w, c->sweep_grid, c->sweep_occ};
   for (const Cand& cd : cands) {
     if (cd.w > 0 && (rc = build_tiles(c, cd.w)) != LBM_OK) break;
-    if ((rc = DISPATCH(c, launch_sweep, c, cd.w, cd.g)) != LBM_OK) break;  // warm-up
+    if ((rc = DISPATCH(c, launch_sweep, c, cd.w, cd.g, cd.occ)) != LBM_OK) break;  // warm-up
     if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = LBM_EHIP; break; }
-    for (int r = 0; r < reps && rc == LBM_OK; r++) rc = DISPATCH(c, launch_sweep, c, cd.w, cd.g);
+    for (int r = 0; r < reps && rc == LBM_OK; r++) rc = DISPATCH(c, launch_sweep, c, cd.w, cd.g, cd.occ);
     if (rc != LBM_OK) break;
     float ms = 0;
     if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -2066,10 +2099,11 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* width, int32_t* grid, double
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != LBM_OK) return rc;
-  rc = lbm_set_sweep_config(c, win.w, win.g);
+  rc = lbm_set_sweep_config(c, win.w, win.g, win.occ);
   if (rc != LBM_OK) return rc;
   if (width) *width = win.w;
   if (grid) *grid = win.g;
+  if (blocks_per_cu) *blocks_per_cu = win.occ;
   if (best_ms) *best_ms = best;
   return LBM_OK;
 }

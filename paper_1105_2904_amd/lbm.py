@@ -71,9 +71,9 @@ def lib():
             "lbm_ensemble_create": [P, ctypes.c_int32, _ip, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)],
             "lbm_ensemble_add_particles": [vp, ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp, _dp, _dp, _dp, _ip],
             "lbm_box_info": [vp, ctypes.c_int32, _ip, ctypes.POINTER(ctypes.c_int64), _ip, _ip],
-            "lbm_set_sweep_config": [vp, ctypes.c_int32, ctypes.c_int32],
-            "lbm_get_sweep_config": [vp, _ip, _ip],
-            "lbm_autotune": [vp, ctypes.c_int32, _ip, _ip, _dp],
+            "lbm_set_sweep_config": [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+            "lbm_get_sweep_config": [vp, _ip, _ip, _ip],
+            "lbm_autotune": [vp, ctypes.c_int32, _ip, _ip, _ip, _dp],
             "lbm_set_graph": [vp, ctypes.c_int32],
             "lbm_set_closure": [vp, vp, ctypes.c_double],
             "lbm_closure_inputs": [ctypes.c_int32, _dp, _dp, _dp, _dp, ctypes.c_double, vp],
@@ -242,19 +242,24 @@ class Simulation:
                                   ctypes.byref(p0), ctypes.byref(n)), "lbm_box_info")
         return dims, s0.value, p0.value, n.value
 
-    def set_sweep_config(self, width, grid=0):
-        _check(lib().lbm_set_sweep_config(self.ctx, int(width), int(grid)), "lbm_set_sweep_config")
+    def set_sweep_config(self, width, grid=0, blocks_per_cu=0):
+        _check(lib().lbm_set_sweep_config(self.ctx, int(width), int(grid), int(blocks_per_cu)),
+               "lbm_set_sweep_config")
 
     def sweep_config(self):
-        w, g = ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().lbm_get_sweep_config(self.ctx, ctypes.byref(w), ctypes.byref(g)), "lbm_get_sweep_config")
-        return w.value, g.value
+        """(width, grid, blocks_per_cu) of the sweep launch."""
+        w, g, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().lbm_get_sweep_config(self.ctx, ctypes.byref(w), ctypes.byref(g), ctypes.byref(k)),
+               "lbm_get_sweep_config")
+        return w.value, g.value, k.value
 
     def autotune(self, reps=5):
-        w, g, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
-        _check(lib().lbm_autotune(self.ctx, int(reps), ctypes.byref(w), ctypes.byref(g), ctypes.byref(ms)),
-               "lbm_autotune")
-        return w.value, g.value, ms.value
+        """Picks and sets the fastest sweep launch; returns (width, grid,
+        blocks_per_cu, ms per sweep)."""
+        w, g, k, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(lib().lbm_autotune(self.ctx, int(reps), ctypes.byref(w), ctypes.byref(g), ctypes.byref(k),
+                                  ctypes.byref(ms)), "lbm_autotune")
+        return w.value, g.value, k.value, ms.value
 
     def set_closure(self, params, h_max=2.0):
         """Near-contact closure with the network parameters `params` (a float32

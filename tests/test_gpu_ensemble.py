@@ -129,22 +129,28 @@ def _same(a, b):
 
 
 def test_sweep_shapes_and_autotune_give_identical_bits():
-    """One box: the row kernel, tile kernels of every width, a persistent grid
-    and the autotuner's pick all produce the same state after 30 steps."""
+    """One box: the row kernel, tile kernels of every width, a persistent grid,
+    occupancy caps and the autotuner's pick all produce the same state after
+    30 steps; caps outside the allowed range are refused."""
     box = (70, 45, 1)
     p = wl.suspension(9, box, 3, 5.0, 1.5, seed=81)
     ref = None
-    for shape in [(0, 0), (64, 0), (128, 16), (512, 0), "auto"]:
+    for shape in [(0, 0, 0), (64, 0, 0), (128, 16, 0), (512, 0, 0), (0, 0, 5), (256, 0, 3), (64, 8, 2), "auto"]:
         sim = lbm.Simulation(9, *box, tau=0.7, gravity=(0, -1e-4, 0), zero_net_force=True, storage="fp32",
                              max_particles=3, max_radius=5.0)
         sim.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
         sim.step(3)
         if shape == "auto":
-            w, g, ms = sim.autotune(reps=3)
-            _say("autotune picked", w, g, ms)
-            assert sim.sweep_config() == (w, g)
+            w, g, k, ms = sim.autotune(reps=3)
+            _say("autotune picked", w, g, k, ms)
+            assert sim.sweep_config() == (w, g, k)
         else:
             sim.set_sweep_config(*shape)
+            assert sim.sweep_config() == shape
+            for bad in (-1, 33):
+                with pytest.raises(lbm.LbmError):
+                    sim.set_sweep_config(0, 0, bad)
+            assert sim.sweep_config() == shape
         sim.step(27)
         st = _state(sim)
         if ref is None:
