@@ -26,20 +26,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0  # MI355X HBM3E
-COUNTERS = os.path.join(ROOT, "profiles", "k_sweep_d3q19_256cubed_500spheres_fp32_hbm_counters.json")
+COUNTERS = os.path.join(ROOT, "profiles", "k_sweep_d3q19_256cubed_500spheres_hbm_counters.json")
 
 
-def measured_traffic(kernel, workload, storage):
-    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
-    counter runs (copy-kernel calibrated), or None when no run covers this
-    kernel and workload or the kernel sources changed since it was taken."""
+def sweep_geometry(box, launch):
+    """Workgroup size and grid (threads) of the sweep launch (width, grid,
+    blocks_per_cu) on one box: the row kernel runs 256-wide workgroups over
+    ceil(nx/256) blocks per row; tiles of width w, one per workgroup unless a
+    smaller persistent grid is set."""
+    import math
+    nx, ny, nz = box
+    w, g = launch["width"], launch["grid"]
+    if w == 0:
+        return 256, math.ceil(nx / 256) * ny * nz * 256
+    nt = ny * nz * math.ceil(nx / w)
+    return w, (g if 0 < g < nt else nt) * w
+
+
+def measured_traffic(kernel, workload, box, launch):
+    """HBM bytes per launch of `kernel` at this launch geometry from the
+    committed FETCH_SIZE/WRITE_SIZE counter runs (copy-kernel calibrated), or
+    None when no run covers it or the kernel sources changed since."""
     import hashlib
     try:
         with open(COUNTERS) as fh:
             c = json.load(fh)
     except OSError:
         return None
-    if (c["kernel"], c["workload"], c["storage"]) != (kernel, workload, storage):
+    if c["workload"] != workload:
         return None
     h = hashlib.sha256()
     for f in c["sources"]:
@@ -47,7 +61,13 @@ def measured_traffic(kernel, workload, storage):
             h.update(fh.read())
     if h.hexdigest() != c["source_sha256"]:
         return None
-    return c["hbm_bytes_per_launch"]
+    wg, grid = sweep_geometry(box, launch)
+    col = {k: i for i, k in enumerate(c["columns"])}
+    for e in c["entries"]:
+        if (e[col["kernel"]], e[col["workgroup_size"]], e[col["grid_threads"]]) == (kernel, wg, grid):
+            rd, wr = e[col["hbm_read_bytes"]], e[col["hbm_write_bytes"]]
+            return {"read": rd, "write": wr, "total": rd + wr}
+    return None
 
 
 def copy_ceiling(torch, lbm, stream, nbytes=2 << 30, reps=10):
@@ -257,11 +277,12 @@ def main():
     sweep_avg_ms = sweep_ms / max(sweeps, 1)
     achieved = bps * N / (sweep_avg_ms * 1e-3) / 1e9
     ceiling = copy_ceiling(torch, lbm, stream)
-    kernel = "%s<%d,%s,%s>" % ("k_sweep" if sim.sweep_config()[0] == 0 else "k_sweep_tiles", q, kname,
+    launch = dict(zip(("width", "grid", "blocks_per_cu"), sim.sweep_config()))
+    kernel = "%s<%d,%s,%s>" % ("k_sweep" if launch["width"] == 0 else "k_sweep_tiles", q, kname,
                                 "true" if args.particles else "false")
     traffic = None
     if args.particles == len(cfg["particles"]["radius"]):
-        traffic = measured_traffic(kernel.replace(",", ", "), cfg["name"], args.storage)
+        traffic = measured_traffic(kernel.replace(",", ", "), cfg["name"], cfg["box"], launch)
     out = {
         "metric": "MLUPS + % HBM roofline, D3Q19 256³ 500 spheres; FP16-store/batched vs FP32",
         "value": round(mlups, 1),
@@ -280,7 +301,7 @@ def main():
                    "radius": float(np.max(cfg["particles"]["radius"])),
                    "density_ratio": 1.2 if q == 19 else 1.5, "gravity": float(-min(cfg["gravity"])),
                    "storage": args.storage, "parallelism": "single-gpu",
-                   "sweep_launch": dict(zip(("width", "grid", "blocks_per_cu"), sim.sweep_config()))},
+                   "sweep_launch": launch},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBPS, 4),
                      "traffic": None if traffic is None else traffic["total"],
@@ -303,10 +324,17 @@ def main():
                 v.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
             vms, (vsw, vn) = timed(v, args.steps, args.warmup, True)
             vb = lbm.lbm_bytes_per_site(v.params)
+            vl = dict(zip(("width", "grid", "blocks_per_cu"), v.sweep_config()))
+            vk = "%s<%d, %s, %s>" % ("k_sweep" if vl["width"] == 0 else "k_sweep_tiles", q,
+                                     {"fp16": "_Float16", "bf16": "bf16s"}[st], "true" if args.particles else "false")
+            vt = None
+            if args.particles == len(cfg["particles"]["radius"]):
+                vt = measured_traffic(vk, cfg["name"], cfg["box"], vl)
             vm = N / (vms / args.steps * 1e-3) / 1e6
             vs = vsw / max(vn, 1)
             out["variants"][st] = {"value": round(vm, 1), "ms_per_step": round(vms / args.steps, 4),
-                                   "sweep_launch": dict(zip(("width", "grid", "blocks_per_cu"), v.sweep_config())),
+                                   "sweep_launch": vl, "kernel": vk.replace(", ", ","),
+                                   "traffic": None if vt is None else vt["total"],
                                    "speedup_vs_fp32": round(vm / mlups, 3), "bytes_per_site": vb,
                                    "sweep_avg_ms": round(vs, 4), "sweep_GBps": round(vb * N / (vs * 1e-3) / 1e9, 1)}
             v.close()

@@ -58,6 +58,7 @@ constexpr double kMargin = 1.0;     // candidate search margin (lattice units)
 constexpr int kSweepBlock = 256;
 constexpr int kTileMax = 512;        // widest tile of the ensemble sweep
 constexpr int kBoundaryBlock = 256;  // reduce workgroup
+constexpr int kPrepareBlock = 256;   // workgroup of the per-particle prepare
 constexpr int kParticleBlock = 1024;
 constexpr int kStatusCollision = 1;
 constexpr int kStatusClosure = 2;     // more close pairs than kClosurePairs
@@ -990,7 +991,7 @@ __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own, co
 // densities of a window around the ball staged in LDS: row-coalesced loads
 // instead of scattered lookups.  Half-width hw = floor(r + 1/2) + 1.
 template <int Q, typename T>
-__global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ own, const int* __restrict__ ball,
+__global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __restrict__ own, const int* __restrict__ ball,
                                                         uint8_t* __restrict__ flag, typename Store<T>::C* __restrict__ vel,
                                                         const typename Store<T>::C* __restrict__ drho,
                                                         T* __restrict__ S, DevParticles P, DevEntries E, Boxes BX,
@@ -1009,12 +1010,12 @@ __global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ o
   // window loads issued in batches of kBatch per thread so that their
   // latencies overlap
   constexpr int kBatch = 8;
-  for (int base = 0; base < nW; base += 256 * kBatch) {
+  for (int base = 0; base < nW; base += kPrepareBlock * kBatch) {
     int vo[kBatch];
     C vd[kBatch];
 #pragma unroll
     for (int j = 0; j < kBatch; j++) {
-      const int idx = base + j * 256 + tid;
+      const int idx = base + j * kPrepareBlock + tid;
       if (idx < nW) {
         const int wx = idx % W, wy = (idx / W) % W, wz = idx / (W * W);
         const int x = wrap1(ox0 + wx - hw, G.nx), y = wrap1(oy0 + wy - hw, G.ny), z = wrap1(oz0 + wz - hz, G.nz);
@@ -1025,7 +1026,7 @@ __global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ o
     }
 #pragma unroll
     for (int j = 0; j < kBatch; j++) {
-      const int idx = base + j * 256 + tid;
+      const int idx = base + j * kPrepareBlock + tid;
       if (idx < nW) {
         s_own[idx] = vo[j];
         s_drho[idx] = vd[j];
@@ -1040,11 +1041,11 @@ __global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ o
   const int e0 = P.ent0[p], ne = P.nbs[p] + P.nis[p] + P.nin[p];
   const bool jump = P.jump[p] != 0;
   constexpr int kEnt = 4;
-  for (int tb = 0; tb < ne; tb += 256 * kEnt) {
+  for (int tb = 0; tb < ne; tb += kPrepareBlock * kEnt) {
     int rep[kEnt], pkv[kEnt];
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
-      const int t = tb + j * 256 + tid;
+      const int t = tb + j * kPrepareBlock + tid;
       rep[j] = -1;
       if (t < ne) {
         pkv[j] = E.off[e0 + t];
@@ -1055,7 +1056,7 @@ __global__ __launch_bounds__(256) void k_prepare_local(const int* __restrict__ o
     }
 #pragma unroll 1
     for (int j = 0; j < kEnt; j++) {
-      const int t = tb + j * 256 + tid;
+      const int t = tb + j * kPrepareBlock + tid;
       if (t >= ne) continue;
       const int e = e0 + t;
       const int pk = pkv[j];
@@ -1380,7 +1381,7 @@ int launch_prepare(lbm_ctx* c, int pending) {
   if (c->nent == 0) return LBM_OK;
   using C = typename Store<T>::C;
   if (c->lds_window > 0) {
-    k_prepare_local<Q, T><<<c->np, 256, c->lds_window, c->stream>>>(
+    k_prepare_local<Q, T><<<c->np, kPrepareBlock, c->lds_window, c->stream>>>(
         c->own, c->ball, c->flag, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
         c->prm.rho0, pending, c->dim);
   } else {
