@@ -308,6 +308,21 @@ __device__ __forceinline__ bool wall_velocity(const SweepArgs<Q, C>& a, int x, i
   return true;
 }
 
+// Element `site` of plane i of a [q][N] array: uniform plane base plus a
+// 32-bit byte offset (valid while N sizeof(T) <= 2^32).
+template <typename T>
+__device__ __forceinline__ T* plane_at(T* p, int i, int64_t N, int site) {
+  return (T*)((char*)p + (size_t)i * (size_t)N * sizeof(T) + (uint32_t)site * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ const T* plane_at(const T* p, int i, int64_t N, int site) {
+  return (const T*)((const char*)p + (size_t)i * (size_t)N * sizeof(T) + (uint32_t)site * (uint32_t)sizeof(T));
+}
+
+// 1/rho: the hardware reciprocal in FP32 (1 ulp), a division in FP64.
+__device__ __forceinline__ float recip(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double recip(double v) { return 1.0 / v; }
+
 // The work of one site (x, y, z) of a box of nx x ny x nz sites whose first
 // site is `off`; fbt holds 3 w_i c_i . f_b of that box.
 template <int Q, typename T, bool PART>
@@ -330,6 +345,9 @@ __device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restric
   // FP32/FP64 collide on the deviations g_i.
   constexpr bool kRaw = std::is_same<T, _Float16>::value || std::is_same<T, bf16s>::value;
   const C inv_sig = (C)(1.0 / pop_unit<T>(1.0));
+  // Addresses: the plane of population i starts at a wave-uniform base (scalar
+  // registers) and the site is a 32-bit byte offset into it (a context keeps
+  // N sizeof(T) <= 2^32), so no 64-bit vector arithmetic per access.
   C g[Q];
 #pragma unroll
   for (int i = 0; i < Q; i++) {
@@ -337,7 +355,7 @@ __device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restric
     const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
     const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
     const int sz = L::cz(i) > 0 ? zm : (L::cz(i) < 0 ? zp : z);
-    const T* src = A + (size_t)i * a.N + (off + sx + nx * (sy + ny * sz));
+    const T* src = plane_at(A, i, a.N, off + sx + nx * (sy + ny * sz));
     g[i] = kRaw ? Store<T>::ld(src) : pop_ld<Q, T>(src, i);
   }
   C drho = 0, jx = 0, jy = 0, jz = 0;
@@ -353,7 +371,7 @@ __device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restric
     if (L::cz(i) < 0) jz -= v;
   }
   const C rho = a.rho0 + drho;
-  const C inv = C(1) / rho;
+  const C inv = recip(rho);
   const C ux = jx * inv, uy = jy * inv, uz = jz * inv;
   const C usq = C(1.5) * (ux * ux + uy * uy + uz * uz);
   if constexpr (kRaw) {
@@ -422,7 +440,7 @@ __device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restric
   }
 #pragma unroll
   for (int i = 0; i < Q; i++) {
-    T* dst = B + (size_t)i * a.N + s;
+    T* dst = plane_at(B, i, a.N, s);
     if constexpr (kRaw)
       Store<T>::st(dst, g[i]);
     else
@@ -430,15 +448,13 @@ __device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restric
   }
 }
 
-// One box: workgroup b covers kSweepBlock sites of row b / nxb.
+// One box: workgroup (bx, y, z) covers kSweepBlock sites of row (y, z).
 template <int Q, typename T, bool PART>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, T* __restrict__ B,
                                                         SweepArgs<Q, typename Store<T>::C> a, SiteArgs<T> sa) {
-  const int blk = blockIdx.x;
-  const int row = blk / a.nxb;
-  const int x = (blk - row * a.nxb) * kSweepBlock + threadIdx.x;
+  const int x = (int)blockIdx.x * kSweepBlock + (int)threadIdx.x;
   if (x >= a.nx) return;
-  sweep_site<Q, T, PART>(A, B, a, sa, x, row % a.ny, row / a.ny, a.nx, a.ny, a.nz, 0, a.fbt);
+  sweep_site<Q, T, PART>(A, B, a, sa, x, (int)blockIdx.y, (int)blockIdx.z, a.nx, a.ny, a.nz, 0, a.fbt);
 }
 
 // Any number of boxes: a tile is a run of blockDim.x sites of one row of
@@ -1190,6 +1206,9 @@ BoxSet make_boxset(int nbox, const int32_t* dims) {
 
 size_t store_size(int storage) { return storage == LBM_FP64 ? 8 : storage == LBM_FP32 ? 4 : 2; }
 
+// The sweep addresses a population plane with 32-bit byte offsets.
+bool plane_fits(int storage, int64_t sites) { return (uint64_t)sites * store_size(storage) <= ((uint64_t)1 << 32); }
+
 int64_t entries_per_particle(int dim, double rmax) {
   const int64_t e = 2 * (int64_t)std::ceil(rmax) + 1;
   return dim == 2 ? e * e : e * e * e;
@@ -1257,7 +1276,7 @@ int check_boxes(const lbm_params* p, int nbox, const int32_t* dims) {
     if (rc != LBM_OK) return rc;
     NT += (int64_t)q.nx * q.ny * q.nz;
   }
-  if (NT >= ((int64_t)1 << 31)) return LBM_EINVAL;
+  if (NT >= ((int64_t)1 << 31) || !plane_fits(p->storage, NT)) return LBM_EINVAL;
   return LBM_OK;
 }
 
@@ -1267,6 +1286,8 @@ int check_params(const lbm_params* p) {
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return LBM_EINVAL;
   if (p->lattice == LBM_D2Q9 && p->nz != 1) return LBM_EINVAL;
   if ((int64_t)p->nx * p->ny * p->nz >= ((int64_t)1 << 31)) return LBM_EINVAL;
+  if (p->storage >= LBM_FP64 && p->storage <= LBM_BF16 && !plane_fits(p->storage, (int64_t)p->nx * p->ny * p->nz))
+    return LBM_EINVAL;
   if (!std::isfinite(p->tau) || !std::isfinite(p->rho0) || !std::isfinite(p->max_radius)) return LBM_ENONFINITE;
   for (int a = 0; a < 3; a++)
     if (!std::isfinite(p->gravity[a]) || !std::isfinite(p->body_force[a])) return LBM_ENONFINITE;
@@ -1311,6 +1332,7 @@ struct lbm_ctx {
   int sweep_w, sweep_grid;  // sweep launch shape: w = 0 the one-box kernel, else tile width; grid 0 = one per tile
   int sweep_occ;            // cap on resident sweep workgroups per CU (0: none)
   int lds_cu, lds_block;    // LDS bytes per CU and the most one workgroup may reserve
+  bool row_ok;              // one box whose rows fit the row kernel's (x-blocks, y, z) grid
   std::vector<int> h_box;   // box of every particle
   std::vector<double> fbb;  // [nbox][3] fluid body force density
   // step graph
@@ -1456,11 +1478,11 @@ int launch_sweep(lbm_ctx* c, int w, int grid, int occ) {
   T* B = (T*)c->f[1 - c->cur];
   const SiteArgs<T> sa = site_args<Q, T>(c);
   if (w == 0) {
-    const unsigned nblk = (unsigned)((int64_t)a.nxb * c->G.ny * c->G.nz);
+    const dim3 grid3((unsigned)a.nxb, (unsigned)c->G.ny, (unsigned)c->G.nz);
     if (c->np > 0)
-      k_sweep<Q, T, true><<<nblk, kSweepBlock, lds, c->stream>>>(A, B, a, sa);
+      k_sweep<Q, T, true><<<grid3, kSweepBlock, lds, c->stream>>>(A, B, a, sa);
     else
-      k_sweep<Q, T, false><<<nblk, kSweepBlock, lds, c->stream>>>(A, B, a, sa);
+      k_sweep<Q, T, false><<<grid3, kSweepBlock, lds, c->stream>>>(A, B, a, sa);
   } else {
     const int64_t nt = c->ntiles;
     const unsigned g = (unsigned)(grid > 0 && grid < nt ? grid : nt);
@@ -1710,19 +1732,22 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
   c->d_tiles = (int4*)(c->ws + L.tiles);
   c->ntiles = 0;
   c->tiles_w = 0;
-  // one box: the row kernel; an ensemble: tiles of 128 sites, one workgroup each
-  c->sweep_w = nbox == 1 ? 0 : 128;
-  c->sweep_grid = 0;
-  c->sweep_occ = 0;
   {
-    int dev = 0;
+    int dev = 0, gy = 0, gz = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&c->lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
-        hipDeviceGetAttribute(&c->lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+        hipDeviceGetAttribute(&c->lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&gy, hipDeviceAttributeMaxGridDimY, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&gz, hipDeviceAttributeMaxGridDimZ, dev) != hipSuccess) {
       delete c;
       return LBM_EHIP;
     }
+    c->row_ok = nbox == 1 && dims[1] <= gy && dims[2] <= gz;
   }
+  // one box: the row kernel; an ensemble: tiles of 128 sites, one workgroup each
+  c->sweep_w = c->row_ok ? 0 : 128;
+  c->sweep_grid = 0;
+  c->sweep_occ = 0;
   c->cap = nullptr;
   c->graph = nullptr;
   c->gexec = nullptr;
@@ -1765,7 +1790,7 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
   k_fill<uint8_t><<<blocks_for(c->NT), 256, 0, c->stream>>>(c->flag, c->NT, (uint8_t)0);
   k_fill<int><<<1, 256, 0, c->stream>>>(c->status, 16, 0);
   if (hipGetLastError() != hipSuccess || upload_boxes(c) != LBM_OK ||
-      (nbox > 1 && build_tiles(c, c->sweep_w) != LBM_OK) || hipStreamSynchronize(c->stream) != hipSuccess) {
+      (c->sweep_w > 0 && build_tiles(c, c->sweep_w) != LBM_OK) || hipStreamSynchronize(c->stream) != hipSuccess) {
     delete c;
     return LBM_EHIP;
   }
@@ -2035,7 +2060,7 @@ int lbm_set_graph(lbm_ctx* c, int32_t steps_per_graph) {
 int lbm_set_sweep_config(lbm_ctx* c, int32_t width, int32_t grid, int32_t blocks_per_cu) {
   if (!c || grid < 0 || !occ_ok(c, blocks_per_cu)) return LBM_EINVAL;
   if (width != 0 && width != 64 && width != 128 && width != 256 && width != 512) return LBM_EINVAL;
-  if (width == 0 && c->nbox != 1) return LBM_EINVAL;  // the row kernel covers one box
+  if (width == 0 && !c->row_ok) return LBM_EINVAL;  // the row kernel covers one box
   if (width > 0) {
     const int rc = build_tiles(c, width);
     if (rc != LBM_OK) return rc;
@@ -2070,7 +2095,7 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* width, int32_t* grid, int32_
   std::vector<Cand> cands;
   for (int occ : {0, 6, 5, 4, 3, 2}) {
     if (!occ_ok(c, occ)) continue;
-    if (c->nbox == 1) cands.push_back({0, 0, occ});
+    if (c->row_ok) cands.push_back({0, 0, occ});
     for (int w : {64, 128, 256, 512})
       for (int k : {0, 4, 8, 16, 32}) cands.push_back({w, k * ncu, occ});
   }
