@@ -59,7 +59,8 @@ constexpr int kSweepBlock = 256;
 constexpr int kTileMax = 512;        // widest tile of the ensemble sweep
 constexpr int kBoundaryBlock = 256;  // reduce workgroup
 constexpr int kPrepareBlock = 256;   // workgroup of the per-particle prepare
-constexpr int kParticleBlock = 1024;
+constexpr int kParticleBlock = 1024;   // particle update of a one-box context
+constexpr int kBoxParticleBlock = 256; // particle update, per box of an ensemble
 constexpr int kStatusCollision = 1;
 constexpr int kStatusClosure = 2;     // more close pairs than kClosurePairs
 constexpr int kClosurePairs = 1024;   // close pairs one step of the closure handles
@@ -515,16 +516,47 @@ __device__ __forceinline__ int block_excl_scan(int c, int* s_w, int& total) {
 }
 
 // ---------------------------------------------------------------------------
-// K3: particle update, one workgroup (eq. 10-11, 16-19, 13).
+// K3: particle update (eq. 10-11, 16-19, 13), one workgroup per box: boxes
+// are independent, and a box's particles have consecutive ids p0 .. p1-1.
+// Positions, velocities, masses and radii of a box of up to kStageParticles
+// particles are staged in LDS, and the box's candidate pairs are compacted in
+// lexicographic order (each particle's list is in increasing j); one thread
+// then walks the pairs -- each collision acts on the velocities earlier ones
+// left -- against LDS instead of a chain of dependent memory loads.
 // ---------------------------------------------------------------------------
+constexpr int kStageParticles = 640;  // particles of one box staged in LDS
+constexpr int kStagePairs = 2048;     // candidate pairs of one box staged in LDS (the rest in memory)
+
+// A box's particle state, staged ([component][particle - p0]) or in the
+// particle arrays ([particle][component]).
+struct PartView {
+  double* x;
+  double* u;
+  const double* m;
+  const double* r;
+  int sa, sp, p0;
+  __device__ __forceinline__ double& X(int p, int a) const { return x[a * sa + (p - p0) * sp]; }
+  __device__ __forceinline__ double& U(int p, int a) const { return u[a * sa + (p - p0) * sp]; }
+  __device__ __forceinline__ double M(int p) const { return m[p - p0]; }
+  __device__ __forceinline__ double R(int p) const { return r[p - p0]; }
+};
+
 template <int NT>
-__global__ __launch_bounds__(NT) void k_particles(DevParticles P, int np, int dim, Boxes BX, int* status) {
+__global__ __launch_bounds__(NT) void k_particles(DevParticles P, int dim, Boxes BX, int* status) {
+  __shared__ double s_x[3 * kStageParticles], s_u[3 * kStageParticles], s_m[kStageParticles], s_r[kStageParticles];
+  __shared__ int2 s_pairs[kStagePairs];
   __shared__ int s_scan[NT / 64];
   __shared__ double s_vmax[NT / 64];
+  const int b = blockIdx.x;
+  const Geo G = BX.nbox == 1 ? BX.g0 : BX.tab[b];
+  const int p0 = b == 0 ? 0 : BX.tab[b - 1].p1, p1 = G.p1;
+  if (p1 <= p0) return;  // an empty box (uniform over the workgroup)
+  const bool staged = p1 - p0 <= kStageParticles;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
+  const int L[3] = {G.nx, G.ny, G.nz};
   double vmax = 0;
-  for (int p = tid; p < np; p += NT) {
+  for (int p = p0 + tid; p < p1; p += NT) {
     const double m = P.m[p], I = P.I[p];
     double v2 = 0;
     for (int a = 0; a < 3; a++) {
@@ -536,108 +568,114 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int np, int di
       P.u[3 * p + a] = u;
       if (!isinf(I)) P.om[3 * p + a] = P.om[3 * p + a] - dl / I;
       v2 += u * u;
+      if (staged) {
+        s_x[a * kStageParticles + p - p0] = P.x[3 * p + a];
+        s_u[a * kStageParticles + p - p0] = u;
+      }
+    }
+    if (staged) {
+      s_m[p - p0] = m;
+      s_r[p - p0] = P.rad[p];
     }
     vmax = fmax(vmax, sqrt(v2));
   }
   for (int o = 32; o > 0; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o));
   if (lane == 0) s_vmax[wv] = vmax;
 
-  // lexicographic list of candidate pairs: exclusive scan of the counts
+  // the box's candidate pairs in lexicographic order: the first kStagePairs
+  // in LDS, any others in the box's part of the pair buffer (a particle has
+  // at most kCandMax candidates, so the part holds them all)
+  int2* gpairs = (int2*)P.pairs + (size_t)p0 * kCandMax;
   int total = 0;
-  for (int b = 0; b < np; b += NT) {
-    const int p = b + tid;
-    const int c = p < np ? P.cand_n[p] : 0;
-    if (!__syncthreads_or(c)) continue;  // no close pair in this chunk
+  for (int c0 = p0; c0 < p1; c0 += NT) {
+    const int p = c0 + tid;
+    const int c = p < p1 ? P.cand_n[p] : 0;
     int chunk;
     const int excl = total + block_excl_scan<NT>(c, s_scan, chunk);
     for (int t = 0; t < c; t++) {
-      P.pairs[2 * (excl + t)] = p;
-      P.pairs[2 * (excl + t) + 1] = P.cand[p * kCandMax + t];
+      const int k = excl + t;
+      const int2 pr = make_int2(p, P.cand[p * kCandMax + t]);
+      if (k < kStagePairs)
+        s_pairs[k] = pr;
+      else
+        gpairs[k] = pr;
     }
     total += chunk;
   }
-
   __syncthreads();
-  // Pairs in lexicographic order, one box after the other (a box holds
-  // consecutive ids): every box's pairs are one segment, walked in order by
-  // one thread, the boxes in parallel.
+
   double vseen = 0;
-  for (int t0 = tid; t0 < total; t0 += NT) {
-    const int b0 = BX.nbox == 1 ? 0 : P.box[P.pairs[2 * t0]];
-    if (t0 > 0 && (BX.nbox == 1 || P.box[P.pairs[2 * (t0 - 1)]] == b0)) continue;  // not a segment start
-    for (int t = t0; t < total; t++) {
-      const int i = P.pairs[2 * t], j = P.pairs[2 * t + 1];
-      if (t > t0 && BX.nbox > 1 && P.box[i] != b0) break;
-      const Geo G = geo_of(BX, P, i);  // pairs never cross boxes
-      const int L[3] = {G.nx, G.ny, G.nz};
-      const bool infA = isinf(P.m[i]), infB = isinf(P.m[j]);
+  if (tid == 0) {
+    const PartView V = staged ? PartView{s_x, s_u, s_m, s_r, kStageParticles, 1, p0}
+                              : PartView{P.x, P.u, P.m, P.rad, 1, 3, 0};
+    for (int k = 0; k < total; k++) {
+      const int2 pr = k < kStagePairs ? s_pairs[k] : gpairs[k];
+      const int i = pr.x, j = pr.y;
+      const double mi = V.M(i), mj = V.M(j), ri = V.R(i), rj = V.R(j);
+      const bool infA = isinf(mi), infB = isinf(mj);
       if (infA && infB) continue;
       double d[3], dd = 0;
       for (int a = 0; a < 3; a++) {
-        d[a] = (P.x[3 * j + a] + P.u[3 * j + a]) - (P.x[3 * i + a] + P.u[3 * i + a]);
+        d[a] = (V.X(j, a) + V.U(j, a)) - (V.X(i, a) + V.U(i, a));
         if (a < dim) d[a] = d[a] - L[a] * floor(d[a] / L[a] + 0.5);
         dd += d[a] * d[a];
       }
       const double dist = sqrt(dd);
-      if (dist > P.rad[i] + P.rad[j] || dist == 0.0) continue;
+      if (dist > ri + rj || dist == 0.0) continue;
       double n[3], vn = 0;
       for (int a = 0; a < 3; a++) {
         n[a] = d[a] / dist;
-        vn += (P.u[3 * j + a] - P.u[3 * i + a]) * n[a];
+        vn += (V.U(j, a) - V.U(i, a)) * n[a];
       }
       if (!(vn < 0.0)) continue;
-      double V[3];
-      const double mi = P.m[i], mj = P.m[j];
+      double W[3];
       for (int a = 0; a < 3; a++) {
         if (infA)
-          V[a] = P.u[3 * i + a];
+          W[a] = V.U(i, a);
         else if (infB)
-          V[a] = P.u[3 * j + a];
+          W[a] = V.U(j, a);
         else
-          V[a] = (mi * P.u[3 * i + a] + mj * P.u[3 * j + a]) / (mi + mj);
+          W[a] = (mi * V.U(i, a) + mj * V.U(j, a)) / (mi + mj);
       }
       const int who[2] = {i, j};
       for (int t2 = 0; t2 < 2; t2++) {
         const int q = who[t2];
         double wvv[3], wn = 0, v2 = 0;
         for (int a = 0; a < 3; a++) {
-          wvv[a] = P.u[3 * q + a] - V[a];
+          wvv[a] = V.U(q, a) - W[a];
           wn += wvv[a] * n[a];
         }
         for (int a = 0; a < 3; a++) {
-          const double u = V[a] + (wvv[a] - 2.0 * wn * n[a]);
-          P.u[3 * q + a] = u;
+          const double u = W[a] + (wvv[a] - 2.0 * wn * n[a]);
+          V.U(q, a) = u;
           v2 += u * u;
         }
         vseen = fmax(vseen, sqrt(v2));
       }
     }
   }
-  for (int o = 32; o > 0; o >>= 1) vseen = fmax(vseen, __shfl_xor(vseen, o));
-  __syncthreads();
-  if (lane == 0) s_vmax[wv] = fmax(s_vmax[wv], vseen);
   __syncthreads();
   if (tid == 0) {
-    double vm = 0;
+    double vm = vseen;
     for (int w = 0; w < NT / 64; w++) vm = fmax(vm, s_vmax[w]);
     if (2.0 * vm >= kMargin) atomicOr(status, kStatusCollision);
   }
-  __syncthreads();
-  for (int p = tid; p < np; p += NT) {
-    const Geo G = geo_of(BX, P, p);
-    const int L[3] = {G.nx, G.ny, G.nz};
+  for (int p = p0 + tid; p < p1; p += NT) {
+    double u[3];
+    for (int a = 0; a < 3; a++) u[a] = staged ? s_u[a * kStageParticles + p - p0] : P.u[3 * p + a];
     if (G.walls && !isinf(P.m[p])) {
       // contact with a wall after the pairs: the normal velocity reverses
       // when the predicted surface reaches the BS layer while approaching
       for (int a = 0; a < dim; a++) {
         if (!(G.walls & (1 << a))) continue;
-        const double u = P.u[3 * p + a], xp = P.x[3 * p + a] + u, r = P.rad[p];
-        if ((xp - r <= 1.0 && u < 0.0) || (xp + r >= (double)(L[a] - 2) && u > 0.0)) P.u[3 * p + a] = -u;
+        const double xp = P.x[3 * p + a] + u[a], r = P.rad[p];
+        if ((xp - r <= 1.0 && u[a] < 0.0) || (xp + r >= (double)(L[a] - 2) && u[a] > 0.0)) u[a] = -u[a];
       }
     }
     int moved = 0;
+    for (int a = 0; a < 3; a++) P.u[3 * p + a] = u[a];
     for (int a = 0; a < dim; a++) {
-      const double x = P.x[3 * p + a] + P.u[3 * p + a];
+      const double x = P.x[3 * p + a] + u[a];
       P.x[3 * p + a] = x;
       const int k = (int)floor(x - P.x0[3 * p + a] + 0.5);
       moved += k != P.k[3 * p + a];
@@ -1521,7 +1559,10 @@ int launch_step(lbm_ctx* c) {
     if (c->closure)
       k_closure<<<1, 256, 0, c->stream>>>(c->P, c->np, bx, c->d_clo, c->clo_h,
                                           c->prm.rho0 * (c->prm.tau - 0.5) / 3.0, c->prm.tau, c->status);
-    k_particles<kParticleBlock><<<1, kParticleBlock, 0, c->stream>>>(c->P, c->np, c->dim, bx, c->status);
+    if (c->nbox == 1)
+      k_particles<kParticleBlock><<<1, kParticleBlock, 0, c->stream>>>(c->P, c->dim, bx, c->status);
+    else
+      k_particles<kBoxParticleBlock><<<c->nbox, kBoxParticleBlock, 0, c->stream>>>(c->P, c->dim, bx, c->status);
     k_stamp<<<blocks_for(c->nent), 256, 0, c->stream>>>(c->own, c->ball, c->P, c->E, bx, 0, (int)c->nent);
     HIP_TRY(hipGetLastError());
   }

@@ -285,6 +285,38 @@ def test_hard_core_collisions():
     assert np.abs(u_end - u).max() > 0.01  # collisions happened
 
 
+def test_hard_core_collisions_beyond_lds_staging():
+    """A box with more particles and candidate pairs than the particle kernel
+    stages in LDS (1225 disks on a square lattice 0.05 apart: about 2450
+    close pairs), random velocities: the chained collisions of the first steps
+    must still follow the oracle's lexicographic sequence exactly."""
+    rng = np.random.default_rng(43)
+    k, h, r = 35, 5.05, 2.5
+    box = (177, 177, 1)
+    g = (np.arange(k) + 0.5) * h
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    n = k * k
+    x = np.zeros((n, 3))
+    x[:, 0], x[:, 1] = X.ravel(), Y.ravel()
+    u = np.zeros((n, 3))
+    u[:, :2] = rng.uniform(-0.05, 0.05, (n, 2))
+    p = {"x": x, "u": u, "omega": np.zeros((n, 3)), "radius": np.full(n, r), "mass": np.full(n, 1e30),
+         "inertia": np.full(n, 1e33)}
+    sim, ora = make_pair(9, box, 0.8, "fp64", particles=p)
+    _say("hard-core collisions,", n, "disks in one box")
+    for t in range(4):
+        sim.step(1)
+        ora.step(1)
+        _, _, xg, ug, _ = sim.forces()
+        _, _, xo, uo, _ = ora.forces()
+        assert np.abs(ug - uo).max() <= 1e-14, t
+        assert np.abs(xg - xo).max() <= 1e-12, t
+        assert np.array_equal(sim.shifts(), ora.shifts()), t
+    _, _, _, u_end, _ = ora.forces()
+    assert (np.abs(u_end - u).max(axis=1) > 1e-3).sum() > 100  # many collisions happened
+    sim.close()
+
+
 def test_particles_added_in_two_batches():
     box = (64, 48, 1)
     p = wl.suspension(9, box, 5, 5.0, 1.5, seed=51)
