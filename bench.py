@@ -32,14 +32,14 @@ COUNTERS = os.path.join(ROOT, "profiles", "k_sweep_d3q19_256cubed_500spheres_hbm
 def sweep_geometry(box, launch):
     """Workgroup size and grid (threads) of the sweep launch (width, grid,
     blocks_per_cu) on one box: the row kernel runs 256-wide workgroups over
-    ceil(nx/256) blocks per row; tiles of width w, one per workgroup unless a
-    smaller persistent grid is set."""
+    ceil(nx/256) blocks per row; tiles are w consecutive sites of the box, one
+    per workgroup unless a smaller persistent grid is set."""
     import math
     nx, ny, nz = box
     w, g = launch["width"], launch["grid"]
     if w == 0:
         return 256, math.ceil(nx / 256) * ny * nz * 256
-    nt = ny * nz * math.ceil(nx / w)
+    nt = math.ceil(nx * ny * nz / w)
     return w, (g if 0 < g < nt else nt) * w
 
 

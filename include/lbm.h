@@ -202,8 +202,9 @@ int lbm_box_info(lbm_ctx* ctx, int32_t box, int32_t* dims, int64_t* first_site, 
 
 /* ---- launch shape, autotuning and step graphs ---------------------------
  * The sweep runs either as the one-box row kernel (width 0; one box only) or
- * as a persistent kernel over tiles of `width` sites of one row (64, 128, 256
- * or 512) with `grid` workgroups (0: one per tile).  blocks_per_cu > 0 caps
+ * as a persistent kernel over tiles of `width` consecutive sites of one box in
+ * raster order (64, 128, 256 or 512; a tile runs on across rows) with `grid`
+ * workgroups (0: one per tile).  blocks_per_cu > 0 caps
  * the sweep workgroups resident on one compute unit at that number, through
  * LDS each workgroup reserves (floor(LDS per CU / blocks_per_cu), whole KiB;
  * LBM_EINVAL if that exceeds what one workgroup may reserve or is below

@@ -458,11 +458,23 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, 
   sweep_site<Q, T, PART>(A, B, a, sa, x, (int)blockIdx.y, (int)blockIdx.z, a.nx, a.ny, a.nz, 0, a.fbt);
 }
 
-// Any number of boxes: a tile is a run of blockDim.x sites of one row of
-// one box, {box, y, z, x0} followed by the box's {nx, ny, nz, first site}
-// (one record, so the pull addresses depend on one load); a persistent grid
-// walks the tile list (the workgroup width and grid size are the tunable
-// launch shape).
+// q = n / d for 0 <= n < 2^31, 1 <= d, from inv = 1/d rounded to FP64: the
+// product is within 2^-21 of n/d, so truncation is off by at most one and the
+// remainder corrects it.
+__device__ __forceinline__ int div_exact(int n, int d, double inv) {
+  const int q = (int)((double)n * inv);
+  const int64_t r = (int64_t)n - (int64_t)q * d;
+  return q + (r >= d) - (r < 0);
+}
+
+// Any number of boxes: a tile is blockDim.x consecutive sites of one box in
+// raster order (x fastest, running on into the next row), so every thread of
+// a tile but the box's last has a site and the tile's accesses are contiguous
+// whatever the box width.  Three records per tile: {box, first box-local
+// site, -, -}, the box's {nx, ny, nz, first site}, and 1/nx, 1/ny as FP64
+// bit pairs {lo, hi, lo, hi} for the split of a box-local index into (x, y,
+// z).  A persistent grid walks the tile list (the workgroup width, grid size
+// and occupancy cap are the tunable launch shape).
 template <int Q, typename T, bool PART>
 __global__ __launch_bounds__(kTileMax) void k_sweep_tiles(const T* __restrict__ A, T* __restrict__ B,
                                                            SweepArgs<Q, typename Store<T>::C> a, SiteArgs<T> sa,
@@ -470,13 +482,16 @@ __global__ __launch_bounds__(kTileMax) void k_sweep_tiles(const T* __restrict__ 
                                                            const typename Store<T>::C* __restrict__ fbt_tab) {
   using C = typename Store<T>::C;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int4 tl = tiles[2 * t], tg = tiles[2 * t + 1];
-    const int x = tl.w + (int)threadIdx.x;
-    if (x >= tg.x) continue;
+    const int4 tl = tiles[3 * t], tg = tiles[3 * t + 1], ti = tiles[3 * t + 2];
+    const int64_t lin64 = (int64_t)tl.y + threadIdx.x;
+    if (lin64 >= (int64_t)tg.x * tg.y * tg.z) continue;
+    const int lin = (int)lin64;
+    const int yz = div_exact(lin, tg.x, __hiloint2double(ti.y, ti.x));
+    const int z = div_exact(yz, tg.y, __hiloint2double(ti.w, ti.z));
     C fb[Q];
 #pragma unroll
     for (int i = 0; i < Q; i++) fb[i] = fbt_tab[tl.x * Q + i];
-    sweep_site<Q, T, PART>(A, B, a, sa, x, tl.y, tl.z, tg.x, tg.y, tg.z, tg.w, fb);
+    sweep_site<Q, T, PART>(A, B, a, sa, lin - yz * tg.x, yz - z * tg.y, z, tg.x, tg.y, tg.z, tg.w, fb);
   }
 }
 
@@ -1237,7 +1252,7 @@ BoxSet make_boxset(int nbox, const int32_t* dims) {
   for (int i = 0; i < nbox; i++) {
     const int64_t nx = dims[3 * i], ny = dims[3 * i + 1], nz = dims[3 * i + 2];
     b.NT += nx * ny * nz;
-    b.max_tiles += ny * nz * ((nx + kTileMin - 1) / kTileMin);
+    b.max_tiles += (nx * ny * nz + kTileMin - 1) / kTileMin;
   }
   return b;
 }
@@ -1292,7 +1307,7 @@ Layout make_layout(const lbm_params& p, const BoxSet& bs) {
   L.boxes = take(sizeof(Geo) * nbox);
   L.fbt = take(sizeof(double) * p.lattice * nbox);
   L.max_tiles = bs.max_tiles;
-  L.tiles = take(2 * sizeof(int4) * bs.max_tiles);
+  L.tiles = take(3 * sizeof(int4) * bs.max_tiles);
   L.fc = take(sizeof(double) * 3 * np);
   L.clo = take(sizeof(float) * mlp::kParams);
   L.total = cur;
@@ -1454,22 +1469,32 @@ int launch_prepare(lbm_ctx* c, int pending) {
 }
 
 // Tile list {box, y, z, x0} of width w, box by box, rows in z, y order.
+// FP64 bits of v as {lo, hi} ints.
+static void dbl_bits(double v, int& lo, int& hi) {
+  uint64_t u;
+  std::memcpy(&u, &v, sizeof u);
+  lo = (int)(uint32_t)(u & 0xffffffffu);
+  hi = (int)(uint32_t)(u >> 32);
+}
+
 int build_tiles(lbm_ctx* c, int w) {
   if (c->tiles_w == w) return LBM_OK;
   std::vector<int4> t;
   for (int b = 0; b < c->nbox; b++) {
     const Geo& g = c->boxes[b];
-    for (int z = 0; z < g.nz; z++)
-      for (int y = 0; y < g.ny; y++)
-        for (int x0 = 0; x0 < g.nx; x0 += w) {
-          t.push_back(make_int4(b, y, z, x0));
-          t.push_back(make_int4(g.nx, g.ny, g.nz, (int)g.off));
-        }
+    int4 inv;
+    dbl_bits(1.0 / g.nx, inv.x, inv.y);
+    dbl_bits(1.0 / g.ny, inv.z, inv.w);
+    for (int64_t s0 = 0; s0 < g.N; s0 += w) {
+      t.push_back(make_int4(b, (int)s0, 0, 0));
+      t.push_back(make_int4(g.nx, g.ny, g.nz, (int)g.off));
+      t.push_back(inv);
+    }
   }
-  if ((int64_t)t.size() > 2 * c->L.max_tiles) return LBM_EINVAL;
+  if ((int64_t)t.size() > 3 * c->L.max_tiles) return LBM_EINVAL;
   HIP_TRY(hipMemcpyAsync(c->d_tiles, t.data(), sizeof(int4) * t.size(), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  c->ntiles = (int64_t)t.size() / 2;
+  c->ntiles = (int64_t)t.size() / 3;
   c->tiles_w = w;
   return LBM_OK;
 }
