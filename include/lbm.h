@@ -101,6 +101,13 @@ typedef struct lbm_params {
                             wall layers at both ends, which needs n_a >= 5; 0 = periodic */
   double wall_velocity[3][2][3]; /* [axis][0 low wall, 1 high wall][component]; the
                             component along the axis must be 0; ignored for open axes */
+  int32_t aa;            /* 0: two population arrays, the sweep pulls from one into the other;
+                            1: one array updated in place with the AA pattern (even steps read
+                            and write a site's own slots, odd steps read and write its
+                            neighbours'), half the population memory, the same results bit for
+                            bit.  An AA context cannot be autotuned (a sweep in place cannot be
+                            repeated on the live state) and its read-outs of distributions and
+                            fields gather on the host. */
 } lbm_params;
 
 /* Bytes of device workspace lbm_create needs for these parameters. */

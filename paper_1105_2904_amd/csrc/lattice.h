@@ -43,3 +43,13 @@ struct Lattice<19> {
     return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
   }
 };
+
+// Index of the direction opposite to i (c_opp = -c_i); opposite directions
+// carry the same weight.
+template <int Q>
+__host__ __device__ constexpr int opposite(int i) {
+  using L = Lattice<Q>;
+  for (int j = 0; j < Q; j++)
+    if (L::cx(j) == -L::cx(i) && L::cy(j) == -L::cy(i) && L::cz(j) == -L::cz(i)) return j;
+  return -1;
+}

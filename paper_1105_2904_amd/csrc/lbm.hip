@@ -200,7 +200,7 @@ __device__ __forceinline__ int off_y(int v) { return (int)(int8_t)((v >> 8) & 0x
 __device__ __forceinline__ int off_z(int v) { return (int)(int8_t)((v >> 16) & 0xff); }
 __host__ __device__ __forceinline__ int entry_kind(int v) { return (v >> 24) & 0xff; }
 
-__device__ __forceinline__ int wrap(int v, int n) {
+__host__ __device__ __forceinline__ int wrap(int v, int n) {
   int r = v % n;
   return r < 0 ? r + n : r;
 }
@@ -264,6 +264,19 @@ __device__ __forceinline__ int as_idx(C v) {
     return (int)v;
 }
 
+// Where the state between two steps keeps population i (eq. 3 splits a step
+// into collision and propagation; the state is one of the two halves):
+//  kLayAB:       two arrays; the current one holds the post-collision f*_i(x)
+//                at [i][x], the sweep pulls f*_i(x - c_i) and writes the other.
+//  kLayAAStream: one array (AA pattern) holding the post-propagation f_i(x) at
+//                [i][x] (after an odd step, and initially); the sweep reads
+//                its own site and writes f*_i(x) to [opp(i)][x].
+//  kLayAASwap:   one array holding f*_i(x) at [opp(i)][x] (after an even
+//                step); the sweep reads [opp(i)][x - c_i] and writes f*_i(x)
+//                to [i][x + c_i], where the next sweep finds it at its own site.
+// In both AA halves every thread reads and writes the same q locations.
+constexpr int kLayAB = 0, kLayAAStream = 1, kLayAASwap = 2;
+
 // ---------------------------------------------------------------------------
 // K1: one pass over every site = propagation of the previous step (pull; the
 // previous step's IS substep is already in the state it pulls from), BGK
@@ -326,11 +339,10 @@ __device__ __forceinline__ double recip(double v) { return 1.0 / v; }
 
 // The work of one site (x, y, z) of a box of nx x ny x nz sites whose first
 // site is `off`; fbt holds 3 w_i c_i . f_b of that box.
-template <int Q, typename T, bool PART>
-__device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restrict__ B,
-                                           const SweepArgs<Q, typename Store<T>::C>& a, const SiteArgs<T>& sa,
-                                           int x, int y, int z, int nx, int ny, int nz, int off,
-                                           const typename Store<T>::C (&fbt)[Q]) {
+template <int Q, typename T, bool PART, int LAY>
+__device__ __forceinline__ void sweep_site(const T* A, T* B, const SweepArgs<Q, typename Store<T>::C>& a,
+                                           const SiteArgs<T>& sa, int x, int y, int z, int nx, int ny, int nz,
+                                           int off, const typename Store<T>::C (&fbt)[Q]) {
   using L = Lattice<Q>;
   using C = typename Store<T>::C;
   const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
@@ -352,11 +364,12 @@ __device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restric
   C g[Q];
 #pragma unroll
   for (int i = 0; i < Q; i++) {
-    // pull: f_i(x, t+1) comes from x - c_i
-    const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
-    const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
-    const int sz = L::cz(i) > 0 ? zm : (L::cz(i) < 0 ? zp : z);
-    const T* src = plane_at(A, i, a.N, off + sx + nx * (sy + ny * sz));
+    // f_i arriving at x: pulled from x - c_i, or found at x itself in the
+    // post-propagation half of the AA pattern
+    const int sx = LAY == kLayAAStream ? x : (L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x));
+    const int sy = LAY == kLayAAStream ? y : (L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y));
+    const int sz = LAY == kLayAAStream ? z : (L::cz(i) > 0 ? zm : (L::cz(i) < 0 ? zp : z));
+    const T* src = plane_at(A, LAY == kLayAASwap ? opposite<Q>(i) : i, a.N, off + sx + nx * (sy + ny * sz));
     g[i] = kRaw ? Store<T>::ld(src) : pop_ld<Q, T>(src, i);
   }
   C drho = 0, jx = 0, jy = 0, jz = 0;
@@ -441,7 +454,12 @@ __device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restric
   }
 #pragma unroll
   for (int i = 0; i < Q; i++) {
-    T* dst = plane_at(B, i, a.N, s);
+    // f*_i(x): at x in the next array, in the opposite slot at x, or pushed to
+    // x + c_i (the three layouts above)
+    const int dx = LAY == kLayAASwap ? (L::cx(i) > 0 ? xp : (L::cx(i) < 0 ? xm : x)) : x;
+    const int dy = LAY == kLayAASwap ? (L::cy(i) > 0 ? yp : (L::cy(i) < 0 ? ym : y)) : y;
+    const int dz = LAY == kLayAASwap ? (L::cz(i) > 0 ? zp : (L::cz(i) < 0 ? zm : z)) : z;
+    T* dst = plane_at(B, LAY == kLayAAStream ? opposite<Q>(i) : i, a.N, off + dx + nx * (dy + ny * dz));
     if constexpr (kRaw)
       Store<T>::st(dst, g[i]);
     else
@@ -450,12 +468,12 @@ __device__ __forceinline__ void sweep_site(const T* __restrict__ A, T* __restric
 }
 
 // One box: workgroup (bx, y, z) covers kSweepBlock sites of row (y, z).
-template <int Q, typename T, bool PART>
-__global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* __restrict__ A, T* __restrict__ B,
-                                                        SweepArgs<Q, typename Store<T>::C> a, SiteArgs<T> sa) {
+template <int Q, typename T, bool PART, int LAY>
+__global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* A, T* B, SweepArgs<Q, typename Store<T>::C> a,
+                                                        SiteArgs<T> sa) {
   const int x = (int)blockIdx.x * kSweepBlock + (int)threadIdx.x;
   if (x >= a.nx) return;
-  sweep_site<Q, T, PART>(A, B, a, sa, x, (int)blockIdx.y, (int)blockIdx.z, a.nx, a.ny, a.nz, 0, a.fbt);
+  sweep_site<Q, T, PART, LAY>(A, B, a, sa, x, (int)blockIdx.y, (int)blockIdx.z, a.nx, a.ny, a.nz, 0, a.fbt);
 }
 
 // q = n / d for 0 <= n < 2^31, 1 <= d, from inv = 1/d rounded to FP64: the
@@ -475,9 +493,9 @@ __device__ __forceinline__ int div_exact(int n, int d, double inv) {
 // bit pairs {lo, hi, lo, hi} for the split of a box-local index into (x, y,
 // z).  A persistent grid walks the tile list (the workgroup width, grid size
 // and occupancy cap are the tunable launch shape).
-template <int Q, typename T, bool PART>
-__global__ __launch_bounds__(kTileMax) void k_sweep_tiles(const T* __restrict__ A, T* __restrict__ B,
-                                                           SweepArgs<Q, typename Store<T>::C> a, SiteArgs<T> sa,
+template <int Q, typename T, bool PART, int LAY>
+__global__ __launch_bounds__(kTileMax) void k_sweep_tiles(const T* A, T* B, SweepArgs<Q, typename Store<T>::C> a,
+                                                           SiteArgs<T> sa,
                                                            const int4* __restrict__ tiles, int ntiles,
                                                            const typename Store<T>::C* __restrict__ fbt_tab) {
   using C = typename Store<T>::C;
@@ -491,7 +509,7 @@ __global__ __launch_bounds__(kTileMax) void k_sweep_tiles(const T* __restrict__ 
     C fb[Q];
 #pragma unroll
     for (int i = 0; i < Q; i++) fb[i] = fbt_tab[tl.x * Q + i];
-    sweep_site<Q, T, PART>(A, B, a, sa, lin - yz * tg.x, yz - z * tg.y, z, tg.x, tg.y, tg.z, tg.w, fb);
+    sweep_site<Q, T, PART, LAY>(A, B, a, sa, lin - yz * tg.x, yz - z * tg.y, z, tg.x, tg.y, tg.z, tg.w, fb);
   }
 }
 
@@ -980,10 +998,21 @@ __global__ __launch_bounds__(256) void k_closure(DevParticles P, int np, Boxes B
 //    kSiteBS at an owned BS site, whose record then receives the rigid-body
 //    velocity of the next BS substep (eq. 5) and the owner entry's index.
 // ---------------------------------------------------------------------------
+// Element of f*_i of site (x, y, z) of box G in a post-collision state of
+// layout lay (kLayAB, or either half of the AA pattern).
+template <int Q>
+__device__ __forceinline__ size_t coll_index(int lay, int i, const Geo& G, int x, int y, int z, int64_t NT) {
+  using L = Lattice<Q>;
+  if (lay == kLayAAStream)
+    return (size_t)i * NT + site_of(G, wrap1(x + L::cx(i), G.nx), wrap1(y + L::cy(i), G.ny), wrap1(z + L::cz(i), G.nz));
+  return (size_t)(lay == kLayAASwap ? opposite<Q>(i) : i) * NT + site_of(G, x, y, z);
+}
+
 // IS values of site s (offset o of particle p with the particle's velocities
 // in the compute type; the value is stored in it).
 template <int Q, typename T>
-__device__ __forceinline__ void impose_is(T* __restrict__ S, int64_t NT, int s, double dr, typename Store<T>::C rx,
+__device__ __forceinline__ void impose_is(T* __restrict__ S, int64_t NT, int lay, const Geo& G, int x, int y, int z,
+                                          double dr, typename Store<T>::C rx,
                                           typename Store<T>::C ry, typename Store<T>::C rz,
                                           typename Store<T>::C upx, typename Store<T>::C upy,
                                           typename Store<T>::C upz, typename Store<T>::C wx,
@@ -999,7 +1028,8 @@ __device__ __forceinline__ void impose_is(T* __restrict__ S, int64_t NT, int s, 
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     const C cu = C(L::cx(i)) * vx + C(L::cy(i)) * vy + C(L::cz(i)) * vz;
-    S[(size_t)i * NT + s] = pop_enc<Q, T>(i, (double)(C(L::w(i)) * (dc + rho * (C(3) * cu + C(4.5) * cu * cu - usq))));
+    S[coll_index<Q>(lay, i, G, x, y, z, NT)] =
+        pop_enc<Q, T>(i, (double)(C(L::w(i)) * (dc + rho * (C(3) * cu + C(4.5) * cu * cu - usq))));
   }
 }
 
@@ -1024,7 +1054,7 @@ __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own, co
                                                   uint8_t* __restrict__ flag, typename Store<T>::C* __restrict__ vel,
                                                   const typename Store<T>::C* __restrict__ drho, T* __restrict__ S,
                                                   DevParticles P, DevEntries E, Boxes BX, int nent, double rho0,
-                                                  int pending) {
+                                                  int pending, int lay) {
   using C = typename Store<T>::C;
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= nent) return;
@@ -1039,11 +1069,12 @@ __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own, co
     double dr;
     if (P.jump[p]) {
       dr = 0;
-      for (int j = 0; j < Q; j++) dr += (double)pop_ld<Q, T>(S + (size_t)j * BX.NT + s, j);
+      for (int j = 0; j < Q; j++) dr += (double)pop_ld<Q, T>(S + coll_index<Q>(lay, j, G, x, y, z, BX.NT), j);
     } else {
       dr = (double)drho[s];
     }
-    impose_is<Q, T>(S, BX.NT, s, dr, (C)((double)off_x(pk) - P.phi[3 * p]), (C)((double)off_y(pk) - P.phi[3 * p + 1]),
+    impose_is<Q, T>(S, BX.NT, lay, G, x, y, z, dr, (C)((double)off_x(pk) - P.phi[3 * p]),
+                    (C)((double)off_y(pk) - P.phi[3 * p + 1]),
                     (C)((double)off_z(pk) - P.phi[3 * p + 2]), (C)P.u[3 * p], (C)P.u[3 * p + 1], (C)P.u[3 * p + 2],
                     (C)P.om[3 * p], (C)P.om[3 * p + 1], (C)P.om[3 * p + 2], rho0);
   }
@@ -1064,7 +1095,7 @@ __global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __re
                                                         uint8_t* __restrict__ flag, typename Store<T>::C* __restrict__ vel,
                                                         const typename Store<T>::C* __restrict__ drho,
                                                         T* __restrict__ S, DevParticles P, DevEntries E, Boxes BX,
-                                                        double rho0, int pending, int dim) {
+                                                        double rho0, int pending, int dim, int lay) {
   using C = typename Store<T>::C;
   extern __shared__ __align__(16) unsigned char smem[];
   const int p = blockIdx.x;
@@ -1130,18 +1161,19 @@ __global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __re
       const int e = e0 + t;
       const int pk = pkv[j];
       const int ox = off_x(pk), oy = off_y(pk), oz = off_z(pk);
-      const int s = site_of(G, wrap1(ox0 + ox, G.nx), wrap1(oy0 + oy, G.ny), wrap1(oz0 + oz, G.nz));
+      const int sxx = wrap1(ox0 + ox, G.nx), syy = wrap1(oy0 + oy, G.ny), szz = wrap1(oz0 + oz, G.nz);
+      const int s = site_of(G, sxx, syy, szz);
       const int w = (ox + hw) + W * ((oy + hw) + W * (oz + hz));
       const int o = s_own[w];
       if (pending && o == 2 * e + 1) {
         double dr;
         if (jump) {
           dr = 0;
-          for (int k = 0; k < Q; k++) dr += (double)pop_ld<Q, T>(S + (size_t)k * BX.NT + s, k);
+          for (int k = 0; k < Q; k++) dr += (double)pop_ld<Q, T>(S + coll_index<Q>(lay, k, G, sxx, syy, szz, BX.NT), k);
         } else {
           dr = (double)s_drho[w];
         }
-        impose_is<Q, T>(S, BX.NT, s, dr, (C)((double)ox - phx), (C)((double)oy - phy), (C)((double)oz - phz), cupx,
+        impose_is<Q, T>(S, BX.NT, lay, G, sxx, syy, szz, dr, (C)((double)ox - phx), (C)((double)oy - phy), (C)((double)oz - phz), cupx,
                         cupy, cupz, cwx, cwy, cwz, rho0);
       }
       if (rep[j] != e) continue;  // another entry represents this site
@@ -1170,7 +1202,7 @@ __global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __re
 // the stride of a population plane.
 template <int Q, typename T>
 __global__ void k_moments(const T* __restrict__ A, double* __restrict__ rho, double* __restrict__ u,
-                          Geo G, int64_t NT, double rho0, int64_t s0, int64_t cnt) {
+                          Geo G, int64_t NT, double rho0, int64_t s0, int64_t cnt, int lay) {
   using L = Lattice<Q>;
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= cnt) return;
@@ -1179,8 +1211,12 @@ __global__ void k_moments(const T* __restrict__ A, double* __restrict__ rho, dou
   double drho = 0, j[3] = {0, 0, 0};
 #pragma unroll
   for (int i = 0; i < Q; i++) {
-    const int sx = wrap(x - L::cx(i), G.nx), sy = wrap(y - L::cy(i), G.ny), sz = wrap(z - L::cz(i), G.nz);
-    const double g = (double)pop_ld<Q, T>(A + (size_t)i * NT + site_of(G, sx, sy, sz), i);
+    // f_i arriving at x (the three state layouts)
+    const bool here = lay == kLayAAStream;
+    const int sx = here ? x : wrap(x - L::cx(i), G.nx), sy = here ? y : wrap(y - L::cy(i), G.ny),
+              sz = here ? z : wrap(z - L::cz(i), G.nz);
+    const int plane = lay == kLayAASwap ? opposite<Q>(i) : i;
+    const double g = (double)pop_ld<Q, T>(A + (size_t)plane * NT + site_of(G, sx, sy, sz), i);
     drho += g;
     j[0] += L::cx(i) * g;
     j[1] += L::cy(i) * g;
@@ -1228,7 +1264,7 @@ inline unsigned blocks_for(int64_t n, int per = 256) { return (unsigned)((n + pe
 // Workspace layout
 // ---------------------------------------------------------------------------
 struct Layout {
-  size_t f[2], drho, own, ball, flag, status;
+  size_t f[2], drho, own, ball, flag, status, stage;
   size_t x, x0, u, om, phi, fext, dP, dL, F, T, m, I, rad, b0, k, org, ent0, nbs, nis, nin, jump, box, cand_n, cand,
       pairs;
   size_t off, pid, slot, vel;
@@ -1282,12 +1318,14 @@ Layout make_layout(const lbm_params& p, const BoxSet& bs) {
   };
   const size_t fb = (size_t)p.lattice * N * store_size(p.storage);
   L.f[0] = take(fb);
-  L.f[1] = take(fb);
+  L.f[1] = p.aa ? L.f[0] : take(fb);  // the AA pattern updates one array in place
   L.drho = take((size_t)N * (p.storage == LBM_FP64 ? 8 : 4));
   L.own = take(sizeof(int) * N);
   L.ball = take(sizeof(int) * N);
   L.flag = take(N);
   L.status = take(64);
+  // moments staging of field read-outs (two arrays stage in the idle one)
+  L.stage = p.aa ? take(4 * sizeof(double) * (size_t)std::min<int64_t>(N, (int64_t)1 << 20)) : 0;
   const size_t v3 = sizeof(double) * 3 * np, v1 = sizeof(double) * np;
   L.x = take(v3); L.x0 = take(v3); L.u = take(v3); L.om = take(v3); L.phi = take(v3);
   L.fext = take(v3); L.dP = take(v3); L.dL = take(v3); L.F = take(v3); L.T = take(v3);
@@ -1352,6 +1390,7 @@ int check_params(const lbm_params* p) {
     return LBM_ECAPACITY;
   if (p->storage < LBM_FP64 || p->storage > LBM_BF16) return LBM_EINVAL;
   if (p->walls < 0 || p->walls >= (1 << dim)) return LBM_EINVAL;
+  if (p->aa != 0 && p->aa != 1) return LBM_EINVAL;
   const int n[3] = {p->nx, p->ny, p->nz};
   for (int a = 0; a < dim; a++) {
     if (!((p->walls >> a) & 1)) continue;
@@ -1422,6 +1461,10 @@ struct lbm_ctx {
   size_t ev_used;
 };
 
+// Layout of the state between steps: the AA pattern alternates its two
+// halves with the step parity (cur), kept like the buffer index of two arrays.
+int state_layout(const lbm_ctx* c) { return c->prm.aa ? (c->cur == 0 ? kLayAAStream : kLayAASwap) : kLayAB; }
+
 #define HIP_TRY(expr)                          \
   do {                                         \
     if ((expr) != hipSuccess) return LBM_EHIP; \
@@ -1458,11 +1501,11 @@ int launch_prepare(lbm_ctx* c, int pending) {
   if (c->lds_window > 0) {
     k_prepare_local<Q, T><<<c->np, kPrepareBlock, c->lds_window, c->stream>>>(
         c->own, c->ball, c->flag, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
-        c->prm.rho0, pending, c->dim);
+        c->prm.rho0, pending, c->dim, state_layout(c));
   } else {
     k_prepare<Q, T><<<blocks_for(c->nent), 256, 0, c->stream>>>(
         c->own, c->ball, c->flag, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
-        (int)c->nent, c->prm.rho0, pending);
+        (int)c->nent, c->prm.rho0, pending, state_layout(c));
   }
   HIP_TRY(hipGetLastError());
   return LBM_OK;
@@ -1531,31 +1574,41 @@ bool occ_ok(const lbm_ctx* c, int occ) {
   return occ == 0 || (occ > 0 && occ <= 32 && sweep_lds(c, occ) >= 1024 && sweep_lds(c, occ) <= (size_t)c->lds_block);
 }
 
-template <int Q, typename T>
-int launch_sweep(lbm_ctx* c, int w, int grid, int occ) {
+template <int Q, typename T, int LAY>
+int launch_sweep_as(lbm_ctx* c, int w, int grid, int occ) {
   using C = typename Store<T>::C;
   // the occupancy cap: LDS reserved (not used) by every workgroup
   const size_t lds = sweep_lds(c, occ);
   const SweepArgs<Q, C> a = sweep_args<Q, T>(c);
   const T* A = (const T*)c->f[c->cur];
-  T* B = (T*)c->f[1 - c->cur];
+  T* B = (T*)c->f[1 - c->cur];  // the same array under the AA pattern
   const SiteArgs<T> sa = site_args<Q, T>(c);
   if (w == 0) {
     const dim3 grid3((unsigned)a.nxb, (unsigned)c->G.ny, (unsigned)c->G.nz);
     if (c->np > 0)
-      k_sweep<Q, T, true><<<grid3, kSweepBlock, lds, c->stream>>>(A, B, a, sa);
+      k_sweep<Q, T, true, LAY><<<grid3, kSweepBlock, lds, c->stream>>>(A, B, a, sa);
     else
-      k_sweep<Q, T, false><<<grid3, kSweepBlock, lds, c->stream>>>(A, B, a, sa);
+      k_sweep<Q, T, false, LAY><<<grid3, kSweepBlock, lds, c->stream>>>(A, B, a, sa);
   } else {
     const int64_t nt = c->ntiles;
     const unsigned g = (unsigned)(grid > 0 && grid < nt ? grid : nt);
     if (c->np > 0)
-      k_sweep_tiles<Q, T, true><<<g, w, lds, c->stream>>>(A, B, a, sa, c->d_tiles, (int)nt, (const C*)c->d_fbt);
+      k_sweep_tiles<Q, T, true, LAY><<<g, w, lds, c->stream>>>(A, B, a, sa, c->d_tiles, (int)nt,
+                                                                (const C*)c->d_fbt);
     else
-      k_sweep_tiles<Q, T, false><<<g, w, lds, c->stream>>>(A, B, a, sa, c->d_tiles, (int)nt, (const C*)c->d_fbt);
+      k_sweep_tiles<Q, T, false, LAY><<<g, w, lds, c->stream>>>(A, B, a, sa, c->d_tiles, (int)nt,
+                                                                 (const C*)c->d_fbt);
   }
   HIP_TRY(hipGetLastError());
   return LBM_OK;
+}
+template <int Q, typename T>
+int launch_sweep(lbm_ctx* c, int w, int grid, int occ) {
+  switch (state_layout(c)) {
+    case kLayAAStream: return launch_sweep_as<Q, T, kLayAAStream>(c, w, grid, occ);
+    case kLayAASwap: return launch_sweep_as<Q, T, kLayAASwap>(c, w, grid, occ);
+    default: return launch_sweep_as<Q, T, kLayAB>(c, w, grid, occ);
+  }
 }
 
 template <int Q, typename T>
@@ -1599,7 +1652,7 @@ int launch_step(lbm_ctx* c) {
 template <int Q, typename T>
 int launch_moments(lbm_ctx* c, int box, double* d_rho, double* d_u, int64_t s0, int64_t cnt) {
   k_moments<Q, T><<<blocks_for(cnt), 256, 0, c->stream>>>((const T*)c->f[c->cur], d_rho, d_u, c->boxes[box], c->NT,
-                                                          c->prm.rho0, s0, cnt);
+                                                          c->prm.rho0, s0, cnt, state_layout(c));
   HIP_TRY(hipGetLastError());
   return LBM_OK;
 }
@@ -2148,6 +2201,7 @@ int lbm_get_sweep_config(lbm_ctx* c, int32_t* width, int32_t* grid, int32_t* blo
 int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* width, int32_t* grid, int32_t* blocks_per_cu,
                  double* best_ms) {
   if (!c || reps < 1) return LBM_EINVAL;
+  if (c->prm.aa) return LBM_EINVAL;  // a sweep in place cannot be repeated on the live state
   // a sweep recomputes B and the ball-site scratch from A and the records,
   // so repeating it leaves the state as one sweep does: time the candidates
   // on the live state
@@ -2260,10 +2314,11 @@ int lbm_forces(lbm_ctx* c, double* F, double* T, double* x, double* u, double* o
 int lbm_fields(lbm_ctx* c, double* rho, double* u, int32_t* owner) {
   if (!c) return LBM_EINVAL;
   if (rho || u) {
-    // the other population buffer is free between steps: stage moments there
-    const size_t stage = (size_t)c->q * c->NT * store_size(c->prm.storage);
+    // two arrays: the idle one stages the moments; AA: the staging area
+    const size_t stage = c->prm.aa ? 4 * sizeof(double) * (size_t)std::min<int64_t>(c->NT, (int64_t)1 << 20)
+                                   : (size_t)c->q * c->NT * store_size(c->prm.storage);
     const int64_t chunk = (int64_t)(stage / (4 * sizeof(double)));
-    double* d_rho = (double*)c->f[1 - c->cur];
+    double* d_rho = c->prm.aa ? (double*)(c->ws + c->L.stage) : (double*)c->f[1 - c->cur];
     double* d_u = d_rho + chunk;
     for (int b = 0; b < c->nbox; b++) {
       const Geo& g = c->boxes[b];
@@ -2313,19 +2368,43 @@ int lbm_particle_info(lbm_ctx* c, int32_t p, int32_t* nbs, int32_t* nis) {
 
 int lbm_get_distributions(lbm_ctx* c, double* f) {
   if (!c || !f) return LBM_EINVAL;
-  void* stage = c->f[1 - c->cur];
-  int rc = DISPATCH(c, launch_shift, c, c->f[c->cur], stage, 1);
-  if (rc != LBM_OK) return rc;
   const int64_t n = (int64_t)c->q * c->NT;
   const int ss = (int)store_size(c->prm.storage);
   std::vector<unsigned char> h((size_t)n * ss);
-  HIP_TRY(hipMemcpyAsync(h.data(), stage, (size_t)n * ss, hipMemcpyDeviceToHost, c->stream));
+  if (c->prm.aa) {
+    // one array: gather the post-propagation values on the host
+    HIP_TRY(hipMemcpyAsync(h.data(), c->f[0], (size_t)n * ss, hipMemcpyDeviceToHost, c->stream));
+  } else {
+    void* stage = c->f[1 - c->cur];
+    const int rc = DISPATCH(c, launch_shift, c, c->f[c->cur], stage, 1);
+    if (rc != LBM_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(h.data(), stage, (size_t)n * ss, hipMemcpyDeviceToHost, c->stream));
+  }
   HIP_TRY(hipStreamSynchronize(c->stream));
+  // element of the host copy that holds f_i of site s
+  const int lay = state_layout(c);
+  std::vector<int64_t> src;
+  if (lay == kLayAASwap) {
+    src.resize((size_t)n);
+    for (const Geo& g : c->boxes)
+      for (int z = 0; z < g.nz; z++)
+        for (int y = 0; y < g.ny; y++)
+          for (int x = 0; x < g.nx; x++)
+            for (int i = 0; i < c->q; i++) {
+              const int cx = c->q == 9 ? Lattice<9>::cx(i) : Lattice<19>::cx(i);
+              const int cy = c->q == 9 ? Lattice<9>::cy(i) : Lattice<19>::cy(i);
+              const int cz = c->q == 9 ? Lattice<9>::cz(i) : Lattice<19>::cz(i);
+              const int o = c->q == 9 ? opposite<9>(i) : opposite<19>(i);
+              const int64_t from = g.off + wrap(x - cx, g.nx) + (int64_t)g.nx * (wrap(y - cy, g.ny) +
+                                                                                  (int64_t)g.ny * wrap(z - cz, g.nz));
+              src[(size_t)i * c->NT + g.off + x + (int64_t)g.nx * (y + (int64_t)g.ny * z)] = (int64_t)o * c->NT + from;
+            }
+  }
   for (int i = 0; i < c->q; i++) {
     const double w = lattice_w(c->q, i);
     const double base = w * c->prm.rho0;
     for (int64_t s = 0; s < c->NT; s++) {
-      const int64_t k = (int64_t)i * c->NT + s;
+      const int64_t k = src.empty() ? (int64_t)i * c->NT + s : src[(size_t)i * c->NT + s];
       double g;
       switch (c->prm.storage) {
         case LBM_FP64: g = ((const double*)h.data())[k]; break;
@@ -2333,7 +2412,7 @@ int lbm_get_distributions(lbm_ctx* c, double* f) {
         case LBM_FP16: g = (double)(float)((const _Float16*)h.data())[k] * pop_unit<_Float16>(w); break;
         default: g = (double)bf16_bits_to_f32(((const uint16_t*)h.data())[k]) * pop_unit<bf16s>(w); break;
       }
-      f[k] = base + g;
+      f[(int64_t)i * c->NT + s] = base + g;
     }
   }
   return check_status(c);
@@ -2360,6 +2439,14 @@ int lbm_set_distributions(lbm_ctx* c, const double* f) {
         default: ((uint16_t*)h.data())[k] = f32_to_bf16_bits((float)(g / pop_unit<bf16s>(w))); break;
       }
     }
+  }
+  if (c->prm.aa) {
+    // the given populations are the complete post-propagation state: the
+    // AA pattern's post-propagation half (the next step is an even one)
+    HIP_TRY(hipMemcpyAsync(c->f[0], h.data(), (size_t)n * ss, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->cur = 0;
+    return LBM_OK;
   }
   HIP_TRY(hipMemcpyAsync(stage, h.data(), (size_t)n * ss, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));

@@ -33,7 +33,7 @@ class lbm_params(ctypes.Structure):
                 ("gravity", ctypes.c_double * 3), ("body_force", ctypes.c_double * 3),
                 ("zero_net_force", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("max_particles", ctypes.c_int32), ("max_radius", ctypes.c_double),
-                ("walls", ctypes.c_int32), ("wall_velocity", ctypes.c_double * 18)]
+                ("walls", ctypes.c_int32), ("wall_velocity", ctypes.c_double * 18), ("aa", ctypes.c_int32)]
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -108,7 +108,7 @@ def _d(a):
 
 def make_params(lattice, nx, ny, nz=1, tau=1.0, rho0=1.0, gravity=(0, 0, 0), body_force=(0, 0, 0),
                 zero_net_force=False, storage="fp32", max_particles=0, max_radius=1.0, walls=0,
-                wall_velocity=None):
+                wall_velocity=None, aa=False):
     p = lbm_params()
     p.lattice, p.nx, p.ny, p.nz = int(lattice), int(nx), int(ny), int(nz)
     p.tau, p.rho0 = float(tau), float(rho0)
@@ -124,6 +124,7 @@ def make_params(lattice, nx, ny, nz=1, tau=1.0, rho0=1.0, gravity=(0, 0, 0), bod
         wu = np.asarray(wall_velocity, dtype=np.float64).reshape(18)
         for k in range(18):
             p.wall_velocity[k] = float(wu[k])
+    p.aa = int(bool(aa))
     return p
 
 
@@ -179,14 +180,16 @@ class Simulation:
 
     def __init__(self, lattice, nx, ny, nz=1, tau=1.0, rho0=1.0, gravity=(0, 0, 0),
                  body_force=(0, 0, 0), zero_net_force=False, storage="fp32", max_particles=0,
-                 max_radius=1.0, walls=0, wall_velocity=None, device="cuda", stream=None, boxes=None):
+                 max_radius=1.0, walls=0, wall_velocity=None, device="cuda", stream=None, boxes=None,
+                 aa=False):
         """One box of nx x ny x nz sites, or with boxes = [[nx, ny, nz], ...]
         an ensemble of independent boxes stepped together (nx, ny, nz are then
-        ignored)."""
+        ignored).  aa=True keeps one population array updated in place (AA
+        pattern) instead of two."""
         import torch
         self.params = make_params(lattice, nx, ny, nz, tau, rho0, gravity, body_force,
                                   zero_net_force, storage, max_particles, max_radius, walls,
-                                  wall_velocity)
+                                  wall_velocity, aa)
         self.q = int(lattice)
         if boxes is None:
             self.dims = np.array([[int(nx), int(ny), int(nz)]], dtype=np.int32)

@@ -58,10 +58,30 @@ def _rc_workspace(**kw):
     (dict(ny=4, walls=2), lbm.LBM_EINVAL),               # no fluid layer left
     (dict(walls=2, wall_velocity=[0] * 7 + [0.01] + [0] * 10), lbm.LBM_EINVAL),  # normal wall velocity
     (dict(walls=2, wall_velocity=[0] * 6 + [math.nan] + [0] * 11), lbm.LBM_ENONFINITE),
+    (dict(nx=1024, ny=1024, nz=1024, storage="fp64"), lbm.LBM_EINVAL),  # a plane above 4 GiB
+    (dict(nx=1024, ny=1024, nz=1025, storage="fp32"), lbm.LBM_EINVAL),
 ])
 def test_invalid_parameters_rejected_on_host(kw, code):
     rc, _ = _rc_workspace(**kw)
     assert rc == code
+
+
+def test_plane_limit_and_aa_layout():
+    """Population planes of up to 4 GiB (32-bit offsets): FP32 1024^3 is the
+    largest cube.  The AA layout keeps one population array instead of two;
+    any other value of the flag is refused."""
+    rc, _ = _rc_workspace(nx=1024, ny=1024, nz=1024, storage="fp32", max_particles=0)
+    assert rc == 0
+    rc2, n2 = _rc_workspace()
+    rc1, n1 = _rc_workspace(aa=True)
+    assert rc1 == rc2 == 0
+    # one q N FP32 array less, one 4-double-per-site staging area more (256-B alignment)
+    expect = 19 * 16 ** 3 * 4 - 4 * 8 * 16 ** 3
+    assert abs((n2 - n1) - expect) <= 512
+    p = lbm.make_params(19, 16, 16, 16, tau=0.6, max_particles=4, max_radius=3.0)
+    p.aa = 2
+    n = ctypes.c_size_t(0)
+    assert lbm.lib().lbm_workspace_size(ctypes.byref(p), ctypes.byref(n)) == lbm.LBM_EINVAL
 
 
 def test_workspace_size_scales_with_box_and_precision():
