@@ -75,8 +75,11 @@ def test_plane_limit_and_aa_layout():
     rc2, n2 = _rc_workspace()
     rc1, n1 = _rc_workspace(aa=True)
     assert rc1 == rc2 == 0
-    # one q N FP32 array less, one 4-double-per-site staging area more (256-B alignment)
-    expect = 19 * 16 ** 3 * 4 - 4 * 8 * 16 ** 3
+    # one FP32 array of q planes less (planes padded to a multiple of 256 sites
+    # plus 256), one 4-double-per-site staging area more (256-B alignment)
+    N = 16 ** 3
+    stride = (N + 255) // 256 * 256 + 256
+    expect = 19 * stride * 4 - 4 * 8 * N
     assert abs((n2 - n1) - expect) <= 512
     p = lbm.make_params(19, 16, 16, 16, tau=0.6, max_particles=4, max_radius=3.0)
     p.aa = 2
