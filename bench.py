@@ -248,7 +248,7 @@ def main():
         Unless --no-autotune, the library's autotuner picks the sweep launch
         on the live state after the warm-up, outside the timed region."""
         sim_.step(warmup)
-        if not args.no_autotune:
+        if not args.no_autotune and not sim_.params.aa:
             sim_.autotune(reps=5)
             sim_.step(2)
         torch.cuda.synchronize()
@@ -278,8 +278,8 @@ def main():
     achieved = bps * N / (sweep_avg_ms * 1e-3) / 1e9
     ceiling = copy_ceiling(torch, lbm, stream)
     launch = dict(zip(("width", "grid", "blocks_per_cu"), sim.sweep_config()))
-    kernel = "%s<%d,%s,%s>" % ("k_sweep" if launch["width"] == 0 else "k_sweep_tiles", q, kname,
-                                "true" if args.particles else "false")
+    kernel = "%s<%d,%s,%s,0>" % ("k_sweep" if launch["width"] == 0 else "k_sweep_tiles", q, kname,
+                                  "true" if args.particles else "false")
     traffic = None
     if args.particles == len(cfg["particles"]["radius"]):
         traffic = measured_traffic(kernel.replace(",", ", "), cfg["name"], cfg["box"], launch)
@@ -316,29 +316,36 @@ def main():
     if not args.no_variants and args.storage == "fp32":
         out["variants"] = {}
         sim.close()
-        for st in ("fp16", "bf16"):
+        for name in ("fp16", "bf16", "fp32_aa"):
+            st, aa = ("fp32", True) if name == "fp32_aa" else (name, False)
             v = lbm.Simulation(q, nx, ny, nz, tau=cfg["tau"], gravity=cfg["gravity"], zero_net_force=True,
                                storage=st, max_particles=max(len(p["radius"]), 1),
-                               max_radius=float(np.max(cfg["particles"]["radius"])))
+                               max_radius=float(np.max(cfg["particles"]["radius"])), aa=aa)
             if args.particles:
                 v.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
+            if aa:  # an AA context cannot be autotuned: the FP32 context's launch
+                v.set_sweep_config(launch["width"], launch["grid"], launch["blocks_per_cu"])
             vms, (vsw, vn) = timed(v, args.steps, args.warmup, True)
             vb = lbm.lbm_bytes_per_site(v.params)
             vl = dict(zip(("width", "grid", "blocks_per_cu"), v.sweep_config()))
-            vk = "%s<%d, %s, %s>" % ("k_sweep" if vl["width"] == 0 else "k_sweep_tiles", q,
-                                     {"fp16": "_Float16", "bf16": "bf16s"}[st], "true" if args.particles else "false")
+            vk = "%s<%d, %s, %s%s>" % ("k_sweep" if vl["width"] == 0 else "k_sweep_tiles", q,
+                                       {"fp16": "_Float16", "bf16": "bf16s", "fp32": "float"}[st],
+                                       "true" if args.particles else "false", ", 0" if not aa else ", 1/2")
             vt = None
-            if args.particles == len(cfg["particles"]["radius"]):
+            if args.particles == len(cfg["particles"]["radius"]) and not aa:
                 vt = measured_traffic(vk, cfg["name"], cfg["box"], vl)
             vm = N / (vms / args.steps * 1e-3) / 1e6
             vs = vsw / max(vn, 1)
-            out["variants"][st] = {"value": round(vm, 1), "ms_per_step": round(vms / args.steps, 4),
+            out["variants"][name] = {"value": round(vm, 1), "ms_per_step": round(vms / args.steps, 4),
                                    "sweep_launch": vl, "kernel": vk.replace(", ", ","),
                                    "traffic": None if vt is None else vt["total"],
                                    "speedup_vs_fp32": round(vm / mlups, 3), "bytes_per_site": vb,
                                    "sweep_avg_ms": round(vs, 4), "sweep_GBps": round(vb * N / (vs * 1e-3) / 1e9, 1)}
             v.close()
-            print("variant %s timed" % st, file=sys.stderr, flush=True)
+            if aa:
+                out["variants"][name]["population_bytes"] = int(q * N * 4)
+                out["variants"][name]["population_bytes_two_arrays"] = int(2 * q * N * 4)
+            print("variant %s timed" % name, file=sys.stderr, flush=True)
     if not args.no_batched and args.storage == "fp32" and args.workload == "spheres-3d":
         out["closure_mlp"] = closure_mlp_rates(torch, lbm)
         print("closure network timed", file=sys.stderr, flush=True)
