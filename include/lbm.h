@@ -31,7 +31,8 @@
  * (eq. 16-19 with the wall as an infinite mass), after the particle pairs.
  *
  * Conventions
- *  - Lattice units: dx = dt = 1.  Every axis is periodic.
+ *  - Lattice units: dx = dt = 1.  An axis is periodic unless wall layers
+ *    close it (lbm_params.walls).
  *  - Distribution layout (host buffers): f[q][nz][ny][nx], x fastest, plain f
  *    (not deviations).  Velocity order:
  *      D2Q9 : (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1)
