@@ -743,6 +743,23 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
   const double upx = P.u[3 * p], upy = P.u[3 * p + 1], upz = P.u[3 * p + 2];
   const double wx = P.om[3 * p], wy = P.om[3 * p + 1], wz = P.om[3 * p + 2];
 
+  // Close neighbours j > p in the same box (positions before translation):
+  // the first chunk's test is issued here, so that its loads overlap the
+  // entry loads below; the list is built after the sums.
+  const double xpx = P.x[3 * p], xpy = P.x[3 * p + 1], xpz = P.x[3 * p + 2];
+  const double rp = P.rad[p];
+  const int np = G.p1;
+  auto is_close = [&](int j) {
+    if (j >= np) return false;
+    double dx = P.x[3 * j] - xpx, dy = P.x[3 * j + 1] - xpy, dz = P.x[3 * j + 2] - xpz;
+    dx -= G.nx * floor(dx / G.nx + 0.5);
+    dy -= G.ny * floor(dy / G.ny + 0.5);
+    if (G.nz > 1) dz -= G.nz * floor(dz / G.nz + 0.5);
+    const double lim = rp + P.rad[j] + margin;
+    return dx * dx + dy * dy + dz * dz <= lim * lim;
+  };
+  const bool close_first = is_close(p + 1 + tid);
+
   double acc[6] = {0, 0, 0, 0, 0, 0};
   const int ne = nbs + nis + nin;
   constexpr int kEnt = 4;  // entries per thread whose loads are issued together
@@ -805,26 +822,14 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
       P.dL[3 * p + tid - 3] = v;
   }
 
-  // Close neighbours j > p in the same box (positions before translation),
-  // listed in increasing j: the only pairs that can pass the collision test
-  // this step while every speed stays below kMargin / 2 (checked in the
-  // particle update), and, with margin >= the closure's gap, every pair the
-  // closure acts on.
-  const double xpx = P.x[3 * p], xpy = P.x[3 * p + 1], xpz = P.x[3 * p + 2];
-  const double rp = P.rad[p];
-  const int np = G.p1;
+  // The close neighbours listed in increasing j: the only pairs that can pass
+  // the collision test this step while every speed stays below kMargin / 2
+  // (checked in the particle update), and, with margin >= the closure's gap,
+  // every pair the closure acts on.
   int base = 0;
   for (int j0 = p + 1; j0 < np; j0 += kBoundaryBlock) {
     const int j = j0 + tid;
-    bool close = false;
-    if (j < np) {
-      double dx = P.x[3 * j] - xpx, dy = P.x[3 * j + 1] - xpy, dz = P.x[3 * j + 2] - xpz;
-      dx -= G.nx * floor(dx / G.nx + 0.5);
-      dy -= G.ny * floor(dy / G.ny + 0.5);
-      if (G.nz > 1) dz -= G.nz * floor(dz / G.nz + 0.5);
-      const double lim = rp + P.rad[j] + margin;
-      close = dx * dx + dy * dy + dz * dz <= lim * lim;
-    }
+    const bool close = j0 == p + 1 ? close_first : is_close(j);
     const unsigned long long bal = __ballot(close);
     if (lane == 0) s_cnt[wv] = __popcll(bal);
     __syncthreads();
@@ -869,6 +874,26 @@ __global__ __launch_bounds__(256) void k_stamp(int* __restrict__ own, int* __res
   const int kind = entry_kind(pk);
   // wall sites belong to the wall
   if (kind != 3 && !wall_site(G, x, y, z)) atomicMin(&own[s], 2 * e + (kind == 2));
+}
+
+// The same for every particle, one workgroup each: the particle's box, origin
+// and entry range are uniform loads and its entries coalesced ones, so each
+// entry costs one dependent load before its stores (the per-step stamp).
+__global__ __launch_bounds__(256) void k_stamp_particles(int* __restrict__ own, int* __restrict__ ball,
+                                                         DevParticles P, DevEntries E, Boxes BX) {
+  const int p = blockIdx.x;
+  const Geo G = geo_of(BX, P, p);
+  const int e0 = P.ent0[p], ne = P.nbs[p] + P.nis[p] + P.nin[p];
+  const int ox = P.org[3 * p], oy = P.org[3 * p + 1], oz = P.org[3 * p + 2];
+  for (int t = threadIdx.x; t < ne; t += 256) {
+    const int e = e0 + t;
+    const int pk = E.off[e];
+    const int x = wrap1(ox + off_x(pk), G.nx), y = wrap1(oy + off_y(pk), G.ny), z = wrap1(oz + off_z(pk), G.nz);
+    const int s = site_of(G, x, y, z);
+    ball[s] = e;
+    const int kind = entry_kind(pk);
+    if (kind != 3 && !wall_site(G, x, y, z)) atomicMin(&own[s], 2 * e + (kind == 2));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1651,7 +1676,7 @@ int launch_step(lbm_ctx* c) {
       k_particles<kParticleBlock><<<1, kParticleBlock, 0, c->stream>>>(c->P, c->dim, bx, c->status);
     else
       k_particles<kBoxParticleBlock><<<c->nbox, kBoxParticleBlock, 0, c->stream>>>(c->P, c->dim, bx, c->status);
-    k_stamp<<<blocks_for(c->nent), 256, 0, c->stream>>>(c->own, c->ball, c->P, c->E, bx, 0, (int)c->nent);
+    k_stamp_particles<<<c->np, 256, 0, c->stream>>>(c->own, c->ball, c->P, c->E, bx);
     HIP_TRY(hipGetLastError());
   }
   c->cur = 1 - c->cur;  // f[cur] now holds this step's post-collision state
