@@ -12,19 +12,18 @@
 //              of every owned BS site from its slot, deterministic
 //              wave-shuffle + LDS sums, release of the particle's stamps, and
 //              the list of particles close enough to collide.         eq. 6-9
-//   particles  one workgroup: Newton-Euler update with buoyancy-corrected
-//              weight, hard-core collisions in lexicographic pair order,
-//              translation and integer shift.               eq. 10-11, 13, 16-19
-//   stamp      rebuild the maps at the new shifts: the owner map (lowest BS/IS
-//              entry index, hence lowest particle id; stored as 2e + [IS]) and
-//              the ball map (one representative entry of any kind per ball
-//              site: whichever write lands last).
+//   particles  one workgroup per box: Newton-Euler update with buoyancy-
+//              corrected weight, hard-core collisions in lexicographic pair
+//              order, translation and integer shift.        eq. 10-11, 13, 16-19
+//   stamp      rebuild the owner map at the new shifts (lowest BS/IS entry
+//              index, hence lowest particle id; stored as 2e + [IS]).
 //                                                                    eq. 14-15
 //   prepare    one workgroup per particle: the IS substep at the new
 //              positions (eq. 12) written in place into the post-collision
 //              state -- f^eq_i(rho_I, u_p' + omega_p' x r) at every owned IS
-//              site -- and, through each ball site's representative entry,
-//              the site flag and, at an owned BS site, its record: the
+//              site -- the flag of every ball site (every entry at a site
+//              writes the same value, read off the owner map) and, by the
+//              owning entry, the record of every owned BS site: the
 //              rigid-body velocity u_p + omega x r of its next BS substep
 //              (eq. 5) and the owner entry.
 // The IS substep of step t acts on the post-collision populations of IS sites
@@ -727,7 +726,7 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int dim, Boxes
 // of the particle's stamps, and the list of particles close enough to collide
 // this step.  One workgroup per particle.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own, int* __restrict__ ball,
+__global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own,
                                                             uint8_t* __restrict__ flag, const double* __restrict__ slot,
                                                             DevParticles P, DevEntries E, Boxes BX,
                                                             double rho0, double margin, int* status) {
@@ -786,7 +785,6 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
       const int pk = pkv[j];
       const int kind = entry_kind(pk);
       const int s = sv[j];
-      ball[s] = kEmpty;
       flag[s] = 0;
       if (kind == 2 && ov[j] == 2 * e + 1) own[s] = kEmpty;
       if (kind != 1 || ov[j] != 2 * e) continue;  // BS sites owned by this entry only
@@ -854,13 +852,10 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
 }
 
 // ---------------------------------------------------------------------------
-// K4: stamp every template entry at its particle's shift.  BS/IS entries
-// claim the owner map (lowest index, hence lowest particle id, wins); every
-// entry writes the ball map, and whichever entry lands there last represents
-// the site (a record describes the site, not the entry, so any choice gives
-// the same results).
+// K4: stamp every template entry at its particle's shift: BS/IS entries
+// claim the owner map (lowest index, hence lowest particle id, wins).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_stamp(int* __restrict__ own, int* __restrict__ ball, DevParticles P,
+__global__ __launch_bounds__(256) void k_stamp(int* __restrict__ own, DevParticles P,
                                                 DevEntries E, Boxes BX, int e_begin, int e_end) {
   const int e = e_begin + blockIdx.x * 256 + threadIdx.x;
   if (e >= e_end) return;
@@ -870,7 +865,6 @@ __global__ __launch_bounds__(256) void k_stamp(int* __restrict__ own, int* __res
   int x, y, z;
   entry_xyz(P, G, p, pk, x, y, z);
   const int s = site_of(G, x, y, z);
-  ball[s] = e;
   const int kind = entry_kind(pk);
   // wall sites belong to the wall
   if (kind != 3 && !wall_site(G, x, y, z)) atomicMin(&own[s], 2 * e + (kind == 2));
@@ -879,8 +873,8 @@ __global__ __launch_bounds__(256) void k_stamp(int* __restrict__ own, int* __res
 // The same for every particle, one workgroup each: the particle's box, origin
 // and entry range are uniform loads and its entries coalesced ones, so each
 // entry costs one dependent load before its stores (the per-step stamp).
-__global__ __launch_bounds__(256) void k_stamp_particles(int* __restrict__ own, int* __restrict__ ball,
-                                                         DevParticles P, DevEntries E, Boxes BX) {
+__global__ __launch_bounds__(256) void k_stamp_particles(int* __restrict__ own, DevParticles P, DevEntries E,
+                                                         Boxes BX) {
   const int p = blockIdx.x;
   const Geo G = geo_of(BX, P, p);
   const int e0 = P.ent0[p], ne = P.nbs[p] + P.nis[p] + P.nin[p];
@@ -890,7 +884,6 @@ __global__ __launch_bounds__(256) void k_stamp_particles(int* __restrict__ own, 
     const int pk = E.off[e];
     const int x = wrap1(ox + off_x(pk), G.nx), y = wrap1(oy + off_y(pk), G.ny), z = wrap1(oz + off_z(pk), G.nz);
     const int s = site_of(G, x, y, z);
-    ball[s] = e;
     const int kind = entry_kind(pk);
     if (kind != 3 && !wall_site(G, x, y, z)) atomicMin(&own[s], 2 * e + (kind == 2));
   }
@@ -1020,9 +1013,11 @@ __global__ __launch_bounds__(256) void k_closure(DevParticles P, int np, Boxes B
 //    site may then lie outside the ball the sweep kept densities for); the
 //    owner reads them before it overwrites them, and no other thread touches
 //    that site.
-//  - Records: the entry representing a ball site (ball map) sets its flag,
-//    kSiteBS at an owned BS site, whose record then receives the rigid-body
-//    velocity of the next BS substep (eq. 5) and the owner entry's index.
+//  - Records: every entry at a ball site writes its flag, kSiteBS at an
+//    owned BS site and kSiteBall elsewhere (the same value from every
+//    writer, read off the owner map); the owning BS entry writes the site's
+//    record: the rigid-body velocity of the next BS substep (eq. 5) and its
+//    own index.
 // ---------------------------------------------------------------------------
 // Element of f*_i of site (x, y, z) of box G in a post-collision state of
 // layout lay (kLayAB, or either half of the AA pattern).
@@ -1076,7 +1071,7 @@ __device__ __forceinline__ void store_bs_velocity(C* __restrict__ vel, int s, in
 }
 
 template <int Q, typename T>
-__global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own, const int* __restrict__ ball,
+__global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own,
                                                   uint8_t* __restrict__ flag, typename Store<T>::C* __restrict__ vel,
                                                   const typename Store<T>::C* __restrict__ drho, T* __restrict__ S,
                                                   DevParticles P, DevEntries E, Boxes BX, int nent, double rho0,
@@ -1104,20 +1099,16 @@ __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own, co
                     (C)((double)off_z(pk) - P.phi[3 * p + 2]), (C)P.u[3 * p], (C)P.u[3 * p + 1], (C)P.u[3 * p + 2],
                     (C)P.om[3 * p], (C)P.om[3 * p + 1], (C)P.om[3 * p + 2], rho0);
   }
-  if (ball[s] != e) return;       // another entry represents this site
-  if (o != kEmpty && !(o & 1)) {  // an owned BS site
-    store_bs_velocity<C>(vel, s, o >> 1, P, E);
-    flag[s] = kSiteBS;
-  } else {
-    flag[s] = kSiteBall;
-  }
+  // every entry at s writes the same flag, from the owner map
+  flag[s] = o != kEmpty && !(o & 1) ? kSiteBS : kSiteBall;
+  if (o == 2 * e) store_bs_velocity<C>(vel, s, e, P, E);  // the owner's record
 }
 
 // The same per particle (one workgroup each), with the owner map and the
 // densities of a window around the ball staged in LDS: row-coalesced loads
 // instead of scattered lookups.  Half-width hw = floor(r + 1/2) + 1.
 template <int Q, typename T>
-__global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __restrict__ own, const int* __restrict__ ball,
+__global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __restrict__ own,
                                                         uint8_t* __restrict__ flag, typename Store<T>::C* __restrict__ vel,
                                                         const typename Store<T>::C* __restrict__ drho,
                                                         T* __restrict__ S, DevParticles P, DevEntries E, Boxes BX,
@@ -1168,17 +1159,11 @@ __global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __re
   const bool jump = P.jump[p] != 0;
   constexpr int kEnt = 4;
   for (int tb = 0; tb < ne; tb += kPrepareBlock * kEnt) {
-    int rep[kEnt], pkv[kEnt];
+    int pkv[kEnt];
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
       const int t = tb + j * kPrepareBlock + tid;
-      rep[j] = -1;
-      if (t < ne) {
-        pkv[j] = E.off[e0 + t];
-        const int x = wrap1(ox0 + off_x(pkv[j]), G.nx), y = wrap1(oy0 + off_y(pkv[j]), G.ny),
-                  z = wrap1(oz0 + off_z(pkv[j]), G.nz);
-        rep[j] = ball[site_of(G, x, y, z)];
-      }
+      if (t < ne) pkv[j] = E.off[e0 + t];
     }
 #pragma unroll 1
     for (int j = 0; j < kEnt; j++) {
@@ -1202,20 +1187,15 @@ __global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __re
         impose_is<Q, T>(S, BX.PS, lay, G, sxx, syy, szz, dr, (C)((double)ox - phx), (C)((double)oy - phy), (C)((double)oz - phz), cupx,
                         cupy, cupz, cwx, cwy, cwz, rho0);
       }
-      if (rep[j] != e) continue;  // another entry represents this site
+      // every entry at s writes the same flag, from the owner map
+      flag[s] = o != kEmpty && !(o & 1) ? kSiteBS : kSiteBall;
       if (o == 2 * e) {
-        // owned by this entry: the particle's velocities are at hand
+        // the owner's record: its particle's velocities are at hand
         const double rx = (double)ox - phx, ry = (double)oy - phy, rz = (double)oz - phz;
         vel[4 * (size_t)s] = (C)(upx + (wy * rz - wz * ry));
         vel[4 * (size_t)s + 1] = (C)(upy + (wz * rx - wx * rz));
         vel[4 * (size_t)s + 2] = (C)(upz + (wx * ry - wy * rx));
         vel[4 * (size_t)s + 3] = idx_as<C>(e);
-        flag[s] = kSiteBS;
-      } else if (o != kEmpty && !(o & 1)) {
-        store_bs_velocity<C>(vel, s, o >> 1, P, E);
-        flag[s] = kSiteBS;
-      } else {
-        flag[s] = kSiteBall;
       }
     }
   }
@@ -1290,7 +1270,7 @@ inline unsigned blocks_for(int64_t n, int per = 256) { return (unsigned)((n + pe
 // Workspace layout
 // ---------------------------------------------------------------------------
 struct Layout {
-  size_t f[2], drho, own, ball, flag, status, stage;
+  size_t f[2], drho, own, flag, status, stage;
   size_t x, x0, u, om, phi, fext, dP, dL, F, T, m, I, rad, b0, k, org, ent0, nbs, nis, nin, jump, box, cand_n, cand,
       pairs;
   size_t off, pid, slot, vel;
@@ -1354,7 +1334,6 @@ Layout make_layout(const lbm_params& p, const BoxSet& bs) {
   L.f[1] = p.aa ? L.f[0] : take(fb);  // the AA pattern updates one array in place
   L.drho = take((size_t)N * (p.storage == LBM_FP64 ? 8 : 4));
   L.own = take(sizeof(int) * N);
-  L.ball = take(sizeof(int) * N);
   L.flag = take(N);
   L.status = take(64);
   // moments staging of field read-outs (two arrays stage in the idle one)
@@ -1480,7 +1459,6 @@ struct lbm_ctx {
   double* slot;
   void* vel;
   int* own;   // owner map: lowest BS/IS entry per site
-  int* ball;  // ball map: representative entry of any kind per site
   uint8_t* flag;  // [site]: 0, kSiteBall or kSiteBS
   int* status;
   DevParticles P;
@@ -1535,11 +1513,11 @@ int launch_prepare(lbm_ctx* c, int pending) {
   using C = typename Store<T>::C;
   if (c->lds_window > 0) {
     k_prepare_local<Q, T><<<c->np, kPrepareBlock, c->lds_window, c->stream>>>(
-        c->own, c->ball, c->flag, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
+        c->own, c->flag, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
         c->prm.rho0, pending, c->dim, state_layout(c));
   } else {
     k_prepare<Q, T><<<blocks_for(c->nent), 256, 0, c->stream>>>(
-        c->own, c->ball, c->flag, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
+        c->own, c->flag, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
         (int)c->nent, c->prm.rho0, pending, state_layout(c));
   }
   HIP_TRY(hipGetLastError());
@@ -1667,7 +1645,7 @@ int launch_step(lbm_ctx* c) {
   if (c->np > 0) {
     const Boxes bx = boxes_arg(c);
     const double margin = c->closure ? std::max(kMargin, c->clo_h) : kMargin;
-    k_reduce<<<c->np, kBoundaryBlock, 0, c->stream>>>(c->own, c->ball, c->flag, c->slot, c->P, c->E, bx, c->prm.rho0,
+    k_reduce<<<c->np, kBoundaryBlock, 0, c->stream>>>(c->own, c->flag, c->slot, c->P, c->E, bx, c->prm.rho0,
                                                       margin, c->status);
     if (c->closure)
       k_closure<<<1, 256, 0, c->stream>>>(c->P, c->np, bx, c->d_clo, c->clo_h,
@@ -1676,7 +1654,7 @@ int launch_step(lbm_ctx* c) {
       k_particles<kParticleBlock><<<1, kParticleBlock, 0, c->stream>>>(c->P, c->dim, bx, c->status);
     else
       k_particles<kBoxParticleBlock><<<c->nbox, kBoxParticleBlock, 0, c->stream>>>(c->P, c->dim, bx, c->status);
-    k_stamp_particles<<<c->np, 256, 0, c->stream>>>(c->own, c->ball, c->P, c->E, bx);
+    k_stamp_particles<<<c->np, 256, 0, c->stream>>>(c->own, c->P, c->E, bx);
     HIP_TRY(hipGetLastError());
   }
   c->cur = 1 - c->cur;  // f[cur] now holds this step's post-collision state
@@ -1879,7 +1857,6 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
   c->slot = (double*)(c->ws + L.slot);
   c->vel = c->ws + L.vel;
   c->own = (int*)(c->ws + L.own);
-  c->ball = (int*)(c->ws + L.ball);
   c->flag = (uint8_t*)(c->ws + L.flag);
   c->status = (int*)(c->ws + L.status);
   c->d_boxes = (Geo*)(c->ws + L.boxes);
@@ -1941,7 +1918,6 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
   const int64_t nwords = (int64_t)(fbytes / 4);
   k_fill<uint32_t><<<blocks_for(nwords), 256, 0, c->stream>>>((uint32_t*)c->f[0], nwords, 0u);
   k_fill<int><<<blocks_for(c->NT), 256, 0, c->stream>>>(c->own, c->NT, kEmpty);
-  k_fill<int><<<blocks_for(c->NT), 256, 0, c->stream>>>(c->ball, c->NT, kEmpty);
   k_fill<uint8_t><<<blocks_for(c->NT), 256, 0, c->stream>>>(c->flag, c->NT, (uint8_t)0);
   k_fill<int><<<1, 256, 0, c->stream>>>(c->status, 16, 0);
   if (hipGetLastError() != hipSuccess || upload_boxes(c) != LBM_OK ||
@@ -2094,7 +2070,7 @@ static int add_impl(lbm_ctx* c, int32_t bx, int32_t n, const double* x, const do
   const int64_t e0 = c->nent, e1 = c->nent + (int64_t)hoff.size();
   for (int b = bx; b < c->nbox; b++) c->boxes[b].p1 = c->np + n;  // later boxes are still empty
   c->G = c->boxes[0];
-  k_stamp<<<blocks_for(e1 - e0), 256, 0, c->stream>>>(c->own, c->ball, c->P, c->E, boxes_arg(c), (int)e0, (int)e1);
+  k_stamp<<<blocks_for(e1 - e0), 256, 0, c->stream>>>(c->own, c->P, c->E, boxes_arg(c), (int)e0, (int)e1);
   HIP_TRY(hipGetLastError());
   c->nent = e1;
   c->np += n;
