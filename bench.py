@@ -217,7 +217,7 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the slab decomposition across GPUs is a design, not code)", file=sys.stderr)
         sys.exit(2)
 

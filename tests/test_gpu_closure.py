@@ -1,6 +1,7 @@
 """The near-contact closure in the GPU step against the oracle, and what the
 trained closure gains over the plain method, with the 4x refined plain method
-as the judge (the data, the training and the closure all run on the GPU)."""
+as the measure of error (the data, the training and the closure all run on
+the GPU)."""
 import numpy as np
 import pytest
 
@@ -82,7 +83,7 @@ def test_closure_parity_with_oracle(kinematic):
 
 
 def test_closure_gain_over_the_plain_method():
-    """Train on 128 cases, judge on 16 held-out cases: the working lattice
+    """Train on 128 cases, evaluate on 16 held-out cases: the working lattice
     with the closure in the step reports pair forces closer to the refined
     lattice's than the plain working lattice does (normal component, gaps
     below 2).  Measured raw and smoothed over 24 working steps: the smoothed
