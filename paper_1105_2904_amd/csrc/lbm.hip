@@ -58,6 +58,7 @@ constexpr int kSweepBlock = 256;
 constexpr int kTileMax = 512;        // widest tile of the ensemble sweep
 constexpr int kBoundaryBlock = 256;  // reduce workgroup
 constexpr int kPrepareBlock = 256;   // workgroup of the per-particle prepare
+constexpr int kPrepareLocalMax = 8192;  // bound on one ball's entries for the per-particle prepare
 constexpr int kParticleBlock = 1024;   // particle update of a one-box context
 constexpr int kBoxParticleBlock = 256; // particle update, per box of an ensemble
 constexpr int kStatusCollision = 1;
@@ -1090,6 +1091,7 @@ __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own,
     double dr;
     if (P.jump[p]) {
       dr = 0;
+#pragma unroll
       for (int j = 0; j < Q; j++) dr += (double)pop_ld<Q, T>(S + coll_index<Q>(lay, j, G, x, y, z, BX.PS), j);
     } else {
       dr = (double)drho[s];
@@ -1104,53 +1106,21 @@ __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own,
   if (o == 2 * e) store_bs_velocity<C>(vel, s, e, P, E);  // the owner's record
 }
 
-// The same per particle (one workgroup each), with the owner map and the
-// densities of a window around the ball staged in LDS: row-coalesced loads
-// instead of scattered lookups.  Half-width hw = floor(r + 1/2) + 1.
+// The same per particle (one workgroup each): the particle's box, origin and
+// velocities are uniform loads, and its entries, in raster order, give
+// row-coalesced loads of the owner map and of the densities at their own
+// sites (four entries per thread in flight at once).
 template <int Q, typename T>
 __global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __restrict__ own,
                                                         uint8_t* __restrict__ flag, typename Store<T>::C* __restrict__ vel,
                                                         const typename Store<T>::C* __restrict__ drho,
                                                         T* __restrict__ S, DevParticles P, DevEntries E, Boxes BX,
-                                                        double rho0, int pending, int dim, int lay) {
+                                                        double rho0, int pending, int lay) {
   using C = typename Store<T>::C;
-  extern __shared__ __align__(16) unsigned char smem[];
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
   const Geo G = geo_of(BX, P, p);
-  const int hw = (int)floor(P.rad[p] + 0.5) + 1;
-  const int W = 2 * hw + 1, Wz = dim == 3 ? W : 1, hz = dim == 3 ? hw : 0;
-  const int nW = W * W * Wz;
-  int* s_own = (int*)smem;
-  C* s_drho = (C*)(smem + ((sizeof(int) * nW + 15) / 16) * 16);
   const int ox0 = P.org[3 * p], oy0 = P.org[3 * p + 1], oz0 = P.org[3 * p + 2];
-  // window loads issued in batches of kBatch per thread so that their
-  // latencies overlap
-  constexpr int kBatch = 8;
-  for (int base = 0; base < nW; base += kPrepareBlock * kBatch) {
-    int vo[kBatch];
-    C vd[kBatch];
-#pragma unroll
-    for (int j = 0; j < kBatch; j++) {
-      const int idx = base + j * kPrepareBlock + tid;
-      if (idx < nW) {
-        const int wx = idx % W, wy = (idx / W) % W, wz = idx / (W * W);
-        const int x = wrap1(ox0 + wx - hw, G.nx), y = wrap1(oy0 + wy - hw, G.ny), z = wrap1(oz0 + wz - hz, G.nz);
-        const int site = site_of(G, x, y, z);
-        vo[j] = own[site];
-        vd[j] = pending ? drho[site] : C(0);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < kBatch; j++) {
-      const int idx = base + j * kPrepareBlock + tid;
-      if (idx < nW) {
-        s_own[idx] = vo[j];
-        s_drho[idx] = vd[j];
-      }
-    }
-  }
-  __syncthreads();
   const double phx = P.phi[3 * p], phy = P.phi[3 * p + 1], phz = P.phi[3 * p + 2];
   const double upx = P.u[3 * p], upy = P.u[3 * p + 1], upz = P.u[3 * p + 2];
   const double wx = P.om[3 * p], wy = P.om[3 * p + 1], wz = P.om[3 * p + 2];
@@ -1159,11 +1129,23 @@ __global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __re
   const bool jump = P.jump[p] != 0;
   constexpr int kEnt = 4;
   for (int tb = 0; tb < ne; tb += kPrepareBlock * kEnt) {
-    int pkv[kEnt];
+    int pkv[kEnt], sv[kEnt], ov[kEnt];
+    C dv[kEnt];
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
       const int t = tb + j * kPrepareBlock + tid;
       if (t < ne) pkv[j] = E.off[e0 + t];
+    }
+#pragma unroll
+    for (int j = 0; j < kEnt; j++) {
+      const int t = tb + j * kPrepareBlock + tid;
+      if (t < ne) {
+        const int pk = pkv[j];
+        sv[j] = site_of(G, wrap1(ox0 + off_x(pk), G.nx), wrap1(oy0 + off_y(pk), G.ny), wrap1(oz0 + off_z(pk), G.nz));
+        ov[j] = own[sv[j]];
+        // the density is only used at an IS site the substep claims
+        dv[j] = pending && !jump && entry_kind(pk) == 2 ? drho[sv[j]] : C(0);
+      }
     }
 #pragma unroll 1
     for (int j = 0; j < kEnt; j++) {
@@ -1172,17 +1154,17 @@ __global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __re
       const int e = e0 + t;
       const int pk = pkv[j];
       const int ox = off_x(pk), oy = off_y(pk), oz = off_z(pk);
-      const int sxx = wrap1(ox0 + ox, G.nx), syy = wrap1(oy0 + oy, G.ny), szz = wrap1(oz0 + oz, G.nz);
-      const int s = site_of(G, sxx, syy, szz);
-      const int w = (ox + hw) + W * ((oy + hw) + W * (oz + hz));
-      const int o = s_own[w];
+      const int s = sv[j];
+      const int o = ov[j];
       if (pending && o == 2 * e + 1) {
+        const int sxx = wrap1(ox0 + ox, G.nx), syy = wrap1(oy0 + oy, G.ny), szz = wrap1(oz0 + oz, G.nz);
         double dr;
         if (jump) {
           dr = 0;
+#pragma unroll
           for (int k = 0; k < Q; k++) dr += (double)pop_ld<Q, T>(S + coll_index<Q>(lay, k, G, sxx, syy, szz, BX.PS), k);
         } else {
-          dr = (double)s_drho[w];
+          dr = (double)dv[j];
         }
         impose_is<Q, T>(S, BX.PS, lay, G, sxx, syy, szz, dr, (C)((double)ox - phx), (C)((double)oy - phy), (C)((double)oz - phz), cupx,
                         cupy, cupz, cwx, cwy, cwz, rho0);
@@ -1467,7 +1449,7 @@ struct lbm_ctx {
   int64_t nent;
   std::vector<double> h_x0, h_rad, h_m, h_I, h_fext;
   std::vector<int> h_off, h_pid, h_nbs, h_nis, h_nin;
-  size_t lds_window;  // LDS bytes of the per-particle record window (0: not used)
+  bool prep_local;    // prepare with one workgroup per particle (else one thread per entry)
   bool prof;
   std::vector<hipEvent_t> ev;
   size_t ev_used;
@@ -1505,16 +1487,16 @@ Boxes boxes_arg(const lbm_ctx* c) {
 }
 
 // The IS substep of the step that just ran (pending = 1) and the records of
-// every ball site for the next sweep.  Per-particle LDS windows when they fit,
-// one thread per entry otherwise.
+// every ball site for the next sweep.  One workgroup per particle for balls of
+// moderate size, one thread per entry otherwise.
 template <int Q, typename T>
 int launch_prepare(lbm_ctx* c, int pending) {
   if (c->nent == 0) return LBM_OK;
   using C = typename Store<T>::C;
-  if (c->lds_window > 0) {
-    k_prepare_local<Q, T><<<c->np, kPrepareBlock, c->lds_window, c->stream>>>(
+  if (c->prep_local) {
+    k_prepare_local<Q, T><<<c->np, kPrepareBlock, 0, c->stream>>>(
         c->own, c->flag, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
-        c->prm.rho0, pending, c->dim, state_layout(c));
+        c->prm.rho0, pending, state_layout(c));
   } else {
     k_prepare<Q, T><<<blocks_for(c->nent), 256, 0, c->stream>>>(
         c->own, c->flag, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
@@ -1907,11 +1889,11 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
   c->prof = false;
   c->ev_used = 0;
   {
-    // window of the largest particle: (2 hw + 1)^d sites, hw = floor(r + 1/2) + 1
-    const int64_t W = 2 * ((int64_t)std::floor(prm->max_radius + 0.5) + 1) + 1;
-    const int64_t nW = c->dim == 3 ? W * W * W : W * W;
-    const size_t bytes = (size_t)((4 * nW + 15) / 16 * 16) + (size_t)nW * (prm->storage == LBM_FP64 ? 8 : 4);
-    c->lds_window = bytes <= 65536 ? bytes : 0;
+    // one workgroup per particle while the largest ball's bounding box, (2 floor(r + 1/2)
+    // + 1)^d sites and so a bound on its entries, stays within kPrepareLocalMax; larger
+    // balls spread their entries over the grid
+    const int64_t W = 2 * (int64_t)std::floor(prm->max_radius + 0.5) + 1;
+    c->prep_local = (c->dim == 3 ? W * W * W : W * W) <= kPrepareLocalMax;
   }
   // fluid at rest: every deviation zero; empty map; clear status
   const size_t fbytes = (size_t)c->q * c->PS * store_size(prm->storage);

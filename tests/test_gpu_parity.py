@@ -186,9 +186,9 @@ def test_suspension_3d(storage):
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])
 def test_large_sphere(storage):
-    """A sphere of radius 10 (its per-particle record window no longer fits in
-    LDS, so the records are built one thread per entry), sinking and
-    spinning next to a small one."""
+    """A sphere of radius 10 (its bounding box holds more sites than the
+    per-particle prepare takes, so the IS substep and the records are built
+    one thread per entry), sinking and spinning next to a small one."""
     box = (40, 36, 44)
     p = {"x": np.array([[20.3, 17.6, 22.1], [6.0, 5.5, 6.2]]), "u": np.array([[0.0, 0.004, -0.006], [0.0, 0.0, 0.0]]),
          "omega": np.array([[0.0, 0.0, 1e-3], [0.0, 0.0, 0.0]]), "radius": np.array([10.0, 3.0])}
