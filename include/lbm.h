@@ -89,7 +89,9 @@ typedef struct lbm_ctx lbm_ctx;
 
 typedef struct lbm_params {
   int32_t lattice;       /* LBM_D2Q9 or LBM_D3Q19 */
-  int32_t nx, ny, nz;    /* box size; nz = 1 for D2Q9; nx*ny*nz < 2^31 */
+  int32_t nx, ny, nz;    /* box size; nz = 1 for D2Q9; nx*ny*nz < 2^31, and one population
+                            plane (nx*ny*nz values of the storage type) at most 4 GiB:
+                            LBM_EINVAL otherwise (FP64 up to 2^29 sites, FP32 2^30) */
   double tau;            /* BGK relaxation time, > 1/2: nu = (tau - 1/2)/3 (eq. 4) */
   double rho0;           /* initial fluid density and deviation base (> 0) */
   double gravity[3];     /* acceleration on particles, lu/step^2 */
