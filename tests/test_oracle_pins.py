@@ -585,6 +585,75 @@ def test_hasimoto_periodic_array_drag():
 
 
 # ---------------------------------------------------------------------------
+# Stokes drag on a simple cubic array of fixed spheres (Hasimoto 1959):
+# F / (6 pi mu a U) = K(c) with 1/K = 1 - 1.7601 c^(1/3) + c - 1.5593 c^2,
+# c = 4 pi a^3 / (3 L^3), U the superficial velocity.
+# ---------------------------------------------------------------------------
+def _hasimoto_sc_K(c):
+    return 1.0 / (1.0 - 1.7601 * c ** (1.0 / 3.0) + c - 1.5593 * c * c)
+
+
+def _invert_radius_sc(F_over_muU, L):
+    """The radius a whose sphere in a simple cubic array of period L has
+    F / (mu U) = 6 pi a K(c(a)) (increasing in a over the dilute range)."""
+    lo, hi = 0.01 * L, 0.3 * L
+    for _ in range(200):
+        a = 0.5 * (lo + hi)
+        if 6 * np.pi * a * _hasimoto_sc_K(4 * np.pi * a ** 3 / (3 * L ** 3)) < F_over_muU:
+            lo = a
+        else:
+            hi = a
+    return 0.5 * (lo + hi)
+
+
+def test_hasimoto_simple_cubic_array_drag():
+    """The 3D coupling: a fixed sphere (kinematic, u = 0) in a periodic cube
+    driven by a uniform body force at Re ~ 0.02.  At steady state the momentum
+    the site conditions remove balances the injected N f_b (less the IS
+    leak); its ratio to mu U gives the effective radius a_h through
+    Hasimoto's simple cubic closed form, which must lie in [r - 1.5, r + 0.5],
+    with no drift proportional to r."""
+    tau = 1.5
+    nu = (tau - 0.5) / 3.0
+    shifts = []
+    for L, r in ((24, 3.0), (32, 4.0)):
+        fb = 2e-6
+        o = Oracle(19, L, L, L, tau, body_force=(fb, 0, 0))
+        o.add_particles([[L / 2, L / 2, L / 2]], radius=r, mass=np.inf, inertia=np.inf)
+        zz, yy, xx = np.mgrid[0:L, 0:L, 0:L]
+        injected = fb * L ** 3
+        # the mean flow approaches steady state with a time constant of about
+        # 1.2 L^2 steps: run 1.8 L^2, then extrapolate three samples 0.6 L^2
+        # apart to their limit (single-exponential, Aitken)
+        o.step(int(1.8 * L * L))
+        Us, bal, Fs = [], [], []
+        for _ in range(3):
+            o.step(int(0.6 * L * L))
+            rho, u, _ = o.fields()
+            kind = o.site_kind()
+            solid = ((xx - L / 2) ** 2 + (yy - L / 2) ** 2 + (zz - L / 2) ** 2 <= r * r) & (kind != 1)
+            Us.append((rho * u[..., 0])[~solid].sum() / L ** 3)
+            F, _, _, _, _ = o.forces()
+            leak = o.diagnostics()["is_leak"][0]
+            bal.append((F[0, 0] - leak) / injected)
+            Fs.append(F[0, 0] / injected)
+
+        def limit(v):
+            d1, d2 = v[1] - v[0], v[2] - v[1]
+            assert 0 < d2 / d1 < 0.9  # a decaying approach
+            return v[2] - d2 * d2 / (d2 - d1)
+
+        U_inf, bal_inf, F_inf = limit(Us), limit(bal), limit(Fs)
+        assert abs(bal_inf - 1.0) < 0.02  # the site conditions remove what the body force injects
+        a_h = _invert_radius_sc(injected / (nu * 1.0 * U_inf), L)
+        print("L %d r %.1f: U %.4e, balance %.4f, a_h %.3f, F/injected %.3f" % (L, r, U_inf, bal_inf, a_h, F_inf))
+        assert r - 1.5 <= a_h <= r + 0.5, (L, r, a_h)
+        shifts.append(a_h - r)
+        assert 0.5 < F_inf < 1.0
+    assert max(shifts) - min(shifts) < 0.5
+
+
+# ---------------------------------------------------------------------------
 # Numbers printed in the paper
 # ---------------------------------------------------------------------------
 def test_paper_numbers():
