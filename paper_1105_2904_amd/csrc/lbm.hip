@@ -9,8 +9,9 @@
 //              post-collision moments go to the owner entry's slot).
 //                                                          eq. 1-5, 12, 3 (left)
 //   reduce     one workgroup per particle: momentum dp and angular momentum dl
-//              of every owned BS site from its slot, deterministic
-//              wave-shuffle + LDS sums, release of the particle's stamps, and
+//              of every owned BS site from its slot (no owner-map lookup:
+//              unowned slots carry a mark), deterministic wave-shuffle + LDS
+//              sums, release of the particle's stamps, and
 //              the list of particles close enough to collide.         eq. 6-9
 //   particles  one workgroup per box: Newton-Euler update with buoyancy-
 //              corrected weight, hard-core collisions in lexicographic pair
@@ -25,7 +26,8 @@
 //              writes the same value, read off the owner map) and, by the
 //              owning entry, the record of every owned BS site: the
 //              rigid-body velocity u_p + omega x r of its next BS substep
-//              (eq. 5) and the owner entry.
+//              (eq. 5) and the owner entry; a BS entry whose site is held by
+//              another particle or a wall marks its slot unowned instead.
 // The IS substep of step t acts on the post-collision populations of IS sites
 // just before they propagate; written into the state, it is what the sweep of
 // step t+1 pulls.  Outside every ball the sweep reads one flag byte and
@@ -49,6 +51,9 @@
 namespace {
 
 constexpr int kEmpty = 0x7fffffff;  // map value of a site no entry claims
+// drho of the slot of a BS entry that does not own its site (another particle
+// or a wall holds it): the entry adds nothing to its particle's sums
+constexpr double kSlotUnowned = -0x1p1000;
 constexpr int64_t kMaxEntries = (int64_t)1 << 29;  // owner map stores 2e + 1 < kEmpty
 constexpr uint8_t kSiteBall = 1;  // site flag: some ball covers the site
 constexpr uint8_t kSiteBS = 2;    // site flag: an owned BS site (its record is valid)
@@ -591,25 +596,42 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int dim, Boxes
   const int L[3] = {G.nx, G.ny, G.nz};
   double vmax = 0;
   for (int p = p0 + tid; p < p1; p += NT) {
-    const double m = P.m[p], I = P.I[p];
-    double v2 = 0;
+    // every input is loaded before the first store: the particle arrays
+    // could alias as far as the compiler knows, and a load after a store
+    // would wait for it
+    const double m = P.m[p], I = P.I[p], rad = P.rad[p];
+    double dp[3], dl[3], fc[3], u[3], fe[3], om[3], x[3];
+#pragma unroll
     for (int a = 0; a < 3; a++) {
-      const double dp = P.dP[3 * p + a], dl = P.dL[3 * p + a], fc = P.fc[3 * p + a];
-      P.F[3 * p + a] = -dp + fc;
-      P.T[3 * p + a] = -dl;
-      double u = P.u[3 * p + a];
-      if (!isinf(m)) u = u + (P.fext[3 * p + a] - dp + fc) / m;
-      P.u[3 * p + a] = u;
-      if (!isinf(I)) P.om[3 * p + a] = P.om[3 * p + a] - dl / I;
-      v2 += u * u;
+      dp[a] = P.dP[3 * p + a];
+      dl[a] = P.dL[3 * p + a];
+      fc[a] = P.fc[3 * p + a];
+      u[a] = P.u[3 * p + a];
+      fe[a] = P.fext[3 * p + a];
+      om[a] = P.om[3 * p + a];
+      x[a] = P.x[3 * p + a];
+    }
+    double v2 = 0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      if (!isinf(m)) u[a] = u[a] + (fe[a] - dp[a] + fc[a]) / m;
+      if (!isinf(I)) om[a] = om[a] - dl[a] / I;
+      v2 += u[a] * u[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      P.F[3 * p + a] = -dp[a] + fc[a];
+      P.T[3 * p + a] = -dl[a];
+      P.u[3 * p + a] = u[a];
+      P.om[3 * p + a] = om[a];
       if (staged) {
-        s_x[a * kStageParticles + p - p0] = P.x[3 * p + a];
-        s_u[a * kStageParticles + p - p0] = u;
+        s_x[a * kStageParticles + p - p0] = x[a];
+        s_u[a * kStageParticles + p - p0] = u[a];
       }
     }
     if (staged) {
       s_m[p - p0] = m;
-      s_r[p - p0] = P.rad[p];
+      s_r[p - p0] = rad;
     }
     vmax = fmax(vmax, sqrt(v2));
   }
@@ -695,26 +717,36 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int dim, Boxes
     if (2.0 * vm >= kMargin) atomicOr(status, kStatusCollision);
   }
   for (int p = p0 + tid; p < p1; p += NT) {
-    double u[3];
-    for (int a = 0; a < 3; a++) u[a] = staged ? s_u[a * kStageParticles + p - p0] : P.u[3 * p + a];
-    if (G.walls && !isinf(P.m[p])) {
+    // inputs first, as above
+    const double m = P.m[p], r = P.rad[p];
+    double u[3], x[3], x0[3];
+    int k0[3], b0[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      u[a] = staged ? s_u[a * kStageParticles + p - p0] : P.u[3 * p + a];
+      x[a] = P.x[3 * p + a];
+      x0[a] = P.x0[3 * p + a];
+      k0[a] = P.k[3 * p + a];
+      b0[a] = P.b0[3 * p + a];
+    }
+    if (G.walls && !isinf(m)) {
       // contact with a wall after the pairs: the normal velocity reverses
       // when the predicted surface reaches the BS layer while approaching
       for (int a = 0; a < dim; a++) {
         if (!(G.walls & (1 << a))) continue;
-        const double xp = P.x[3 * p + a] + u[a], r = P.rad[p];
+        const double xp = x[a] + u[a];
         if ((xp - r <= 1.0 && u[a] < 0.0) || (xp + r >= (double)(L[a] - 2) && u[a] > 0.0)) u[a] = -u[a];
       }
     }
     int moved = 0;
     for (int a = 0; a < 3; a++) P.u[3 * p + a] = u[a];
     for (int a = 0; a < dim; a++) {
-      const double x = P.x[3 * p + a] + u[a];
-      P.x[3 * p + a] = x;
-      const int k = (int)floor(x - P.x0[3 * p + a] + 0.5);
-      moved += k != P.k[3 * p + a];
+      const double xn = x[a] + u[a];
+      P.x[3 * p + a] = xn;
+      const int k = (int)floor(xn - x0[a] + 0.5);
+      moved += k != k0[a];
       P.k[3 * p + a] = k;
-      P.org[3 * p + a] = wrap(P.b0[3 * p + a] + k, L[a]);
+      P.org[3 * p + a] = wrap(b0[a] + k, L[a]);
     }
     // a shift along all three axes at once (not a D3Q19 link) can take an IS
     // site outside the ball the sweep kept densities for
@@ -764,7 +796,7 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
   const int ne = nbs + nis + nin;
   constexpr int kEnt = 4;  // entries per thread whose loads are issued together
   for (int tb = 0; tb < ne; tb += kBoundaryBlock * kEnt) {
-    int pkv[kEnt], sv[kEnt], ov[kEnt];
+    int pkv[kEnt];
     double4 mv[kEnt];
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
@@ -772,10 +804,9 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
       if (t < ne) {
         const int e = e0 + t;
         pkv[j] = E.off[e];
-        sv[j] = entry_site(P, G, p, pkv[j]);
-        ov[j] = own[sv[j]];
-        // the slot is only meaningful for an owned BS site; read it anyway
-        mv[j] = entry_kind(pkv[j]) == 1 ? *(const double4*)(slot + 4 * (size_t)e) : make_double4(0, 0, 0, 0);
+        // every entry's slot, loaded beside its offset: only those of BS
+        // entries hold moments (or the unowned mark), the rest go unused
+        mv[j] = *(const double4*)(slot + 4 * (size_t)e);
       }
     }
 #pragma unroll
@@ -785,11 +816,12 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
       const int e = e0 + t;
       const int pk = pkv[j];
       const int kind = entry_kind(pk);
-      const int s = sv[j];
+      const int s = entry_site(P, G, p, pk);
       flag[s] = 0;
-      if (kind == 2 && ov[j] == 2 * e + 1) own[s] = kEmpty;
-      if (kind != 1 || ov[j] != 2 * e) continue;  // BS sites owned by this entry only
-      own[s] = kEmpty;                             // only the owner clears its site
+      // every claim at s is released this step, the owner's among them, so
+      // each BS/IS entry clears s without asking whose it is
+      if (kind != 3) own[s] = kEmpty;
+      if (kind != 1 || mv[j].x == kSlotUnowned) continue;  // BS sites owned by this entry only
       // dp = rho_B (u_B' - u_B), dl = r x dp with the post-collision moments
       const double rhoB = rho0 + mv[j].x;
       const double ubx = mv[j].y / rhoB, uby = mv[j].z / rhoB, ubz = mv[j].w / rhoB;
@@ -880,13 +912,25 @@ __global__ __launch_bounds__(256) void k_stamp_particles(int* __restrict__ own, 
   const Geo G = geo_of(BX, P, p);
   const int e0 = P.ent0[p], ne = P.nbs[p] + P.nis[p] + P.nin[p];
   const int ox = P.org[3 * p], oy = P.org[3 * p + 1], oz = P.org[3 * p + 2];
-  for (int t = threadIdx.x; t < ne; t += 256) {
-    const int e = e0 + t;
-    const int pk = E.off[e];
-    const int x = wrap1(ox + off_x(pk), G.nx), y = wrap1(oy + off_y(pk), G.ny), z = wrap1(oz + off_z(pk), G.nz);
-    const int s = site_of(G, x, y, z);
-    const int kind = entry_kind(pk);
-    if (kind != 3 && !wall_site(G, x, y, z)) atomicMin(&own[s], 2 * e + (kind == 2));
+  // the offsets of kEnt entries per thread are loaded before any of their
+  // atomics, which the compiler would otherwise keep in order with the loads
+  constexpr int kEnt = 4;
+  for (int tb = 0; tb < ne; tb += 256 * kEnt) {
+    int pkv[kEnt];
+#pragma unroll
+    for (int j = 0; j < kEnt; j++) {
+      const int t = tb + j * 256 + (int)threadIdx.x;
+      if (t < ne) pkv[j] = E.off[e0 + t];
+    }
+#pragma unroll
+    for (int j = 0; j < kEnt; j++) {
+      const int t = tb + j * 256 + (int)threadIdx.x;
+      if (t >= ne) continue;
+      const int pk = pkv[j];
+      const int x = wrap1(ox + off_x(pk), G.nx), y = wrap1(oy + off_y(pk), G.ny), z = wrap1(oz + off_z(pk), G.nz);
+      const int kind = entry_kind(pk);
+      if (kind != 3 && !wall_site(G, x, y, z)) atomicMin(&own[site_of(G, x, y, z)], 2 * (e0 + t) + (kind == 2));
+    }
   }
 }
 
@@ -1074,6 +1118,7 @@ __device__ __forceinline__ void store_bs_velocity(C* __restrict__ vel, int s, in
 template <int Q, typename T>
 __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own,
                                                   uint8_t* __restrict__ flag, typename Store<T>::C* __restrict__ vel,
+                                                  double* __restrict__ slot,
                                                   const typename Store<T>::C* __restrict__ drho, T* __restrict__ S,
                                                   DevParticles P, DevEntries E, Boxes BX, int nent, double rho0,
                                                   int pending, int lay) {
@@ -1104,6 +1149,7 @@ __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own,
   // every entry at s writes the same flag, from the owner map
   flag[s] = o != kEmpty && !(o & 1) ? kSiteBS : kSiteBall;
   if (o == 2 * e) store_bs_velocity<C>(vel, s, e, P, E);  // the owner's record
+  else if (entry_kind(pk) == 1) slot[4 * (size_t)e] = kSlotUnowned;
 }
 
 // The same per particle (one workgroup each): the particle's box, origin and
@@ -1113,6 +1159,7 @@ __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own,
 template <int Q, typename T>
 __global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __restrict__ own,
                                                         uint8_t* __restrict__ flag, typename Store<T>::C* __restrict__ vel,
+                                                        double* __restrict__ slot,
                                                         const typename Store<T>::C* __restrict__ drho,
                                                         T* __restrict__ S, DevParticles P, DevEntries E, Boxes BX,
                                                         double rho0, int pending, int lay) {
@@ -1178,6 +1225,8 @@ __global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __re
         vel[4 * (size_t)s + 1] = (C)(upy + (wz * rx - wx * rz));
         vel[4 * (size_t)s + 2] = (C)(upz + (wx * ry - wy * rx));
         vel[4 * (size_t)s + 3] = idx_as<C>(e);
+      } else if (entry_kind(pk) == 1) {
+        slot[4 * (size_t)e] = kSlotUnowned;  // a BS entry whose site another particle or a wall holds
       }
     }
   }
@@ -1495,11 +1544,11 @@ int launch_prepare(lbm_ctx* c, int pending) {
   using C = typename Store<T>::C;
   if (c->prep_local) {
     k_prepare_local<Q, T><<<c->np, kPrepareBlock, 0, c->stream>>>(
-        c->own, c->flag, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
+        c->own, c->flag, (C*)c->vel, c->slot, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
         c->prm.rho0, pending, state_layout(c));
   } else {
     k_prepare<Q, T><<<blocks_for(c->nent), 256, 0, c->stream>>>(
-        c->own, c->flag, (C*)c->vel, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
+        c->own, c->flag, (C*)c->vel, c->slot, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
         (int)c->nent, c->prm.rho0, pending, state_layout(c));
   }
   HIP_TRY(hipGetLastError());
