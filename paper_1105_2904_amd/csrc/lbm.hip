@@ -774,6 +774,9 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
   const double phx = P.phi[3 * p], phy = P.phi[3 * p + 1], phz = P.phi[3 * p + 2];
   const double upx = P.u[3 * p], upy = P.u[3 * p + 1], upz = P.u[3 * p + 2];
   const double wx = P.om[3 * p], wy = P.om[3 * p + 1], wz = P.om[3 * p + 2];
+  // the wrapped origin, loaded once (a load inside the entry loop would wait
+  // for the map stores before it, which the compiler cannot prove distinct)
+  const int ox0 = P.org[3 * p], oy0 = P.org[3 * p + 1], oz0 = P.org[3 * p + 2];
 
   // Close neighbours j > p in the same box (positions before translation):
   // the first chunk's test is issued here, so that its loads overlap the
@@ -781,47 +784,49 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
   const double xpx = P.x[3 * p], xpy = P.x[3 * p + 1], xpz = P.x[3 * p + 2];
   const double rp = P.rad[p];
   const int np = G.p1;
-  auto is_close = [&](int j) {
-    if (j >= np) return false;
-    double dx = P.x[3 * j] - xpx, dy = P.x[3 * j + 1] - xpy, dz = P.x[3 * j + 2] - xpz;
+  auto close_to = [&](double xj, double yj, double zj, double rj) {
+    double dx = xj - xpx, dy = yj - xpy, dz = zj - xpz;
     dx -= G.nx * floor(dx / G.nx + 0.5);
     dy -= G.ny * floor(dy / G.ny + 0.5);
     if (G.nz > 1) dz -= G.nz * floor(dz / G.nz + 0.5);
-    const double lim = rp + P.rad[j] + margin;
+    const double lim = rp + rj + margin;
     return dx * dx + dy * dy + dz * dz <= lim * lim;
   };
-  const bool close_first = is_close(p + 1 + tid);
+  auto is_close = [&](int j) {
+    if (j >= np) return false;
+    return close_to(P.x[3 * j], P.x[3 * j + 1], P.x[3 * j + 2], P.rad[j]);
+  };
+  // the first chunk's positions, loaded without a branch (lanes past the box's
+  // last particle load this particle's own) and tested after the sums
+  const int j1 = p + 1 + tid;
+  const int jc = j1 < np ? j1 : p;
+  const double xj1 = P.x[3 * jc], yj1 = P.x[3 * jc + 1], zj1 = P.x[3 * jc + 2], rj1 = P.rad[jc];
 
   double acc[6] = {0, 0, 0, 0, 0, 0};
   const int ne = nbs + nis + nin;
   constexpr int kEnt = 4;  // entries per thread whose loads are issued together
   for (int tb = 0; tb < ne; tb += kBoundaryBlock * kEnt) {
+    // every entry's offset and slot, loaded together and without per-lane
+    // branches (lanes past the last entry load the last one again and drop
+    // it): only the slots of BS entries hold moments (or the unowned mark)
     int pkv[kEnt];
     double4 mv[kEnt];
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
-      const int t = tb + j * kBoundaryBlock + tid;
-      if (t < ne) {
-        const int e = e0 + t;
-        pkv[j] = E.off[e];
-        // every entry's slot, loaded beside its offset: only those of BS
-        // entries hold moments (or the unowned mark), the rest go unused
-        mv[j] = *(const double4*)(slot + 4 * (size_t)e);
-      }
+      if (tb + j * kBoundaryBlock >= ne) break;  // the same for the whole workgroup
+      const int e = e0 + min(tb + j * kBoundaryBlock + tid, ne - 1);
+      pkv[j] = E.off[e];
+      mv[j] = *(const double4*)(slot + 4 * (size_t)e);
     }
+    // the sums first, the stores after: a wait for a loaded value placed
+    // between two stores would also wait for the first store (the vector
+    // memory counter counts both)
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
+      if (tb + j * kBoundaryBlock >= ne) break;
       const int t = tb + j * kBoundaryBlock + tid;
-      if (t >= ne) continue;
-      const int e = e0 + t;
       const int pk = pkv[j];
-      const int kind = entry_kind(pk);
-      const int s = entry_site(P, G, p, pk);
-      flag[s] = 0;
-      // every claim at s is released this step, the owner's among them, so
-      // each BS/IS entry clears s without asking whose it is
-      if (kind != 3) own[s] = kEmpty;
-      if (kind != 1 || mv[j].x == kSlotUnowned) continue;  // BS sites owned by this entry only
+      if (t >= ne || entry_kind(pk) != 1 || mv[j].x == kSlotUnowned) continue;  // owned BS sites only
       // dp = rho_B (u_B' - u_B), dl = r x dp with the post-collision moments
       const double rhoB = rho0 + mv[j].x;
       const double ubx = mv[j].y / rhoB, uby = mv[j].z / rhoB, ubz = mv[j].w / rhoB;
@@ -836,6 +841,18 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
       acc[3] += ry * dpz - rz * dpy;
       acc[4] += rz * dpx - rx * dpz;
       acc[5] += rx * dpy - ry * dpx;
+    }
+#pragma unroll
+    for (int j = 0; j < kEnt; j++) {
+      if (tb + j * kBoundaryBlock >= ne) break;
+      const int t = tb + j * kBoundaryBlock + tid;
+      if (t >= ne) continue;
+      const int pk = pkv[j];
+      const int s = site_of(G, wrap1(ox0 + off_x(pk), G.nx), wrap1(oy0 + off_y(pk), G.ny), wrap1(oz0 + off_z(pk), G.nz));
+      flag[s] = 0;
+      // every claim at s is released this step, the owner's among them, so
+      // each BS/IS entry clears s without asking whose it is
+      if (entry_kind(pk) != 3) own[s] = kEmpty;
     }
   }
 #pragma unroll
@@ -860,7 +877,7 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
   int base = 0;
   for (int j0 = p + 1; j0 < np; j0 += kBoundaryBlock) {
     const int j = j0 + tid;
-    const bool close = j0 == p + 1 ? close_first : is_close(j);
+    const bool close = j0 == p + 1 ? j < np && close_to(xj1, yj1, zj1, rj1) : is_close(j);
     const unsigned long long bal = __ballot(close);
     if (lane == 0) s_cnt[wv] = __popcll(bal);
     __syncthreads();
@@ -919,17 +936,26 @@ __global__ __launch_bounds__(256) void k_stamp_particles(int* __restrict__ own, 
     int pkv[kEnt];
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
-      const int t = tb + j * 256 + (int)threadIdx.x;
-      if (t < ne) pkv[j] = E.off[e0 + t];
+      if (tb + j * 256 >= ne) break;  // the same for the whole workgroup
+      pkv[j] = E.off[e0 + min(tb + j * 256 + (int)threadIdx.x, ne - 1)];
     }
+    // every site and code first, the atomics after, back to back (a wait for
+    // an offset between two atomics would also wait for the first atomic)
+    int sv[kEnt], cv[kEnt];
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
+      if (tb + j * 256 >= ne) break;
       const int t = tb + j * 256 + (int)threadIdx.x;
-      if (t >= ne) continue;
       const int pk = pkv[j];
       const int x = wrap1(ox + off_x(pk), G.nx), y = wrap1(oy + off_y(pk), G.ny), z = wrap1(oz + off_z(pk), G.nz);
       const int kind = entry_kind(pk);
-      if (kind != 3 && !wall_site(G, x, y, z)) atomicMin(&own[site_of(G, x, y, z)], 2 * (e0 + t) + (kind == 2));
+      sv[j] = site_of(G, x, y, z);
+      cv[j] = t < ne && kind != 3 && !wall_site(G, x, y, z) ? 2 * (e0 + t) + (kind == 2) : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < kEnt; j++) {
+      if (tb + j * 256 >= ne) break;
+      if (cv[j] >= 0) atomicMin(&own[sv[j]], cv[j]);
     }
   }
 }
@@ -1176,23 +1202,23 @@ __global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __re
   const bool jump = P.jump[p] != 0;
   constexpr int kEnt = 4;
   for (int tb = 0; tb < ne; tb += kPrepareBlock * kEnt) {
+    // loads without per-lane branches, so that all of them are in flight
+    // together: lanes past the last entry load the last entry again and drop
+    // it (a batch wholly past it is skipped by the whole workgroup)
     int pkv[kEnt], sv[kEnt], ov[kEnt];
     C dv[kEnt];
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
-      const int t = tb + j * kPrepareBlock + tid;
-      if (t < ne) pkv[j] = E.off[e0 + t];
+      if (tb + j * kPrepareBlock >= ne) break;  // the same for the whole workgroup
+      pkv[j] = E.off[e0 + min(tb + j * kPrepareBlock + tid, ne - 1)];
     }
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
-      const int t = tb + j * kPrepareBlock + tid;
-      if (t < ne) {
-        const int pk = pkv[j];
-        sv[j] = site_of(G, wrap1(ox0 + off_x(pk), G.nx), wrap1(oy0 + off_y(pk), G.ny), wrap1(oz0 + off_z(pk), G.nz));
-        ov[j] = own[sv[j]];
-        // the density is only used at an IS site the substep claims
-        dv[j] = pending && !jump && entry_kind(pk) == 2 ? drho[sv[j]] : C(0);
-      }
+      if (tb + j * kPrepareBlock >= ne) break;
+      const int pk = pkv[j];
+      sv[j] = site_of(G, wrap1(ox0 + off_x(pk), G.nx), wrap1(oy0 + off_y(pk), G.ny), wrap1(oz0 + off_z(pk), G.nz));
+      ov[j] = own[sv[j]];
+      dv[j] = drho[sv[j]];  // used only at an IS site the substep claims
     }
 #pragma unroll 1
     for (int j = 0; j < kEnt; j++) {
