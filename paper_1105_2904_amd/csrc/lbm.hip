@@ -1188,9 +1188,11 @@ __global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __re
                                                         double* __restrict__ slot,
                                                         const typename Store<T>::C* __restrict__ drho,
                                                         T* __restrict__ S, DevParticles P, DevEntries E, Boxes BX,
-                                                        double rho0, int pending, int lay) {
+                                                        double rho0, int pending, int lay, int split) {
   using C = typename Store<T>::C;
-  const int p = blockIdx.x;
+  // split workgroups per particle: rows of kPrepareBlock consecutive entries
+  // are dealt to them round-robin, kEnt rows per pass
+  const int p = blockIdx.x / split, part = blockIdx.x % split;
   const int tid = threadIdx.x;
   const Geo G = geo_of(BX, P, p);
   const int ox0 = P.org[3 * p], oy0 = P.org[3 * p + 1], oz0 = P.org[3 * p + 2];
@@ -1201,20 +1203,21 @@ __global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __re
   const int e0 = P.ent0[p], ne = P.nbs[p] + P.nis[p] + P.nin[p];
   const bool jump = P.jump[p] != 0;
   constexpr int kEnt = 4;
-  for (int tb = 0; tb < ne; tb += kPrepareBlock * kEnt) {
+  for (int rb = part; rb * kPrepareBlock < ne; rb += split * kEnt) {
     // loads without per-lane branches, so that all of them are in flight
     // together: lanes past the last entry load the last entry again and drop
-    // it (a batch wholly past it is skipped by the whole workgroup)
+    // it (a row wholly past it is skipped by the whole workgroup)
     int pkv[kEnt], sv[kEnt], ov[kEnt];
     C dv[kEnt];
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
-      if (tb + j * kPrepareBlock >= ne) break;  // the same for the whole workgroup
-      pkv[j] = E.off[e0 + min(tb + j * kPrepareBlock + tid, ne - 1)];
+      const int t0 = (rb + j * split) * kPrepareBlock;
+      if (t0 >= ne) break;  // the same for the whole workgroup
+      pkv[j] = E.off[e0 + min(t0 + tid, ne - 1)];
     }
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
-      if (tb + j * kPrepareBlock >= ne) break;
+      if ((rb + j * split) * kPrepareBlock >= ne) break;
       const int pk = pkv[j];
       sv[j] = site_of(G, wrap1(ox0 + off_x(pk), G.nx), wrap1(oy0 + off_y(pk), G.ny), wrap1(oz0 + off_z(pk), G.nz));
       ov[j] = own[sv[j]];
@@ -1222,7 +1225,7 @@ __global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __re
     }
 #pragma unroll 1
     for (int j = 0; j < kEnt; j++) {
-      const int t = tb + j * kPrepareBlock + tid;
+      const int t = (rb + j * split) * kPrepareBlock + tid;
       if (t >= ne) continue;
       const int e = e0 + t;
       const int pk = pkv[j];
@@ -1524,7 +1527,8 @@ struct lbm_ctx {
   int64_t nent;
   std::vector<double> h_x0, h_rad, h_m, h_I, h_fext;
   std::vector<int> h_off, h_pid, h_nbs, h_nis, h_nin;
-  bool prep_local;    // prepare with one workgroup per particle (else one thread per entry)
+  bool prep_local;    // prepare with workgroups per particle (else one thread per entry)
+  int prep_split;     // most workgroups per particle of the per-particle prepare
   bool prof;
   std::vector<hipEvent_t> ev;
   size_t ev_used;
@@ -1569,9 +1573,12 @@ int launch_prepare(lbm_ctx* c, int pending) {
   if (c->nent == 0) return LBM_OK;
   using C = typename Store<T>::C;
   if (c->prep_local) {
-    k_prepare_local<Q, T><<<c->np, kPrepareBlock, 0, c->stream>>>(
+    // split workgroups per particle only while the particles alone leave the
+    // GPU short of workgroups (about 8 per CU)
+    const int split = std::max(1, std::min(c->prep_split, 2048 / c->np));
+    k_prepare_local<Q, T><<<c->np * split, kPrepareBlock, 0, c->stream>>>(
         c->own, c->flag, (C*)c->vel, c->slot, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
-        c->prm.rho0, pending, state_layout(c));
+        c->prm.rho0, pending, state_layout(c), split);
   } else {
     k_prepare<Q, T><<<blocks_for(c->nent), 256, 0, c->stream>>>(
         c->own, c->flag, (C*)c->vel, c->slot, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
@@ -1969,6 +1976,11 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
     // balls spread their entries over the grid
     const int64_t W = 2 * (int64_t)std::floor(prm->max_radius + 0.5) + 1;
     c->prep_local = (c->dim == 3 ? W * W * W : W * W) <= kPrepareLocalMax;
+    // about one workgroup per kPrepareBlock entries of the largest ball (its
+    // volume), so that a particle's scattered IS stores spread over CUs
+    const double r = prm->max_radius;
+    const double vol = c->dim == 3 ? 4.0 / 3.0 * M_PI * r * r * r : M_PI * r * r;
+    c->prep_split = std::max(1, std::min(8, (int)std::ceil(vol / kPrepareBlock)));
   }
   // fluid at rest: every deviation zero; empty map; clear status
   const size_t fbytes = (size_t)c->q * c->PS * store_size(prm->storage);
