@@ -924,28 +924,29 @@ __global__ __launch_bounds__(256) void k_stamp(int* __restrict__ own, DevParticl
 // and entry range are uniform loads and its entries coalesced ones, so each
 // entry costs one dependent load before its stores (the per-step stamp).
 __global__ __launch_bounds__(256) void k_stamp_particles(int* __restrict__ own, DevParticles P, DevEntries E,
-                                                         Boxes BX) {
-  const int p = blockIdx.x;
+                                                         Boxes BX, int split) {
+  // split workgroups per particle, rows of 256 entries dealt round-robin
+  const int p = blockIdx.x / split, part = blockIdx.x % split;
   const Geo G = geo_of(BX, P, p);
   const int e0 = P.ent0[p], ne = P.nbs[p] + P.nis[p] + P.nin[p];
   const int ox = P.org[3 * p], oy = P.org[3 * p + 1], oz = P.org[3 * p + 2];
   // the offsets of kEnt entries per thread are loaded before any of their
   // atomics, which the compiler would otherwise keep in order with the loads
   constexpr int kEnt = 4;
-  for (int tb = 0; tb < ne; tb += 256 * kEnt) {
+  for (int rb = part; rb * 256 < ne; rb += split * kEnt) {
     int pkv[kEnt];
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
-      if (tb + j * 256 >= ne) break;  // the same for the whole workgroup
-      pkv[j] = E.off[e0 + min(tb + j * 256 + (int)threadIdx.x, ne - 1)];
+      if ((rb + j * split) * 256 >= ne) break;  // the same for the whole workgroup
+      pkv[j] = E.off[e0 + min((rb + j * split) * 256 + (int)threadIdx.x, ne - 1)];
     }
     // every site and code first, the atomics after, back to back (a wait for
     // an offset between two atomics would also wait for the first atomic)
     int sv[kEnt], cv[kEnt];
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
-      if (tb + j * 256 >= ne) break;
-      const int t = tb + j * 256 + (int)threadIdx.x;
+      if ((rb + j * split) * 256 >= ne) break;
+      const int t = (rb + j * split) * 256 + (int)threadIdx.x;
       const int pk = pkv[j];
       const int x = wrap1(ox + off_x(pk), G.nx), y = wrap1(oy + off_y(pk), G.ny), z = wrap1(oz + off_z(pk), G.nz);
       const int kind = entry_kind(pk);
@@ -954,7 +955,7 @@ __global__ __launch_bounds__(256) void k_stamp_particles(int* __restrict__ own, 
     }
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
-      if (tb + j * 256 >= ne) break;
+      if ((rb + j * split) * 256 >= ne) break;
       if (cv[j] >= 0) atomicMin(&own[sv[j]], cv[j]);
     }
   }
@@ -1575,7 +1576,7 @@ int launch_prepare(lbm_ctx* c, int pending) {
   if (c->prep_local) {
     // split workgroups per particle only while the particles alone leave the
     // GPU short of workgroups (about 8 per CU)
-    const int split = std::max(1, std::min(c->prep_split, 2048 / c->np));
+    const int split = std::max(1, std::min(c->prep_split, 2048 / std::max(c->np, 1)));
     k_prepare_local<Q, T><<<c->np * split, kPrepareBlock, 0, c->stream>>>(
         c->own, c->flag, (C*)c->vel, c->slot, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
         c->prm.rho0, pending, state_layout(c), split);
@@ -1718,7 +1719,8 @@ int launch_step(lbm_ctx* c) {
       k_particles<kParticleBlock><<<1, kParticleBlock, 0, c->stream>>>(c->P, c->dim, bx, c->status);
     else
       k_particles<kBoxParticleBlock><<<c->nbox, kBoxParticleBlock, 0, c->stream>>>(c->P, c->dim, bx, c->status);
-    k_stamp_particles<<<c->np, 256, 0, c->stream>>>(c->own, c->P, c->E, bx);
+    const int split = std::max(1, std::min(c->prep_split, 2048 / std::max(c->np, 1)));  // as for prepare
+    k_stamp_particles<<<c->np * split, 256, 0, c->stream>>>(c->own, c->P, c->E, bx, split);
     HIP_TRY(hipGetLastError());
   }
   c->cur = 1 - c->cur;  // f[cur] now holds this step's post-collision state
