@@ -227,12 +227,6 @@ __device__ __forceinline__ int site_of(const Geo& G, int x, int y, int z) {
   return (int)G.off + x + G.nx * (y + G.ny * z);
 }
 
-__device__ __forceinline__ int entry_site(const DevParticles& P, const Geo& G, int p, int pk) {
-  int x, y, z;
-  entry_xyz(P, G, p, pk, x, y, z);
-  return site_of(G, x, y, z);
-}
-
 // ---------------------------------------------------------------------------
 // Ball sites.  flag[s] is 0 outside every ball, kSiteBall inside one and
 // kSiteBS at an owned BS site; there the site's record vel[4s..4s+2] is the
