@@ -16,10 +16,11 @@
 //   particles  one workgroup per box: Newton-Euler update with buoyancy-
 //              corrected weight, hard-core collisions in lexicographic pair
 //              order, translation and integer shift.        eq. 10-11, 13, 16-19
-//   stamp      rebuild the owner map at the new shifts (lowest BS/IS entry
-//              index, hence lowest particle id; stored as 2e + [IS]).
+//   stamp      one to eight workgroups per particle: rebuild the owner map at
+//              the new shifts (lowest BS/IS entry index, hence lowest
+//              particle id; stored as 2e + [IS]).
 //                                                                    eq. 14-15
-//   prepare    one workgroup per particle: the IS substep at the new
+//   prepare    one to eight workgroups per particle: the IS substep at the new
 //              positions (eq. 12) written in place into the post-collision
 //              state -- f^eq_i(rho_I, u_p' + omega_p' x r) at every owned IS
 //              site -- the flag of every ball site (every entry at a site
@@ -1561,8 +1562,8 @@ Boxes boxes_arg(const lbm_ctx* c) {
 }
 
 // The IS substep of the step that just ran (pending = 1) and the records of
-// every ball site for the next sweep.  One workgroup per particle for balls of
-// moderate size, one thread per entry otherwise.
+// every ball site for the next sweep.  Up to eight workgroups per particle for
+// balls of moderate size, one thread per entry otherwise.
 template <int Q, typename T>
 int launch_prepare(lbm_ctx* c, int pending) {
   if (c->nent == 0) return LBM_OK;
