@@ -2136,8 +2136,10 @@ static int add_impl(lbm_ctx* c, int32_t bx, int32_t n, const double* x, const do
   const int64_t e0 = c->nent, e1 = c->nent + (int64_t)hoff.size();
   for (int b = bx; b < c->nbox; b++) c->boxes[b].p1 = c->np + n;  // later boxes are still empty
   c->G = c->boxes[0];
-  k_stamp<<<blocks_for(e1 - e0), 256, 0, c->stream>>>(c->own, c->P, c->E, boxes_arg(c), (int)e0, (int)e1);
-  HIP_TRY(hipGetLastError());
+  if (e1 > e0) {  // particles this small may hold no site at all
+    k_stamp<<<blocks_for(e1 - e0), 256, 0, c->stream>>>(c->own, c->P, c->E, boxes_arg(c), (int)e0, (int)e1);
+    HIP_TRY(hipGetLastError());
+  }
   c->nent = e1;
   c->np += n;
   // records of every ball site, with nothing pending (written into the state above)
