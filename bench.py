@@ -7,12 +7,15 @@ particle update, map rebuild, IS substep) over the box.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage fp32|fp64|fp16|bf16]
                   [--no-cpu-baseline] [--no-variants] [--no-autotune] [--workload spheres-3d|disks-2d]
+                  [--accuracy-steps N]
 
 The FP32 run also times the FP16 and BF16 storage variants of the same
-workload ("variants"), a 64-box D2Q9 ensemble stepped by one launch per
-kernel with a tuned sweep shape and step graphs against a loop of one-box
-contexts ("batched"), and the FP64 oracle on a few steps of the same box
-("cpu_baseline").
+workload ("variants") and, outside every timed region, runs the workload for
+--accuracy-steps steps in FP64, FP32, FP16 and BF16 to give each variant its
+drag and settling-velocity error against FP64 ("accuracy"); it times a 64-box
+D2Q9 ensemble stepped by one launch per kernel with a tuned sweep shape and
+step graphs against a loop of one-box contexts ("batched"), and the FP64
+oracle on a few steps of the same box ("cpu_baseline").
 """
 import argparse
 import json
@@ -86,6 +89,33 @@ def copy_ceiling(torch, lbm, stream, nbytes=2 << 30, reps=10):
     ms = e0.elapsed_time(e1) / reps
     del src, dst
     return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def storage_accuracy(lbm, cfg, steps):
+    """The same workload run for `steps` steps (outside any timed region) in
+    FP64, FP32, FP16 and BF16 storage: per-sphere drag and mean settling
+    velocity of each against the FP64 run, the GPU path that matches the
+    oracle to 1e-12 where the oracle can follow it."""
+    p = cfg["particles"]
+    res = {}
+    for st in ("fp64", "fp32", "fp16", "bf16"):
+        sim = lbm.Simulation(19, *cfg["box"], tau=cfg["tau"], gravity=cfg["gravity"], zero_net_force=True,
+                             storage=st, max_particles=len(p["radius"]), max_radius=float(np.max(p["radius"])))
+        sim.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
+        sim.set_graph(50)
+        sim.step(steps)
+        F, _, _, u, _ = sim.forces()
+        sim.close()
+        res[st] = (F, u[:, 2].mean())
+    F64, w64 = res["fp64"]
+    scale = float(np.linalg.norm(F64, axis=1).max())
+    out = {"reference": {"storage": "fp64", "steps": steps, "mean_settling_velocity": w64,
+                         "max_drag": scale}}
+    for st in ("fp32", "fp16", "bf16"):
+        F, w = res[st]
+        out[st] = {"drag_error_vs_fp64": float(np.linalg.norm(F - F64, axis=1).max() / scale),
+                   "settling_error_vs_fp64": float(abs(w - w64) / abs(w64)), "accuracy_steps": steps}
+    return out
 
 
 def cpu_baseline(cfg, steps):
@@ -216,6 +246,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip timing the 64-box D2Q9 ensemble (batched) variant")
     ap.add_argument("--batched-steps", type=int, default=200)
+    ap.add_argument("--accuracy-steps", type=int, default=2000,
+                    help="steps of the storage-accuracy leg (FP32/FP16/BF16 against FP64; 0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -358,6 +390,13 @@ def main():
                 out["variants"][name]["population_bytes"] = int(q * N * 4)
                 out["variants"][name]["population_bytes_two_arrays"] = int(2 * q * N * 4)
             print("variant %s timed" % name, file=sys.stderr, flush=True)
+        if args.accuracy_steps > 0 and args.workload == "spheres-3d" and args.particles:
+            acc = storage_accuracy(lbm, cfg, args.accuracy_steps)
+            out["accuracy"] = acc["reference"]
+            for name in ("fp16", "bf16"):
+                out["variants"][name].update(acc[name])
+            out["accuracy"]["fp32"] = acc["fp32"]
+            print("storage accuracy measured", file=sys.stderr, flush=True)
     if not args.no_batched and args.storage == "fp32" and args.workload == "spheres-3d":
         out["closure_mlp"] = closure_mlp_rates(torch, lbm)
         print("closure network timed", file=sys.stderr, flush=True)
