@@ -1096,9 +1096,15 @@ __device__ __forceinline__ size_t coll_index(int lay, int i, const Geo& G, int x
   return (size_t)(lay == kLayAASwap ? opposite<Q>(i) : i) * NT + site_of(G, x, y, z);
 }
 
+// Streaming store of one stored population value.
+__device__ __forceinline__ void nt_put(double* p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void nt_put(float* p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void nt_put(_Float16* p, _Float16 v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void nt_put(bf16s* p, bf16s v) { __builtin_nontemporal_store(v.v, (uint16_t*)p); }
+
 // IS values of site s (offset o of particle p with the particle's velocities
 // in the compute type; the value is stored in it).
-template <int Q, typename T>
+template <int Q, typename T, bool NTS>
 __device__ __forceinline__ void impose_is(T* __restrict__ S, int64_t NT, int lay, const Geo& G, int x, int y, int z,
                                           double dr, typename Store<T>::C rx,
                                           typename Store<T>::C ry, typename Store<T>::C rz,
@@ -1116,8 +1122,15 @@ __device__ __forceinline__ void impose_is(T* __restrict__ S, int64_t NT, int lay
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     const C cu = C(L::cx(i)) * vx + C(L::cy(i)) * vy + C(L::cz(i)) * vz;
-    S[coll_index<Q>(lay, i, G, x, y, z, NT)] =
-        pop_enc<Q, T>(i, (double)(C(L::w(i)) * (dc + rho * (C(3) * cu + C(4.5) * cu * cu - usq))));
+    const T v = pop_enc<Q, T>(i, (double)(C(L::w(i)) * (dc + rho * (C(3) * cu + C(4.5) * cu * cu - usq))));
+    T* const dst = S + coll_index<Q>(lay, i, G, x, y, z, NT);
+    // NTS (the AA pattern, whose next sweep reads and rewrites these lines in
+    // place): streaming stores keep the partly written lines out of the
+    // caches; with two arrays they only move the same cost from the sweep here
+    if constexpr (NTS)
+      nt_put(dst, v);
+    else
+      *dst = v;
   }
 }
 
@@ -1137,7 +1150,7 @@ __device__ __forceinline__ void store_bs_velocity(C* __restrict__ vel, int s, in
   vel[4 * (size_t)s + 3] = idx_as<C>(bs);
 }
 
-template <int Q, typename T>
+template <int Q, typename T, bool NTS>
 __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own,
                                                   uint8_t* __restrict__ flag, typename Store<T>::C* __restrict__ vel,
                                                   double* __restrict__ slot,
@@ -1163,7 +1176,7 @@ __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own,
     } else {
       dr = (double)drho[s];
     }
-    impose_is<Q, T>(S, BX.PS, lay, G, x, y, z, dr, (C)((double)off_x(pk) - P.phi[3 * p]),
+    impose_is<Q, T, NTS>(S, BX.PS, lay, G, x, y, z, dr, (C)((double)off_x(pk) - P.phi[3 * p]),
                     (C)((double)off_y(pk) - P.phi[3 * p + 1]),
                     (C)((double)off_z(pk) - P.phi[3 * p + 2]), (C)P.u[3 * p], (C)P.u[3 * p + 1], (C)P.u[3 * p + 2],
                     (C)P.om[3 * p], (C)P.om[3 * p + 1], (C)P.om[3 * p + 2], rho0);
@@ -1178,7 +1191,7 @@ __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own,
 // velocities are uniform loads, and its entries, in raster order, give
 // row-coalesced loads of the owner map and of the densities at their own
 // sites (four entries per thread in flight at once).
-template <int Q, typename T>
+template <int Q, typename T, bool NTS>
 __global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __restrict__ own,
                                                         uint8_t* __restrict__ flag, typename Store<T>::C* __restrict__ vel,
                                                         double* __restrict__ slot,
@@ -1238,7 +1251,7 @@ __global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __re
         } else {
           dr = (double)dv[j];
         }
-        impose_is<Q, T>(S, BX.PS, lay, G, sxx, syy, szz, dr, (C)((double)ox - phx), (C)((double)oy - phy), (C)((double)oz - phz), cupx,
+        impose_is<Q, T, NTS>(S, BX.PS, lay, G, sxx, syy, szz, dr, (C)((double)ox - phx), (C)((double)oy - phy), (C)((double)oz - phz), cupx,
                         cupy, cupz, cwx, cwy, cwz, rho0);
       }
       // every entry at s writes the same flag, from the owner map
@@ -1564,24 +1577,31 @@ Boxes boxes_arg(const lbm_ctx* c) {
 // The IS substep of the step that just ran (pending = 1) and the records of
 // every ball site for the next sweep.  Up to eight workgroups per particle for
 // balls of moderate size, one thread per entry otherwise.
-template <int Q, typename T>
-int launch_prepare(lbm_ctx* c, int pending) {
-  if (c->nent == 0) return LBM_OK;
+template <int Q, typename T, bool NTS>
+int launch_prepare_as(lbm_ctx* c, int pending) {
   using C = typename Store<T>::C;
   if (c->prep_local) {
     // split workgroups per particle only while the particles alone leave the
     // GPU short of workgroups (about 8 per CU)
     const int split = std::max(1, std::min(c->prep_split, 2048 / std::max(c->np, 1)));
-    k_prepare_local<Q, T><<<c->np * split, kPrepareBlock, 0, c->stream>>>(
+    k_prepare_local<Q, T, NTS><<<c->np * split, kPrepareBlock, 0, c->stream>>>(
         c->own, c->flag, (C*)c->vel, c->slot, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
         c->prm.rho0, pending, state_layout(c), split);
   } else {
-    k_prepare<Q, T><<<blocks_for(c->nent), 256, 0, c->stream>>>(
+    k_prepare<Q, T, NTS><<<blocks_for(c->nent), 256, 0, c->stream>>>(
         c->own, c->flag, (C*)c->vel, c->slot, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
         (int)c->nent, c->prm.rho0, pending, state_layout(c));
   }
   HIP_TRY(hipGetLastError());
   return LBM_OK;
+}
+
+template <int Q, typename T>
+int launch_prepare(lbm_ctx* c, int pending) {
+  if (c->nent == 0) return LBM_OK;
+  // streaming IS stores for the AA pattern only
+  return state_layout(c) == kLayAB ? launch_prepare_as<Q, T, false>(c, pending)
+                                   : launch_prepare_as<Q, T, true>(c, pending);
 }
 
 // Tile list {box, y, z, x0} of width w, box by box, rows in z, y order.
