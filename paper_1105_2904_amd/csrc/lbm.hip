@@ -62,7 +62,8 @@ constexpr int kCandMax = 64;        // close neighbours listed per particle
 constexpr double kMargin = 1.0;     // candidate search margin (lattice units)
 constexpr int kSweepBlock = 256;
 constexpr int kTileMax = 512;        // widest tile of the ensemble sweep
-constexpr int kBoundaryBlock = 256;  // reduce workgroup
+constexpr int kBoundaryBlock = 256;  // reduce workgroup (128 for balls of at most kSmallBall entries)
+constexpr int kSmallBall = 512;
 constexpr int kPrepareBlock = 256;   // workgroup of the per-particle prepare
 constexpr int kPrepareLocalMax = 8192;  // bound on one ball's entries for the per-particle prepare
 constexpr int kParticleBlock = 1024;   // particle update of a one-box context
@@ -754,11 +755,12 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int dim, Boxes
 // of the particle's stamps, and the list of particles close enough to collide
 // this step.  One workgroup per particle.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own,
+template <int NB>
+__global__ __launch_bounds__(NB) void k_reduce(int* __restrict__ own,
                                                             uint8_t* __restrict__ flag, const double* __restrict__ slot,
                                                             DevParticles P, DevEntries E, Boxes BX,
                                                             double rho0, double margin, int* status) {
-  constexpr int kWaves = kBoundaryBlock / 64;
+  constexpr int kWaves = NB / 64;
   __shared__ double s_part[kWaves][6];
   __shared__ int s_cnt[kWaves];
   const int p = blockIdx.x;
@@ -800,7 +802,7 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
   double acc[6] = {0, 0, 0, 0, 0, 0};
   const int ne = nbs + nis + nin;
   constexpr int kEnt = 4;  // entries per thread whose loads are issued together
-  for (int tb = 0; tb < ne; tb += kBoundaryBlock * kEnt) {
+  for (int tb = 0; tb < ne; tb += NB * kEnt) {
     // every entry's offset and slot, loaded together and without per-lane
     // branches (lanes past the last entry load the last one again and drop
     // it): only the slots of BS entries hold moments (or the unowned mark)
@@ -808,8 +810,8 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
     double4 mv[kEnt];
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
-      if (tb + j * kBoundaryBlock >= ne) break;  // the same for the whole workgroup
-      const int e = e0 + min(tb + j * kBoundaryBlock + tid, ne - 1);
+      if (tb + j * NB >= ne) break;  // the same for the whole workgroup
+      const int e = e0 + min(tb + j * NB + tid, ne - 1);
       pkv[j] = E.off[e];
       mv[j] = *(const double4*)(slot + 4 * (size_t)e);
     }
@@ -818,8 +820,8 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
     // memory counter counts both)
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
-      if (tb + j * kBoundaryBlock >= ne) break;
-      const int t = tb + j * kBoundaryBlock + tid;
+      if (tb + j * NB >= ne) break;
+      const int t = tb + j * NB + tid;
       const int pk = pkv[j];
       if (t >= ne || entry_kind(pk) != 1 || mv[j].x == kSlotUnowned) continue;  // owned BS sites only
       // dp = rho_B (u_B' - u_B), dl = r x dp with the post-collision moments
@@ -839,8 +841,8 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
     }
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
-      if (tb + j * kBoundaryBlock >= ne) break;
-      const int t = tb + j * kBoundaryBlock + tid;
+      if (tb + j * NB >= ne) break;
+      const int t = tb + j * NB + tid;
       if (t >= ne) continue;
       const int pk = pkv[j];
       const int s = site_of(G, wrap1(ox0 + off_x(pk), G.nx), wrap1(oy0 + off_y(pk), G.ny), wrap1(oz0 + off_z(pk), G.nz));
@@ -870,7 +872,7 @@ __global__ __launch_bounds__(kBoundaryBlock) void k_reduce(int* __restrict__ own
   // (checked in the particle update), and, with margin >= the closure's gap,
   // every pair the closure acts on.
   int base = 0;
-  for (int j0 = p + 1; j0 < np; j0 += kBoundaryBlock) {
+  for (int j0 = p + 1; j0 < np; j0 += NB) {
     const int j = j0 + tid;
     const bool close = j0 == p + 1 ? j < np && close_to(xj1, yj1, zj1, rj1) : is_close(j);
     const unsigned long long bal = __ballot(close);
@@ -1538,6 +1540,7 @@ struct lbm_ctx {
   std::vector<int> h_off, h_pid, h_nbs, h_nis, h_nin;
   bool prep_local;    // prepare with workgroups per particle (else one thread per entry)
   int prep_split;     // most workgroups per particle of the per-particle prepare
+  bool small_ball;    // the largest ball holds at most kSmallBall entries
   bool prof;
   std::vector<hipEvent_t> ev;
   size_t ev_used;
@@ -1725,8 +1728,14 @@ int launch_step(lbm_ctx* c) {
   if (c->np > 0) {
     const Boxes bx = boxes_arg(c);
     const double margin = c->closure ? std::max(kMargin, c->clo_h) : kMargin;
-    k_reduce<<<c->np, kBoundaryBlock, 0, c->stream>>>(c->own, c->flag, c->slot, c->P, c->E, bx, c->prm.rho0,
-                                                      margin, c->status);
+    // half-size workgroups for many small balls: two waves then hold every
+    // entry, and twice as many particles' workgroups fit the GPU at once
+    if (c->small_ball && c->np > 1024)
+      k_reduce<128><<<c->np, 128, 0, c->stream>>>(c->own, c->flag, c->slot, c->P, c->E, bx, c->prm.rho0, margin,
+                                                  c->status);
+    else
+      k_reduce<kBoundaryBlock><<<c->np, kBoundaryBlock, 0, c->stream>>>(c->own, c->flag, c->slot, c->P, c->E, bx,
+                                                                          c->prm.rho0, margin, c->status);
     if (c->closure)
       k_closure<<<1, 256, 0, c->stream>>>(c->P, c->np, bx, c->d_clo, c->clo_h,
                                           c->prm.rho0 * (c->prm.tau - 0.5) / 3.0, c->prm.tau, c->status);
@@ -1998,6 +2007,7 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
     const double r = prm->max_radius;
     const double vol = c->dim == 3 ? 4.0 / 3.0 * M_PI * r * r * r : M_PI * r * r;
     c->prep_split = std::max(1, std::min(8, (int)std::ceil(vol / kPrepareBlock)));
+    c->small_ball = vol <= kSmallBall;
   }
   // fluid at rest: every deviation zero; empty map; clear status
   const size_t fbytes = (size_t)c->q * c->PS * store_size(prm->storage);
