@@ -158,3 +158,16 @@ def test_closure_inputs_match_the_oracle_bit_for_bit():
         d -= np.array(L) * np.floor(d / np.array(L) + 0.5)
         ours = lbm.closure_inputs(xi, d, ri, rj, tau)[0]
         assert np.array_equal(ours, ref), (k, ours, ref)
+
+
+def test_bench_measures_one_gpu_only():
+    """bench.py refuses a multi-GPU run with a message and exit status 2,
+    before it touches a device (the library has one-GPU code only)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
