@@ -167,3 +167,33 @@ def test_capacity_without_particles():
         _check(sim, ora, "no particles", [0.0, 0.0])
     assert sim.forces()[0].shape == (0, 3)
     sim.close()
+
+
+def test_many_small_particles():
+    """1156 free disks of r = 2 on a jittered lattice: more than 1024 small
+    balls, the case in which the per-particle sums run in half-size
+    workgroups; forces, torques and populations against the oracle."""
+    rng = np.random.default_rng(29)
+    k, h = 34, 6.0
+    box = (204, 204, 1)
+    g = (np.arange(k) + 0.5) * h
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    n = k * k
+    x = np.zeros((n, 3))
+    x[:, 0] = X.ravel() + rng.uniform(-0.4, 0.4, n)
+    x[:, 1] = Y.ravel() + rng.uniform(-0.4, 0.4, n)
+    u = np.zeros((n, 3))
+    u[:, :2] = rng.uniform(-0.01, 0.01, (n, 2))
+    om = np.zeros((n, 3))
+    om[:, 2] = rng.uniform(-0.005, 0.005, n)
+    r = np.full(n, 2.0)
+    mass = 1.5 * np.pi * r ** 2
+    p = {"x": x, "u": u, "omega": om, "radius": r, "mass": mass, "inertia": 0.5 * mass * r ** 2}
+    sim, ora = _pair(9, box, 0.8, p, 2.0, gravity=(0, -1e-4, 0), zero_net_force=True)
+    scale = [0.0, 0.0]
+    for steps in (1, 2, 5):
+        sim.step(steps)
+        ora.step(steps)
+        e_f = _check(sim, ora, "%d small disks" % n, scale)
+        _say("%d small disks: e_f %.1e, max |F| %.2e" % (n, e_f, scale[0]))
+    sim.close()
