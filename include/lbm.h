@@ -128,7 +128,10 @@ int lbm_create(const lbm_params* prm, void* d_workspace, size_t bytes,
  * [0, n_axis); u, omega: initial velocities (NULL = 0); radius in
  * (0, max_radius]; mass, inertia > 0, or +INFINITY for a kinematic particle
  * whose velocity is imposed (forces are still reported).  The particle record
- * is that of section 2.2 (x_p, r_p, m_p, I_p, u_p, omega_p).  Rejects overlap
+ * is that of section 2.2 (x_p, r_p, m_p, I_p, u_p, omega_p).  A particle so
+ * small that no site lies within r of its centre (r < sqrt(d)/2 at the worst
+ * offset) has an empty site set: it moves under its weight and collisions
+ * but exchanges no momentum with the fluid.  Rejects overlap
  * with any particle (centre distance < r_i + r_j, minimum image) or with a
  * wall (x - r < 1 or x + r > n - 2 along a closed axis) as LBM_EOVERLAP.
  * Host arrays are read before the call returns. */
