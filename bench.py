@@ -47,6 +47,14 @@ def sweep_geometry(box, launch):
     return w, (g if 0 < g < nt else nt) * w
 
 
+def sweep_kernel(width, q, tname, particles, layout):
+    """Name of a one-box sweep kernel as the profiler lists it: the row kernel
+    (width 0) or the tile kernel with streaming loads."""
+    if width == 0:
+        return "k_sweep<%d,%s,%s,%s>" % (q, tname, "true" if particles else "false", layout)
+    return "k_sweep_tiles<%d,%s,%s,%s,true>" % (q, tname, "true" if particles else "false", layout)
+
+
 def measured_traffic(kernel, workload, box, launch):
     """HBM bytes per launch of `kernel` at this launch geometry from the
     committed FETCH_SIZE/WRITE_SIZE counter runs (copy-kernel calibrated), or
@@ -319,8 +327,7 @@ def main():
     if footprint <= MALL_BYTES * 3 // 4:
         cache_ceiling = copy_ceiling(torch, lbm, stream, nbytes=footprint // 32 * 16, reps=200)
     launch = dict(zip(("width", "grid", "blocks_per_cu"), sim.sweep_config()))
-    kernel = "%s<%d,%s,%s,0>" % ("k_sweep" if launch["width"] == 0 else "k_sweep_tiles", q, kname,
-                                  "true" if args.particles else "false")
+    kernel = sweep_kernel(launch["width"], q, kname, bool(args.particles), "0")
     traffic = None
     if args.particles == len(cfg["particles"]["radius"]):
         traffic = measured_traffic(kernel.replace(",", ", "), cfg["name"], cfg["box"], launch)
@@ -372,9 +379,8 @@ def main():
             vms, (vsw, vn) = timed(v, args.steps, args.warmup, True)
             vb = lbm.lbm_bytes_per_site(v.params)
             vl = dict(zip(("width", "grid", "blocks_per_cu"), v.sweep_config()))
-            vk = "%s<%d, %s, %s%s>" % ("k_sweep" if vl["width"] == 0 else "k_sweep_tiles", q,
-                                       {"fp16": "_Float16", "bf16": "bf16s", "fp32": "float"}[st],
-                                       "true" if args.particles else "false", ", 0" if not aa else ", 1/2")
+            vk = sweep_kernel(vl["width"], q, {"fp16": "_Float16", "bf16": "bf16s", "fp32": "float"}[st],
+                              bool(args.particles), "0" if not aa else "1/2").replace(",", ", ")
             vt = None
             if args.particles == len(cfg["particles"]["radius"]) and not aa:
                 vt = measured_traffic(vk, cfg["name"], cfg["box"], vl)

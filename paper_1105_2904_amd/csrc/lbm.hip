@@ -82,12 +82,14 @@ template <>
 struct Store<double> {
   using C = double;
   static __device__ __forceinline__ double ld(const double* p) { return *p; }
+  static __device__ __forceinline__ double ldnt(const double* p) { return __builtin_nontemporal_load(p); }
   static __device__ __forceinline__ void st(double* p, double v) { __builtin_nontemporal_store(v, p); }
 };
 template <>
 struct Store<float> {
   using C = float;
   static __device__ __forceinline__ float ld(const float* p) { return *p; }
+  static __device__ __forceinline__ float ldnt(const float* p) { return __builtin_nontemporal_load(p); }
   static __device__ __forceinline__ void st(float* p, float v) { __builtin_nontemporal_store(v, p); }
 };
 // Half precision: the stored number is g_i / (w_i 2^-10), i.e. the deviation
@@ -97,6 +99,7 @@ template <>
 struct Store<_Float16> {
   using C = float;
   static __device__ __forceinline__ float ld(const _Float16* p) { return (float)*p; }
+  static __device__ __forceinline__ float ldnt(const _Float16* p) { return (float)__builtin_nontemporal_load(p); }
   static __device__ __forceinline__ void st(_Float16* p, float v) { __builtin_nontemporal_store((_Float16)v, p); }
 };
 // bfloat16: the top half of an FP32 number, rounded to nearest even; stores
@@ -120,6 +123,9 @@ template <>
 struct Store<bf16s> {
   using C = float;
   static __device__ __forceinline__ float ld(const bf16s* p) { return bf16_bits_to_f32(p->v); }
+  static __device__ __forceinline__ float ldnt(const bf16s* p) {
+    return bf16_bits_to_f32(__builtin_nontemporal_load(&p->v));
+  }
   static __device__ __forceinline__ void st(bf16s* p, float v) {
     __builtin_nontemporal_store(f32_to_bf16_bits(v), (uint16_t*)p);
   }
@@ -340,8 +346,11 @@ __device__ __forceinline__ float recip(float v) { return __builtin_amdgcn_rcpf(v
 __device__ __forceinline__ double recip(double v) { return 1.0 / v; }
 
 // The work of one site (x, y, z) of a box of nx x ny x nz sites whose first
-// site is `off`; fbt holds 3 w_i c_i . f_b of that box.
-template <int Q, typename T, bool PART, int LAY>
+// site is `off`; fbt holds 3 w_i c_i . f_b of that box.  NTL: streaming
+// (non-temporal) population loads.  Each pulled value is read once, so on
+// long rows they only keep dead lines out of the caches; in an ensemble of
+// narrow boxes the lines shared by neighbouring tiles are worth keeping.
+template <int Q, typename T, bool PART, int LAY, bool NTL>
 __device__ __forceinline__ void sweep_site(const T* A, T* B, const SweepArgs<Q, typename Store<T>::C>& a,
                                            const SiteArgs<T>& sa, int x, int y, int z, int nx, int ny, int nz,
                                            int off, const typename Store<T>::C (&fbt)[Q]) {
@@ -372,7 +381,8 @@ __device__ __forceinline__ void sweep_site(const T* A, T* B, const SweepArgs<Q, 
     const int sy = LAY == kLayAAStream ? y : (L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y));
     const int sz = LAY == kLayAAStream ? z : (L::cz(i) > 0 ? zm : (L::cz(i) < 0 ? zp : z));
     const T* src = plane_at(A, LAY == kLayAASwap ? opposite<Q>(i) : i, a.N, off + sx + nx * (sy + ny * sz));
-    g[i] = kRaw ? Store<T>::ld(src) : pop_ld<Q, T>(src, i);
+    const C h = NTL ? Store<T>::ldnt(src) : Store<T>::ld(src);
+    g[i] = kRaw ? h : h * (C)pop_unit<T>(L::w(i));
   }
   C drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
@@ -469,13 +479,14 @@ __device__ __forceinline__ void sweep_site(const T* A, T* B, const SweepArgs<Q, 
   }
 }
 
-// One box: workgroup (bx, y, z) covers kSweepBlock sites of row (y, z).
+// One box: workgroup (bx, y, z) covers kSweepBlock sites of row (y, z), with
+// streaming loads.
 template <int Q, typename T, bool PART, int LAY>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* A, T* B, SweepArgs<Q, typename Store<T>::C> a,
                                                         SiteArgs<T> sa) {
   const int x = (int)blockIdx.x * kSweepBlock + (int)threadIdx.x;
   if (x >= a.nx) return;
-  sweep_site<Q, T, PART, LAY>(A, B, a, sa, x, (int)blockIdx.y, (int)blockIdx.z, a.nx, a.ny, a.nz, 0, a.fbt);
+  sweep_site<Q, T, PART, LAY, true>(A, B, a, sa, x, (int)blockIdx.y, (int)blockIdx.z, a.nx, a.ny, a.nz, 0, a.fbt);
 }
 
 // q = n / d for 0 <= n < 2^31, 1 <= d, from inv = 1/d rounded to FP64: the
@@ -495,7 +506,7 @@ __device__ __forceinline__ int div_exact(int n, int d, double inv) {
 // bit pairs {lo, hi, lo, hi} for the split of a box-local index into (x, y,
 // z).  A persistent grid walks the tile list (the workgroup width, grid size
 // and occupancy cap are the tunable launch shape).
-template <int Q, typename T, bool PART, int LAY>
+template <int Q, typename T, bool PART, int LAY, bool NTL>
 __global__ __launch_bounds__(kTileMax) void k_sweep_tiles(const T* A, T* B, SweepArgs<Q, typename Store<T>::C> a,
                                                            SiteArgs<T> sa,
                                                            const int4* __restrict__ tiles, int ntiles,
@@ -511,7 +522,7 @@ __global__ __launch_bounds__(kTileMax) void k_sweep_tiles(const T* A, T* B, Swee
     C fb[Q];
 #pragma unroll
     for (int i = 0; i < Q; i++) fb[i] = fbt_tab[tl.x * Q + i];
-    sweep_site<Q, T, PART, LAY>(A, B, a, sa, lin - yz * tg.x, yz - z * tg.y, z, tg.x, tg.y, tg.z, tg.w, fb);
+    sweep_site<Q, T, PART, LAY, NTL>(A, B, a, sa, lin - yz * tg.x, yz - z * tg.y, z, tg.x, tg.y, tg.z, tg.w, fb);
   }
 }
 
@@ -1688,12 +1699,20 @@ int launch_sweep_as(lbm_ctx* c, int w, int grid, int occ) {
   } else {
     const int64_t nt = c->ntiles;
     const unsigned g = (unsigned)(grid > 0 && grid < nt ? grid : nt);
-    if (c->np > 0)
-      k_sweep_tiles<Q, T, true, LAY><<<g, w, lds, c->stream>>>(A, B, a, sa, c->d_tiles, (int)nt,
-                                                                (const C*)c->d_fbt);
+    // streaming loads for one box, cached ones for an ensemble
+    const bool one = c->nbox == 1;
+    if (c->np > 0 && one)
+      k_sweep_tiles<Q, T, true, LAY, true><<<g, w, lds, c->stream>>>(A, B, a, sa, c->d_tiles, (int)nt,
+                                                                      (const C*)c->d_fbt);
+    else if (c->np > 0)
+      k_sweep_tiles<Q, T, true, LAY, false><<<g, w, lds, c->stream>>>(A, B, a, sa, c->d_tiles, (int)nt,
+                                                                       (const C*)c->d_fbt);
+    else if (one)
+      k_sweep_tiles<Q, T, false, LAY, true><<<g, w, lds, c->stream>>>(A, B, a, sa, c->d_tiles, (int)nt,
+                                                                       (const C*)c->d_fbt);
     else
-      k_sweep_tiles<Q, T, false, LAY><<<g, w, lds, c->stream>>>(A, B, a, sa, c->d_tiles, (int)nt,
-                                                                 (const C*)c->d_fbt);
+      k_sweep_tiles<Q, T, false, LAY, false><<<g, w, lds, c->stream>>>(A, B, a, sa, c->d_tiles, (int)nt,
+                                                                        (const C*)c->d_fbt);
   }
   HIP_TRY(hipGetLastError());
   return LBM_OK;
