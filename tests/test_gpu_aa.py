@@ -117,6 +117,35 @@ def test_aa_equals_two_arrays_ensemble_tiles():
     aa.close()
 
 
+@pytest.mark.parametrize("q,box,n", [(9, (64, 40, 1), 3), (9, (300, 24, 1), 4), (9, (549, 18, 1), 5),
+                                     (19, (261, 14, 12), 3)])
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "bf16"])
+def test_aa_equals_two_arrays_rows_across_waves_and_workgroups(q, box, n, storage):
+    """Rows of one wave, of several, and of a ragged number of 64-site waves
+    over two or three row-kernel workgroups, with the periodic seam inside
+    the last wave: every odd step's push along x must land at the right
+    neighbour."""
+    r = 3.0 if q == 19 else 4.0
+    p = wl.suspension(q, box, n, r, 1.3, seed=131 + box[0])
+    g = (0, -2e-4, 0)
+    ab, aa = _pair(q, box, storage, p, tau=0.7, gravity=g, zero_net_force=True)
+    rng = np.random.default_rng(box[0])
+    f = ab.get_distributions()
+    f = f * (1.0 + 2e-3 * rng.standard_normal(f.shape))
+    for s in (ab, aa):
+        s.set_sweep_config(0, 0, 0)  # the row kernel
+        s.set_distributions(f)
+    total = 0
+    for n_steps in (1, 2, 5):
+        for s in (ab, aa):
+            s.step(n_steps)
+        total += n_steps
+        _same(ab, aa, "Q%d %s %s after %d steps" % (q, box, storage, total))
+    _say("AA = two arrays, row kernel, box %s %s: %d steps" % (box, storage, total))
+    ab.close()
+    aa.close()
+
+
 def test_aa_context_follows_the_oracle():
     box = (30, 28, 26)
     p = wl.suspension(19, box, 3, 4.5, 1.3, seed=97)
