@@ -83,20 +83,25 @@ def measured_traffic(kernel, workload, box, launch):
 
 
 def copy_ceiling(torch, lbm, stream, nbytes=2 << 30, reps=10):
-    """Bandwidth of the library's plain device copy (read + write bytes / time)."""
+    """Bandwidth of the library's device copy (read + write bytes / time),
+    the faster of its two load kinds: streaming loads win from HBM, plain
+    loads from the last-level cache."""
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
-    for _ in range(2):
-        lbm.lbm_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, stream.cuda_stream)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        lbm.lbm_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, stream.cuda_stream)
-    e1.record(stream)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    best = 0.0
+    for streaming in (True, False):
+        for _ in range(2):
+            lbm.lbm_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, stream.cuda_stream, streaming)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            lbm.lbm_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, stream.cuda_stream, streaming)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        best = max(best, 2 * nbytes / (ms * 1e-3) / 1e9)
     del src, dst
-    return 2 * nbytes / (ms * 1e-3) / 1e9
+    return best
 
 
 def storage_accuracy(lbm, cfg, steps):

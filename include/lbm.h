@@ -298,9 +298,13 @@ int lbm_closure_inputs(int32_t n, const double* xi, const double* d, const doubl
 /* Algorithmic HBM bytes one sweep moves per site (2 q sizeof(storage)). */
 int lbm_bytes_per_site(const lbm_params* prm, int64_t* bytes);
 
-/* Plain device copy of `bytes` (multiple of 16, 16-B aligned pointers) on
- * `hip_stream`: the bandwidth ceiling reference for the sweep. */
-int lbm_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
+/* Device copy of `bytes` (multiple of 16, 16-B aligned pointers) on
+ * `hip_stream` with streaming (non-temporal) stores, and streaming loads when
+ * `streaming_loads` is nonzero, else plain ones: the bandwidth ceiling
+ * reference for the sweep.  Streaming loads are the faster kind from HBM,
+ * plain loads from the last-level cache.  LBM_EINVAL for a null or unaligned
+ * pointer or a size that is not a multiple of 16. */
+int lbm_device_copy(void* dst, const void* src, size_t bytes, int32_t streaming_loads, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -1339,11 +1339,13 @@ __global__ void k_fill(V* __restrict__ p, int64_t n, V v) {
 
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
-// one 16-byte vector per thread: plain load, streaming store (the access
-// kinds the sweep uses)
+// one 16-byte vector per thread, streaming store; NTL: streaming load too
+// (the access kinds of the one-box sweeps, fastest from HBM), else a plain
+// load (the ensemble sweep's, fastest from the last-level cache)
+template <bool NTL>
 __global__ __launch_bounds__(256) void k_copy16(const v4u* __restrict__ src, v4u* __restrict__ dst, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) __builtin_nontemporal_store(src[i], dst + i);
+  if (i < n) __builtin_nontemporal_store(NTL ? __builtin_nontemporal_load(src + i) : src[i], dst + i);
 }
 
 inline unsigned blocks_for(int64_t n, int per = 256) { return (unsigned)((n + per - 1) / per); }
@@ -2610,12 +2612,15 @@ int lbm_profile(lbm_ctx* c, double* sweep_ms, int64_t* sweeps) {
   return LBM_OK;
 }
 
-int lbm_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
+int lbm_device_copy(void* dst, const void* src, size_t bytes, int32_t streaming_loads, void* hip_stream) {
   if (!dst || !src || bytes % 16 || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16)) return LBM_EINVAL;
   const int64_t n = (int64_t)(bytes / 16);
   if (n == 0) return LBM_OK;
   if (blocks_for(n) > 0x7fffffff) return LBM_EINVAL;
-  k_copy16<<<blocks_for(n), 256, 0, (hipStream_t)hip_stream>>>((const v4u*)src, (v4u*)dst, n);
+  if (streaming_loads)
+    k_copy16<true><<<blocks_for(n), 256, 0, (hipStream_t)hip_stream>>>((const v4u*)src, (v4u*)dst, n);
+  else
+    k_copy16<false><<<blocks_for(n), 256, 0, (hipStream_t)hip_stream>>>((const v4u*)src, (v4u*)dst, n);
   HIP_TRY(hipGetLastError());
   return LBM_OK;
 }

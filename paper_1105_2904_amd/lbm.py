@@ -66,7 +66,7 @@ def lib():
             "lbm_set_profiling": [vp, ctypes.c_int32],
             "lbm_profile": [vp, _dp, ctypes.POINTER(ctypes.c_int64)],
             "lbm_bytes_per_site": [P, ctypes.POINTER(ctypes.c_int64)],
-            "lbm_device_copy": [vp, vp, ctypes.c_size_t, vp],
+            "lbm_device_copy": [vp, vp, ctypes.c_size_t, ctypes.c_int32, vp],
             "lbm_ensemble_workspace_size": [P, ctypes.c_int32, _ip, ctypes.POINTER(ctypes.c_size_t)],
             "lbm_ensemble_create": [P, ctypes.c_int32, _ip, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)],
             "lbm_ensemble_add_particles": [vp, ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp, _dp, _dp, _dp, _ip],
@@ -147,9 +147,9 @@ def lbm_create(params, workspace_ptr, workspace_bytes, stream_handle):
     return ctx
 
 
-def lbm_device_copy(dst_ptr, src_ptr, nbytes, stream_handle):
+def lbm_device_copy(dst_ptr, src_ptr, nbytes, stream_handle, streaming_loads=True):
     _check(lib().lbm_device_copy(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr), nbytes,
-                                 ctypes.c_void_p(stream_handle)), "lbm_device_copy")
+                                 int(bool(streaming_loads)), ctypes.c_void_p(stream_handle)), "lbm_device_copy")
 
 
 def _vec3(a, n):

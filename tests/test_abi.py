@@ -123,7 +123,8 @@ def test_null_context_and_arguments():
     assert L.lbm_step(None, 1) == lbm.LBM_EINVAL
     assert L.lbm_forces(None, None, None, None, None, None) == lbm.LBM_EINVAL
     assert L.lbm_destroy(None) == lbm.LBM_EINVAL
-    assert L.lbm_device_copy(None, None, 16, None) == lbm.LBM_EINVAL
+    assert L.lbm_device_copy(None, None, 16, 1, None) == lbm.LBM_EINVAL
+    assert L.lbm_device_copy(None, None, 16, 0, None) == lbm.LBM_EINVAL
 
 
 def test_product_path_never_uses_the_oracle():
