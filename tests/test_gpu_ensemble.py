@@ -128,16 +128,19 @@ def _same(a, b):
     return all(np.array_equal(p, q) for p, q in zip(a, b))
 
 
-def test_sweep_shapes_and_autotune_give_identical_bits():
+@pytest.mark.parametrize("q,storage", [(9, "fp32"), (19, "fp16"), (19, "bf16")])
+def test_sweep_shapes_and_autotune_give_identical_bits(q, storage):
     """One box: the row kernel, tile kernels of every width, a persistent grid,
     occupancy caps and the autotuner's pick all produce the same state after
     30 steps; caps outside the allowed range are refused."""
-    box = (70, 45, 1)
-    p = wl.suspension(9, box, 3, 5.0, 1.5, seed=81)
+    box = (70, 45, 1) if q == 9 else (70, 22, 18)
+    r = 5.0 if q == 9 else 4.0
+    p = wl.suspension(q, box, 3, r, 1.5, seed=81)
+    g = (0, -1e-4, 0) if q == 9 else (0, 0, -1e-4)
     ref = None
     for shape in [(0, 0, 0), (64, 0, 0), (128, 16, 0), (512, 0, 0), (0, 0, 5), (256, 0, 3), (64, 8, 2), "auto"]:
-        sim = lbm.Simulation(9, *box, tau=0.7, gravity=(0, -1e-4, 0), zero_net_force=True, storage="fp32",
-                             max_particles=3, max_radius=5.0)
+        sim = lbm.Simulation(q, *box, tau=0.7, gravity=g, zero_net_force=True, storage=storage,
+                             max_particles=3, max_radius=r)
         sim.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
         sim.step(3)
         if shape == "auto":
