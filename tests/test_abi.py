@@ -172,3 +172,23 @@ def test_bench_measures_one_gpu_only():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_bench_kernel_names_match_the_counter_runs():
+    """The sweep kernel names bench.py looks up in the committed HBM counter
+    runs are the names those runs list, for every storage and both sweep
+    kernels, so that roofline.traffic can only go null when the sources
+    change (hash) and not through a naming slip."""
+    import importlib.util
+    import json
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    with open(bench.COUNTERS) as fh:
+        c = json.load(fh)
+    names = {e[0] for e in c["entries"]}
+    for tname in ("float", "_Float16", "bf16s"):
+        for width in (0, 256):
+            k = bench.sweep_kernel(width, 19, tname, True, "0").replace(",", ", ")
+            assert k in names, k
