@@ -15,7 +15,10 @@ workload ("variants") and, outside every timed region, runs the workload for
 drag and settling-velocity error against FP64 ("accuracy"); it times a 64-box
 D2Q9 ensemble stepped by one launch per kernel with a tuned sweep shape and
 step graphs against a loop of one-box contexts ("batched"), and the FP64
-oracle on a few steps of the same box ("cpu_baseline").
+oracle on a few steps of the same box ("cpu_baseline").  copy_ceiling_GBps is
+the library's 2 GiB device copy with the faster of its two load kinds (and,
+for a population footprint that fits the last-level cache, the same copy at
+that footprint: copy_ceiling_cache_resident_GBps).
 """
 import argparse
 import json
