@@ -109,11 +109,14 @@ def copy_ceiling(torch, lbm, stream, nbytes=2 << 30, reps=10):
 
 def storage_accuracy(lbm, cfg, steps):
     """The same workload run for `steps` steps (outside any timed region) in
-    FP64, FP32, FP16 and BF16 storage: per-sphere drag and mean settling
-    velocity of each against the FP64 run, the GPU path that matches the
-    oracle to 1e-12 where the oracle can follow it."""
+    FP64, FP32, FP16 and BF16 storage: the velocity field (relative L2 norm
+    of the difference), the per-sphere drag and the mean settling velocity of
+    each against the FP64 run.  The reference is the GPU's FP64 path, which
+    matches the FP64 oracle to 1e-12 wherever the oracle has followed it (the
+    oracle itself would take hours for 2000 steps of this box)."""
     p = cfg["particles"]
     res = {}
+    u64 = None
     for st in ("fp64", "fp32", "fp16", "bf16"):
         sim = lbm.Simulation(19, *cfg["box"], tau=cfg["tau"], gravity=cfg["gravity"], zero_net_force=True,
                              storage=st, max_particles=len(p["radius"]), max_radius=float(np.max(p["radius"])))
@@ -121,33 +124,103 @@ def storage_accuracy(lbm, cfg, steps):
         sim.set_graph(50)
         sim.step(steps)
         F, _, _, u, _ = sim.forces()
+        uf = sim.fields()[1]
         sim.close()
-        res[st] = (F, u[:, 2].mean())
-    F64, w64 = res["fp64"]
+        if u64 is None:
+            u64 = uf
+            ev = 0.0
+        else:
+            ev = float(np.linalg.norm(uf - u64) / np.linalg.norm(u64))
+        del uf
+        res[st] = (F, u[:, 2].mean(), ev)
+    F64, w64, _ = res["fp64"]
     scale = float(np.linalg.norm(F64, axis=1).max())
-    out = {"reference": {"storage": "fp64", "steps": steps, "mean_settling_velocity": w64,
-                         "max_drag": scale}}
+    out = {"reference": {"storage": "fp64", "path": "GPU FP64 (oracle-matched)", "steps": steps,
+                         "mean_settling_velocity": w64, "max_drag": scale,
+                         "velocity_field_l2": float(np.linalg.norm(u64))}}
     for st in ("fp32", "fp16", "bf16"):
-        F, w = res[st]
-        out[st] = {"drag_error_vs_fp64": float(np.linalg.norm(F - F64, axis=1).max() / scale),
+        F, w, ev = res[st]
+        out[st] = {"velocity_field_error_vs_fp64": ev,
+                   "drag_error_vs_fp64": float(np.linalg.norm(F - F64, axis=1).max() / scale),
                    "settling_error_vs_fp64": float(abs(w - w64) / abs(w64)), "accuracy_steps": steps}
     return out
 
 
-def cpu_baseline(cfg, steps):
-    """The FP64 oracle on the same box and particles, a bounded number of steps."""
+def disks_2d_rates(torch, lbm, wl, steps, warmup, graph_steps=20):
+    """The D2Q9 1024^2 workload with 200 disks (FP32): the autotuned launch
+    replayed in step graphs.  Its two population arrays (75 MB) fit the
+    256 MB last-level cache, so its ceiling is a copy of the same footprint."""
+    cfg = wl.disks_2d_config()
+    p = cfg["particles"]
+    nx, ny, nz = cfg["box"]
+    N = nx * ny * nz
+    sim = lbm.Simulation(9, nx, ny, nz, tau=cfg["tau"], gravity=cfg["gravity"], zero_net_force=True,
+                         storage="fp32", max_particles=len(p["radius"]), max_radius=float(np.max(p["radius"])))
+    sim.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
+    sim.step(warmup)
+    w, g, k, _ = sim.autotune(reps=10)
+    sim.set_graph(graph_steps)
+    sim.step(max(warmup, graph_steps))
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    sim.step(steps)
+    e1.record(sim.stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    assert np.isfinite(sim.forces()[0]).all()
+    bps = lbm.lbm_bytes_per_site(sim.params)
+    sim.close()
+    footprint = bps * N
+    cache = copy_ceiling(torch, lbm, torch.cuda.current_stream(), nbytes=footprint // 32 * 16, reps=200)
+    gbps = bps * N / (ms * 1e-3) / 1e9
+    return {"workload": cfg["name"], "value": round(N / (ms * 1e-3) / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(ms, 5), "steps": steps, "graph_steps": graph_steps,
+            "sweep_launch": {"width": w, "grid": g, "blocks_per_cu": k}, "bytes_per_site": bps,
+            "step_GBps": round(gbps, 1), "step_frac_of_hbm_peak": round(gbps / PEAK_HBM_GBPS, 4),
+            "copy_ceiling_cache_resident_GBps": round(cache, 1),
+            "step_frac_of_cache_resident_copy": round(gbps / cache, 4)}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, steps_one, steps_all):
+    """The FP64 oracle on the same box and particles, a bounded number of
+    steps on one thread and on the host's share of cores (its per-site loops
+    run on OpenMP threads with the same bits as one thread)."""
     import oracle
     p = cfg["particles"]
-    o = oracle.Oracle(19, *cfg["box"], cfg["tau"], gravity=cfg["gravity"], zero_net_force=True)
-    o.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
-    t0 = time.perf_counter()
-    o.step(steps)
-    dt = time.perf_counter() - t0
     N = cfg["box"][0] * cfg["box"][1] * cfg["box"][2]
-    o.close()
-    return {"value": N * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": "%d steps of the full 256^3 D3Q19 box with 500 spheres (FP64, one thread), %.1f s"
-                      % (steps, dt)}
+
+    def run(threads, steps):
+        oracle.set_threads(threads)
+        o = oracle.Oracle(19, *cfg["box"], cfg["tau"], gravity=cfg["gravity"], zero_net_force=True)
+        o.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
+        used = oracle.threads()
+        t0 = time.perf_counter()
+        o.step(steps)
+        dt = time.perf_counter() - t0
+        o.close()
+        return N * steps / dt / 1e6, dt, used
+
+    one, dt1, _ = run(1, steps_one)
+    allc, dta, used = run(0, steps_all)
+    oracle.set_threads(0)
+    return {"value": allc, "unit": "MLUPS", "cores": used, "kind": "oracle",
+            "sample": "%d steps of the full 256^3 D3Q19 box with 500 spheres (FP64) on %d threads, %.1f s"
+                      % (steps_all, used, dta),
+            "single_thread": {"value": one, "unit": "MLUPS", "cores": 1,
+                              "sample": "%d steps of the same box on one thread, %.1f s" % (steps_one, dt1)},
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
 
 
 def ensemble_rates(torch, lbm, wl, steps, warmup, graph_steps=20):
@@ -249,7 +322,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp64", "fp16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps on one thread")
+    ap.add_argument("--cpu-steps-all", type=int, default=12, help="oracle steps on all the host's cores")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip timing the FP16/BF16 storage variants of the same workload")
     ap.add_argument("--particles", type=int, default=-1,
@@ -365,7 +439,10 @@ def main():
                      "traffic_read_write": None if traffic is None else [traffic["read"], traffic["write"]],
                      "algorithmic_bytes_per_launch": bps * N,
                      "kernel": kernel, "kernel_avg_ms": round(sweep_avg_ms, 4), "sites_per_launch": N,
-                     "bytes_per_site": bps},
+                     "bytes_per_site": bps,
+                     "sweep_frac": round(achieved / PEAK_HBM_GBPS, 4),
+                     "step_achieved": round(bps * N / (ms_step * 1e-3) / 1e9, 1),
+                     "step_frac": round(bps * mlups * 1e6 / 1e9 / PEAK_HBM_GBPS, 4)},
         "step_roofline_frac": round(bps * mlups * 1e6 / 1e9 / PEAK_HBM_GBPS, 4),
         "copy_ceiling_GBps": round(ceiling, 1),
     }
@@ -387,11 +464,16 @@ def main():
             vms, (vsw, vn) = timed(v, args.steps, args.warmup, True)
             vb = lbm.lbm_bytes_per_site(v.params)
             vl = dict(zip(("width", "grid", "blocks_per_cu"), v.sweep_config()))
-            vk = sweep_kernel(vl["width"], q, {"fp16": "_Float16", "bf16": "bf16s", "fp32": "float"}[st],
-                              bool(args.particles), "0" if not aa else "1/2").replace(",", ", ")
+            tn = {"fp16": "_Float16", "bf16": "bf16s", "fp32": "float"}[st]
+            # the AA pattern alternates two sweep kernels (layouts 1 and 2)
+            halves = ["1", "2"] if aa else ["0"]
+            vks = [sweep_kernel(vl["width"], q, tn, bool(args.particles), h).replace(",", ", ") for h in halves]
+            vk = vks[0] if not aa else vks[0][:-1] + "1/2>"
             vt = None
-            if args.particles == len(cfg["particles"]["radius"]) and not aa:
-                vt = measured_traffic(vk, cfg["name"], cfg["box"], vl)
+            if args.particles == len(cfg["particles"]["radius"]):
+                ts = [measured_traffic(k_, cfg["name"], cfg["box"], vl) for k_ in vks]
+                if all(t_ is not None for t_ in ts):
+                    vt = {"total": sum(t_["total"] for t_ in ts) / len(ts)}
             vm = N / (vms / args.steps * 1e-3) / 1e6
             vs = vsw / max(vn, 1)
             out["variants"][name] = {"value": round(vm, 1), "ms_per_step": round(vms / args.steps, 4),
@@ -416,9 +498,12 @@ def main():
         print("closure network timed", file=sys.stderr, flush=True)
         out["batched"] = ensemble_rates(torch, lbm, wl, args.batched_steps, args.warmup)
         print("batched ensemble timed", file=sys.stderr, flush=True)
+        out["disks_2d"] = disks_2d_rates(torch, lbm, wl, 2000, args.warmup)
+        print("D2Q9 1024^2 workload timed", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline and args.workload == "spheres-3d":
-        print("cpu baseline: %d oracle steps" % args.cpu_steps, file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
+        print("cpu baseline: %d + %d oracle steps" % (args.cpu_steps, args.cpu_steps_all), file=sys.stderr,
+              flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps, args.cpu_steps_all)
     print(json.dumps(out), flush=True)
     sim.close()
 

@@ -80,9 +80,13 @@ enum lbm_status {
   LBM_ECAPACITY = -5,   /* more particles than max_particles */
   LBM_ENONFINITE = -6,  /* non-finite input value */
   LBM_EUNSUPPORTED = -7,/* storage mode not built */
-  LBM_ECOLLISION = -8   /* collision search bound exceeded: a particle speed
+  LBM_ECOLLISION = -8,  /* collision search bound exceeded: a particle speed
                            >= 0.5 lu/step, or > 64 particles within r_i+r_j+1
                            of one particle; results of that step are invalid */
+  LBM_ESTATE = -9       /* the sweep met an owned boundary site whose record named
+                           no entry of the particle table (it wrote nothing through
+                           it); the device state is inconsistent and the results of
+                           that step are invalid */
 };
 
 typedef struct lbm_ctx lbm_ctx;

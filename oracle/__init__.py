@@ -5,7 +5,8 @@ and the ``cpu_baseline`` leg of ``bench.py`` may import this package.  It
 shares no code with the GPU library under ``paper_1105_2904_amd/`` and
 imports nothing from it.
 
-The arithmetic lives in ``lbm_oracle.c`` (plain C, FP64, one thread); this
+The arithmetic lives in ``lbm_oracle.c`` (plain C, FP64; its per-site loops
+may run on several OpenMP threads with the same results bit for bit); this
 module only builds it with gcc and marshals numpy arrays through ctypes.
 """
 import ctypes
@@ -25,7 +26,7 @@ _bp = ctypes.POINTER(ctypes.c_int8)
 
 def build():
     """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
-    cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fPIC", "-shared",
+    cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
            _SRC, "-o", _LIB + ".tmp", "-lm"]
     subprocess.check_call(cmd)
     os.replace(_LIB + ".tmp", _LIB)
@@ -71,6 +72,8 @@ def lib():
         L.ora_closure_net.argtypes = [_dp, _dp, _dp]
         L.ora_half.restype = ctypes.c_double
         L.ora_half.argtypes = [ctypes.c_double]
+        L.ora_set_threads.argtypes = [ctypes.c_int]
+        L.ora_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -101,6 +104,24 @@ def closure_net(params, x):
     for k in range(x.shape[0]):
         lib().ora_closure_net(_d(p), _d(x[k]), y[k].ctypes.data_as(_dp))
     return y
+
+
+def default_threads():
+    """The host's share of cores: OMP_NUM_THREADS when set, else the CPUs this
+    process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0))
+
+
+def set_threads(n):
+    """Threads of the oracle's per-site loops (0: default_threads())."""
+    lib().ora_set_threads(int(n) if int(n) > 0 else default_threads())
+
+
+def threads():
+    return lib().ora_threads()
 
 
 def half(x):

@@ -2,9 +2,16 @@
  * FP64 CPU oracle of the site-based suspension lattice Boltzmann method
  * (dos Santos & Philippi).  TEST INFRASTRUCTURE ONLY: loaded by the tests,
  * the smoke check and the CPU-baseline leg of the benchmark, never by the
- * product path.  Plain loops, plain f, FP64, one thread, no blocking or
- * fusion.  Each function names the passage of the paper it follows; the
- * readings taken where the paper is silent are listed with the function.
+ * product path.  Plain loops, plain f, FP64, no blocking or fusion.  Each
+ * function names the passage of the paper it follows; the readings taken where
+ * the paper is silent are listed with the function.
+ *
+ * Threads: the per-site loops (collision, propagation, read-outs) may run on
+ * several OpenMP threads.  Each of their iterations writes only its own sites
+ * and no iteration reads what another writes, so the result is the same bit
+ * for bit as with one thread; every sum over sites or particles (the BS
+ * substep, the walls' momentum, the IS leak) stays a plain loop in a fixed
+ * order on one thread.
  *
  * One time step, in the paper's order (section 2.2: the particle substeps sit
  * between collision and propagation):
@@ -20,6 +27,7 @@
 #include "lbm_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -170,8 +178,11 @@ ora_sim *ora_create(int q, int nx, int ny, int nz, double tau, double rho0,
     return NULL;
   }
   /* Initial state: fluid at rest with density rho0 (the paper is silent). */
-  for (int i = 0; i < q; i++)
+  for (int i = 0; i < q; i++) {
+#pragma omp parallel for schedule(static)
     for (long n = 0; n < s->N; n++) s->f[i * s->N + n] = s->w[i] * rho0;
+  }
+#pragma omp parallel for schedule(static)
   for (long n = 0; n < s->N; n++) s->own_p[n] = s->own_e[n] = -1;
   return s;
 }
@@ -291,6 +302,7 @@ static double min_image(double d, int n) { return d - n * floor(d / n + 0.5); }
  * A site claimed by two particles belongs to the lower id (the paper is
  * silent on overlapping site sets). */
 static void raster(ora_sim *s) {
+#pragma omp parallel for schedule(static)
   for (long n = 0; n < s->N; n++) s->own_p[n] = s->own_e[n] = -1;
   s->conflicts = 0;
   for (int p = 0; p < s->np; p++) {
@@ -386,8 +398,9 @@ int ora_add_particles(ora_sim *s, int n, const double *x, const double *u,
 static void collide(ora_sim *s) {
   const int q = s->q;
   const long N = s->N;
-  double fi[19], feq[19], u[3];
+#pragma omp parallel for schedule(static)
   for (long n = 0; n < N; n++) {
+    double fi[19], feq[19], u[3];
     double rho = 0, j[3] = {0, 0, 0};
     for (int i = 0; i < q; i++) {
       fi[i] = s->f[i * N + n];
@@ -483,7 +496,8 @@ static void wall_substep(ora_sim *s) {
  * section 2.3).  A perceptron 8 -> 64 -> 64 -> 2 with tanh hidden units maps
  * the geometry of a close pair to the force the coarse lattice misses, in
  * units of mu U (2D Stokes forces per unit depth are mu U times a function of
- * the geometry).  Readings of the closure, shared with the GPU:
+ * the geometry).  Readings of the closure (the library's kernels take the
+ * same ones, written separately):
  *  - every pair i < j whose surface gap h = |d| - r_i - r_j is below clo_h
  *    at the start of the step (minimum image); kinematic particles report
  *    the force but keep their velocity, as for the hydrodynamic force;
@@ -700,6 +714,7 @@ static void internal_substep(ora_sim *s) {
 
 /* Propagation (left-hand side of eq. 3): f_i(x + c_i) <- f*_i(x). */
 static void propagate(ora_sim *s) {
+#pragma omp parallel for collapse(2) schedule(static)
   for (int i = 0; i < s->q; i++)
     for (long z = 0; z < s->nz; z++)
       for (long y = 0; y < s->ny; y++)
@@ -747,6 +762,7 @@ void ora_forces(const ora_sim *s, double *F, double *T, double *x, double *u,
 }
 
 void ora_fields(const ora_sim *s, double *rho, double *u, int32_t *owner) {
+#pragma omp parallel for schedule(static)
   for (long n = 0; n < s->N; n++) {
     double r, v[3];
     site_moments(s, s->f, n, &r, v);
@@ -879,3 +895,10 @@ int ora_set_walls(ora_sim *s, int walls, const double *wall_u) {
   s->walls = walls;
   return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Threads of the per-site loops (results do not depend on the count).
+ * ---------------------------------------------------------------------- */
+void ora_set_threads(int n) { omp_set_num_threads(n > 0 ? n : omp_get_num_procs()); }
+
+int ora_threads(void) { return omp_get_max_threads(); }

@@ -113,6 +113,11 @@ double ora_half(double x);
 
 int ora_num_particles(const ora_sim *s);
 
+/* Threads the per-site loops use (n <= 0: one per processor), and the
+ * current count.  Results are identical for every count. */
+void ora_set_threads(int n);
+int ora_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

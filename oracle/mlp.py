@@ -11,13 +11,14 @@ Network (8 -> 64 -> 64 -> 2, tanh hidden units):
 Loss over a batch of B rows: L = (1/B) sum_rows sum_o (y - t)^2.
 
 Parameters travel as one flat vector in the order W1 (8x64, row-major),
-b1 (64), W2 (64x64), b2 (64), W3 (64x2), b3 (2): 4802 values.
+b1 (64), W2 (64x64), b2 (64), W3 (64x2), b3 (2): 4866 values.
 
-quantize=True applies the rounding points of the mixed-precision kernels
-(round to nearest even to FP16): the inputs, every weight matrix, the hidden
-activations h1 and h2, and the backward signals after multiplication by the
-loss scale S (dL/dy, dL/dz2, dL/dz1); biases, sums and the scale removal are
-exact here (FP64).  With quantize=False everything is FP64.
+quantize=True rounds to FP16 (nearest even) at the points a network with
+FP16 weights on FP16 matrix-core operands has: the inputs, every weight
+matrix, the hidden activations h1 and h2, and the backward signals (dL/dy,
+dL/dz2, dL/dz1), the latter after multiplication by a loss scale S (a choice
+of the mixed-precision kernels, not of the problem); biases, sums and the
+scale removal are exact here (FP64).  With quantize=False everything is FP64.
 """
 import numpy as np
 

@@ -70,6 +70,7 @@ constexpr int kParticleBlock = 1024;   // particle update of a one-box context
 constexpr int kBoxParticleBlock = 256; // particle update, per box of an ensemble
 constexpr int kStatusCollision = 1;
 constexpr int kStatusClosure = 2;     // more close pairs than kClosurePairs
+constexpr int kStatusRecord = 4;      // an owned-BS record named no entry of the table
 constexpr int kClosurePairs = 1024;   // close pairs one step of the closure handles
 constexpr size_t kAlign = 256;
 
@@ -249,6 +250,8 @@ struct SiteArgs {
   const typename Store<T>::C* vel;  // [site][4]: record of a kSiteBS site
   double* slot;                     // [entry][4]: post-collision drho, j of an owned BS site
   typename Store<T>::C* drho;       // density deviation of every ball site (this sweep)
+  int nent;                         // entries in the table: a record's index must lie below
+  int* status;                      // device status word (kStatusRecord)
 };
 
 // One site record as a single 16- (FP32) or 32-byte (FP64) load.
@@ -434,11 +437,17 @@ __device__ __forceinline__ void sweep_site(const T* A, T* B, const SweepArgs<Q, 
         by += L::cy(i) * v;
         bz += L::cz(i) * v;
       }
-      double* sl = sa.slot + 4 * (size_t)bs;
-      sl[0] = dr;
-      sl[1] = bx;
-      sl[2] = by;
-      sl[3] = bz;
+      if ((unsigned)bs < (unsigned)sa.nent) {
+        double* sl = sa.slot + 4 * (size_t)bs;
+        sl[0] = dr;
+        sl[1] = bx;
+        sl[2] = by;
+        sl[3] = bz;
+      } else {
+        // a record that names no entry (never written by the prepare pass):
+        // no write through it; the next synchronising call reports it
+        atomicOr(sa.status, kStatusRecord);
+      }
       const C drB = (C)dr;
       const C rhoB = a.rho0 + drB;
       const C usqB = C(1.5) * (vx * vx + vy * vy + vz * vz);
@@ -1337,6 +1346,18 @@ __global__ void k_fill(V* __restrict__ p, int64_t n, V v) {
   if (i < n) p[i] = v;
 }
 
+// Every site record at rest and naming no entry (index -1), so that a record
+// the prepare pass never wrote can never be taken for a valid one.
+template <typename C>
+__global__ void k_fill_records(C* __restrict__ vel, int64_t n) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= n) return;
+  vel[4 * s] = C(0);
+  vel[4 * s + 1] = C(0);
+  vel[4 * s + 2] = C(0);
+  vel[4 * s + 3] = idx_as<C>(-1);
+}
+
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 // one 16-byte vector per thread, streaming store; NTL: streaming load too
@@ -1555,6 +1576,7 @@ struct lbm_ctx {
   int prep_split;     // most workgroups per particle of the per-particle prepare
   bool small_ball;    // the largest ball holds at most kSmallBall entries
   bool prof;
+  bool failed;  // a HIP error left the device state part-way through an update
   std::vector<hipEvent_t> ev;
   size_t ev_used;
 };
@@ -1577,6 +1599,8 @@ SiteArgs<T> site_args(lbm_ctx* c) {
   sa.vel = (const typename Store<T>::C*)c->vel;
   sa.slot = c->slot;
   sa.drho = (typename Store<T>::C*)c->drho;
+  sa.nent = (int)c->nent;
+  sa.status = c->status;
   return sa;
 }
 
@@ -1862,6 +1886,7 @@ int check_status(lbm_ctx* c) {
     const int zero[4] = {0, 0, 0, 0};
     HIP_TRY(hipMemcpyAsync(c->status, zero, sizeof(zero), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    if (st[0] & kStatusRecord) return LBM_ESTATE;
     if (st[0] & kStatusCollision) return LBM_ECOLLISION;
     if (st[0] & kStatusClosure) return LBM_ECAPACITY;
   }
@@ -2016,6 +2041,7 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
   for (int b = 0; b < nbox; b++)
     for (int a = 0; a < 3; a++) c->fbb[3 * b + a] = prm->body_force[a];
   c->prof = false;
+  c->failed = false;
   c->ev_used = 0;
   {
     // one workgroup per particle while the largest ball's bounding box, (2 floor(r + 1/2)
@@ -2037,6 +2063,10 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
   k_fill<int><<<blocks_for(c->NT), 256, 0, c->stream>>>(c->own, c->NT, kEmpty);
   k_fill<uint8_t><<<blocks_for(c->NT), 256, 0, c->stream>>>(c->flag, c->NT, (uint8_t)0);
   k_fill<int><<<1, 256, 0, c->stream>>>(c->status, 16, 0);
+  if (prm->storage == LBM_FP64)
+    k_fill_records<double><<<blocks_for(c->NT), 256, 0, c->stream>>>((double*)c->vel, c->NT);
+  else
+    k_fill_records<float><<<blocks_for(c->NT), 256, 0, c->stream>>>((float*)c->vel, c->NT);
   if (hipGetLastError() != hipSuccess || upload_boxes(c) != LBM_OK ||
       (c->sweep_w > 0 && build_tiles(c, c->sweep_w) != LBM_OK) || hipStreamSynchronize(c->stream) != hipSuccess) {
     delete c;
@@ -2073,6 +2103,7 @@ int lbm_destroy(lbm_ctx* c) {
 static int add_impl(lbm_ctx* c, int32_t bx, int32_t n, const double* x, const double* u, const double* omega,
                     const double* radius, const double* mass, const double* inertia, int32_t* first_id) {
   if (!c || n < 0 || bx < 0 || bx >= c->nbox) return LBM_EINVAL;
+  if (c->failed) return LBM_EHIP;
   // particles of a box have consecutive ids: boxes are filled in order
   if (c->np > 0 && bx < c->h_box.back()) return LBM_EINVAL;
   if (n == 0) {
@@ -2151,10 +2182,26 @@ static int add_impl(lbm_ctx* c, int32_t bx, int32_t n, const double* x, const do
     hpid.insert(hpid.end(), (size_t)(nb + ni + nn), c->np + j);
   }
   if (c->nent + (int64_t)hoff.size() > c->L.max_ent) return LBM_ECAPACITY;
+  // Every argument has been checked: from here on only a HIP error can fail
+  // the call.  The host bookkeeping is then put back as it was, and the
+  // context is marked failed (the device map may already hold stamps of the
+  // rejected particles), so that every later call reports LBM_EHIP.
   const int p0 = c->np;
+  const int64_t e0 = c->nent, e1 = c->nent + (int64_t)hoff.size();
+  const std::vector<Geo> boxes_before = c->boxes;
+  const std::vector<double> fbb_before = c->fbb;
+  auto fail = [&](int code) {
+    c->boxes = boxes_before;
+    c->G = c->boxes[0];
+    c->fbb = fbb_before;
+    c->np = p0;
+    c->nent = e0;
+    c->failed = true;
+    return code;
+  };
   int rc;
 #define UP(dst, src, cnt) \
-  if ((rc = upload(c, dst, src, cnt)) != LBM_OK) return rc
+  if ((rc = upload(c, dst, src, cnt)) != LBM_OK) return fail(rc)
   UP(c->P.x + 3 * p0, hx.data(), 3 * (size_t)n);
   UP(c->P.x0 + 3 * p0, hx.data(), 3 * (size_t)n);
   UP(c->P.u + 3 * p0, hu.data(), 3 * (size_t)n);
@@ -2178,25 +2225,38 @@ static int add_impl(lbm_ctx* c, int32_t bx, int32_t n, const double* x, const do
   UP(c->P.box + p0, hbox.data(), (size_t)n);
   UP(c->E.off + c->nent, hoff.data(), hoff.size());
   UP(c->E.pid + c->nent, hpid.data(), hpid.size());
+  const std::vector<double> zero(3 * (size_t)n, 0.0);
+  UP(c->P.F + 3 * p0, zero.data(), 3 * (size_t)n);
+  UP(c->P.T + 3 * p0, zero.data(), 3 * (size_t)n);
+  UP(c->P.fc + 3 * p0, zero.data(), 3 * (size_t)n);
 #undef UP
-  std::vector<double> zero(3 * (size_t)n, 0.0);
-  HIP_TRY(hipMemcpyAsync(c->P.F + 3 * p0, zero.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipMemcpyAsync(c->P.T + 3 * p0, zero.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipMemcpyAsync(c->P.fc + 3 * p0, zero.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
   // stamp the new entries into the current map (existing owners have lower ids)
-  const int64_t e0 = c->nent, e1 = c->nent + (int64_t)hoff.size();
   for (int b = bx; b < c->nbox; b++) c->boxes[b].p1 = c->np + n;  // later boxes are still empty
   c->G = c->boxes[0];
   if (e1 > e0) {  // particles this small may hold no site at all
     k_stamp<<<blocks_for(e1 - e0), 256, 0, c->stream>>>(c->own, c->P, c->E, boxes_arg(c), (int)e0, (int)e1);
-    HIP_TRY(hipGetLastError());
+    if (hipGetLastError() != hipSuccess) return fail(LBM_EHIP);
   }
   c->nent = e1;
   c->np += n;
   // records of every ball site, with nothing pending (written into the state above)
   const int prc = DISPATCH(c, launch_prepare, c, 0);
-  if (prc != LBM_OK) return prc;
-  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (prc != LBM_OK) return fail(prc);
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(LBM_EHIP);
+  // fluid body force of every box: user value, plus the opposite of the
+  // box's particles' total external force spread over its sites in a
+  // zero-net-force box
+  std::vector<double> tot(3 * (size_t)c->nbox, 0.0);
+  for (int p = 0; p < p0; p++)
+    for (int a = 0; a < 3; a++) tot[3 * c->h_box[p] + a] += c->h_fext[3 * p + a];
+  for (int j = 0; j < n; j++)
+    for (int a = 0; a < 3; a++) tot[3 * bx + a] += hfext[3 * j + a];
+  for (int b = 0; b < c->nbox; b++)
+    for (int a = 0; a < 3; a++)
+      c->fbb[3 * b + a] =
+          c->prm.body_force[a] - (c->prm.zero_net_force ? tot[3 * b + a] / (double)c->boxes[b].N : 0.0);
+  if (upload_boxes(c) != LBM_OK) return fail(LBM_EHIP);
+  // the call has succeeded: the host copies of the particle set grow
   for (int j = 0; j < n; j++) {
     c->h_x0.insert(c->h_x0.end(), &hx[3 * j], &hx[3 * j] + 3);
     c->h_rad.push_back(radius[j]);
@@ -2210,18 +2270,6 @@ static int add_impl(lbm_ctx* c, int32_t bx, int32_t n, const double* x, const do
   c->h_off.insert(c->h_off.end(), hoff.begin(), hoff.end());
   c->h_pid.insert(c->h_pid.end(), hpid.begin(), hpid.end());
   c->h_box.insert(c->h_box.end(), (size_t)n, bx);
-  // fluid body force of every box: user value, plus the opposite of the
-  // box's particles' total external force spread over its sites in a
-  // zero-net-force box
-  std::vector<double> tot(3 * (size_t)c->nbox, 0.0);
-  for (int p = 0; p < c->np; p++)
-    for (int a = 0; a < 3; a++) tot[3 * c->h_box[p] + a] += c->h_fext[3 * p + a];
-  for (int b = 0; b < c->nbox; b++)
-    for (int a = 0; a < 3; a++)
-      c->fbb[3 * b + a] =
-          c->prm.body_force[a] - (c->prm.zero_net_force ? tot[3 * b + a] / (double)c->boxes[b].N : 0.0);
-  const int urc = upload_boxes(c);
-  if (urc != LBM_OK) return urc;
   drop_graph(c);
   if (first_id) *first_id = p0;
   return LBM_OK;
@@ -2280,6 +2328,7 @@ static int ensure_graph(lbm_ctx* c) {
 
 int lbm_step(lbm_ctx* c, int32_t nsteps) {
   if (!c || nsteps < 0) return LBM_EINVAL;
+  if (c->failed) return LBM_EHIP;
   if (c->sweep_w > 0) {
     const int rc = build_tiles(c, c->sweep_w);
     if (rc != LBM_OK) return rc;
@@ -2332,6 +2381,7 @@ int lbm_get_sweep_config(lbm_ctx* c, int32_t* width, int32_t* grid, int32_t* blo
 int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* width, int32_t* grid, int32_t* blocks_per_cu,
                  double* best_ms) {
   if (!c || reps < 1) return LBM_EINVAL;
+  if (c->failed) return LBM_EHIP;
   if (c->prm.aa) return LBM_EINVAL;  // a sweep in place cannot be repeated on the live state
   // a sweep recomputes B and the ball-site scratch from A and the records,
   // so repeating it leaves the state as one sweep does: time the candidates
@@ -2431,6 +2481,7 @@ int lbm_box_info(lbm_ctx* c, int32_t box, int32_t* dims, int64_t* first_site, in
 
 int lbm_forces(lbm_ctx* c, double* F, double* T, double* x, double* u, double* omega) {
   if (!c) return LBM_EINVAL;
+  if (c->failed) return LBM_EHIP;
   const size_t b = sizeof(double) * 3 * c->np;
   if (c->np > 0) {
     if (F) HIP_TRY(hipMemcpyAsync(F, c->P.F, b, hipMemcpyDeviceToHost, c->stream));
@@ -2444,6 +2495,7 @@ int lbm_forces(lbm_ctx* c, double* F, double* T, double* x, double* u, double* o
 
 int lbm_fields(lbm_ctx* c, double* rho, double* u, int32_t* owner) {
   if (!c) return LBM_EINVAL;
+  if (c->failed) return LBM_EHIP;
   if (rho || u) {
     // two arrays: the idle one stages the moments; AA: the staging area
     const size_t stage = c->prm.aa ? 4 * sizeof(double) * (size_t)std::min<int64_t>(c->NT, (int64_t)1 << 20)
@@ -2477,6 +2529,7 @@ int lbm_fields(lbm_ctx* c, double* rho, double* u, int32_t* owner) {
 
 int lbm_site_kind(lbm_ctx* c, int8_t* kind) {
   if (!c || !kind) return LBM_EINVAL;
+  if (c->failed) return LBM_EHIP;
   std::vector<int> m(c->NT);
   HIP_TRY(hipMemcpyAsync(m.data(), c->own, sizeof(int) * c->NT, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
@@ -2486,6 +2539,7 @@ int lbm_site_kind(lbm_ctx* c, int8_t* kind) {
 
 int lbm_shifts(lbm_ctx* c, int32_t* k) {
   if (!c || !k) return LBM_EINVAL;
+  if (c->failed) return LBM_EHIP;
   if (c->np > 0) HIP_TRY(hipMemcpyAsync(k, c->P.k, sizeof(int) * 3 * c->np, hipMemcpyDeviceToHost, c->stream));
   return check_status(c);
 }
@@ -2499,6 +2553,7 @@ int lbm_particle_info(lbm_ctx* c, int32_t p, int32_t* nbs, int32_t* nis) {
 
 int lbm_get_distributions(lbm_ctx* c, double* f) {
   if (!c || !f) return LBM_EINVAL;
+  if (c->failed) return LBM_EHIP;
   const int64_t n = (int64_t)c->q * c->PS;  // device planes (padded)
   const int ss = (int)store_size(c->prm.storage);
   std::vector<unsigned char> h((size_t)n * ss);
@@ -2551,6 +2606,7 @@ int lbm_get_distributions(lbm_ctx* c, double* f) {
 
 int lbm_set_distributions(lbm_ctx* c, const double* f) {
   if (!c || !f) return LBM_EINVAL;
+  if (c->failed) return LBM_EHIP;
   const int64_t nf = (int64_t)c->q * c->NT;
   for (int64_t i = 0; i < nf; i++)
     if (!std::isfinite(f[i])) return LBM_ENONFINITE;
@@ -2636,6 +2692,7 @@ const char* lbm_strerror(int code) {
     case LBM_ENONFINITE: return "non-finite value";
     case LBM_EUNSUPPORTED: return "storage mode not supported";
     case LBM_ECOLLISION: return "collision search bound exceeded";
+    case LBM_ESTATE: return "inconsistent device state: a boundary-site record named no entry";
     default: return "unknown error";
   }
 }

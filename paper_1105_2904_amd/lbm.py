@@ -19,6 +19,7 @@ STORAGE = {"fp64": LBM_FP64, "fp32": LBM_FP32, "fp16": LBM_FP16, "bf16": LBM_BF1
 LBM_OK = 0
 LBM_EINVAL, LBM_EWORKSPACE, LBM_EHIP, LBM_EOVERLAP = -1, -2, -3, -4
 LBM_ECAPACITY, LBM_ENONFINITE, LBM_EUNSUPPORTED, LBM_ECOLLISION = -5, -6, -7, -8
+LBM_ESTATE = -9
 
 
 class LbmError(RuntimeError):

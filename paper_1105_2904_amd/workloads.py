@@ -113,6 +113,17 @@ def suspension(q, box, n, radius, density_ratio, seed, min_gap=2.0, rho0=1.0):
             "inertia": np.asarray(inertia, dtype=np.float64)}
 
 
+def seeded_velocities(n, dim, vmax, seed):
+    """Initial velocities [n][3]: every in-plane component uniform in
+    [-vmax, vmax) from a SplitMix64 stream (the z components are 0 in 2D)."""
+    rng = SplitMix64(seed)
+    u = np.zeros((n, 3))
+    for j in range(n):
+        for a in range(dim):
+            u[j, a] = vmax * (2.0 * rng.uniform() - 1.0)
+    return u
+
+
 def kinematic_disk_config():
     """D2Q9, tau 0.8, 64x64 periodic, one disk of radius 8 at the centre moving
     with imposed velocity (0.01, 0); FP64; 1000 steps."""

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_strerror_covers_every_code():
-    for code in range(0, -9, -1):
+    for code in range(0, -10, -1):
         assert lbm.lbm_strerror(code) != "unknown error"
     assert lbm.lbm_strerror(-99) == "unknown error"
 
@@ -192,3 +192,7 @@ def test_bench_kernel_names_match_the_counter_runs():
         for width in (0, 256):
             k = bench.sweep_kernel(width, 19, tname, True, "0").replace(",", ", ")
             assert k in names, k
+    # the AA pattern's two halves (even and odd steps) are separate kernels
+    for layout in ("1", "2"):
+        k = bench.sweep_kernel(0, 19, "float", True, layout).replace(",", ", ")
+        assert k in names, k

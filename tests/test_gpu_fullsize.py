@@ -1,0 +1,172 @@
+"""Full-size parity of the benchmark workloads, the HIP path in the launch the
+benchmark times (the autotuner's pick on the live state) against the FP64
+oracle on the same seeded inputs, with particles that move: their integer
+shifts change, so the map is rebuilt and the IS substep is imposed at new
+positions (section 2.2, third and fourth substeps; eq. 13-15).
+
+  - D2Q9 1024^2, 200 disks r = 10, FP32: every site, every F and T, the
+    shifts, the owner map and the site kinds.
+  - D3Q19 256^3, 500 spheres r = 6, FP32: every site (compared slab by slab),
+    every F and T, the shifts.
+  - A sphere whose shift changes along all three axes in one step (not a
+    D3Q19 link: the new IS sites may lie outside the ball of the step before),
+    FP64 and FP32, every site at every step around the jump.
+
+Gates: e_f, e_dev and the velocity field as in _gates; forces and torques
+relative to the run's force and torque scales (1e-4 FP32, 1e-12 FP64);
+shifts, owner map and site kinds bit-exact.  The oracle runs its per-site
+loops on the host's cores (same bits as one thread).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from _gates import check_f, check_u
+from paper_1105_2904_amd import lbm
+from paper_1105_2904_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    lbm.lib()
+    oracle.set_threads(0)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _pair(cfg, p, storage):
+    q, box = cfg["q"], cfg["box"]
+    rmax = float(np.max(p["radius"]))
+    sim = lbm.Simulation(q, *box, tau=cfg["tau"], gravity=cfg["gravity"], zero_net_force=True,
+                         storage=storage, max_particles=len(p["radius"]), max_radius=rmax)
+    ora = oracle.Oracle(q, *box, cfg["tau"], gravity=cfg["gravity"], zero_net_force=True)
+    kw = dict(u=p["u"], omega=p["omega"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
+    sim.add_particles(p["x"], **kw)
+    ora.add_particles(p["x"], **kw)
+    return sim, ora
+
+
+class Scales:
+    """Force and torque scales of the run so far (see test_gpu_parity)."""
+
+    def __init__(self, rmax):
+        self.F = self.T = 0.0
+        self.r = rmax
+
+    def check(self, sim, ora, tol, label):
+        Fg, Tg, xg, ug, _ = sim.forces()
+        Fo, To, xo, uo, _ = ora.forces()
+        self.F = max(self.F, float(np.linalg.norm(Fo, axis=1).max()))
+        self.T = max(self.T, float(np.linalg.norm(To, axis=1).max()))
+        eF = float(np.linalg.norm(Fg - Fo, axis=1).max()) / self.F
+        eT = float(np.linalg.norm(Tg - To, axis=1).max()) / max(self.T, self.r * self.F)
+        ex = float(np.abs(xg - xo).max())
+        _say("  %s e_F %.2e e_T %.2e |x_gpu - x_ora| %.2e" % (label, eF, eT, ex))
+        assert eF <= tol and eT <= tol, (label, eF, eT)
+        kg, ko = sim.shifts(), ora.shifts()
+        assert np.array_equal(kg, ko), (label, "shifts", np.argwhere(kg != ko)[:5])
+        return ko
+
+
+def test_disks_1024sq_200_full_size_fp32():
+    """The D2Q9 1024^2 workload (tau 0.7, 200 disks r = 10, density ratio 1.5,
+    gravity 1e-5, zero-net-force frame) with seeded initial velocities of up
+    to 0.02 lu/step per component, 300 steps in FP32."""
+    cfg = wl.disks_2d_config()
+    p = dict(cfg["particles"])
+    p["u"] = wl.seeded_velocities(len(p["radius"]), 2, 0.02, seed=11)
+    sim, ora = _pair(cfg, p, "fp32")
+    w, g, k, ms = sim.autotune(reps=3)
+    _say("D2Q9 1024^2, 200 disks, fp32, sweep launch (%d, %d, %d) %.4f ms" % (w, g, k, ms))
+    sc = Scales(10.0)
+    k0 = sim.shifts()
+    for t in range(0, 300, 50):
+        sim.step(50)
+        ora.step(50)
+        ko = sc.check(sim, ora, 1e-4, "step %d" % (t + 50))
+    moved = int((ko != k0).any(axis=1).sum())
+    _say("  disks whose shift changed: %d of 200" % moved)
+    assert moved >= 100
+    _, wts = oracle.lattice(9)
+    check_f(sim.get_distributions(), ora.get_f(), wts, "fp32", "300 steps, every site")
+    _, ug, og = sim.fields()
+    _, uo, oo = ora.fields()
+    check_u(ug, uo, "fp32", "300 steps")
+    assert np.array_equal(og, oo)
+    assert np.array_equal(sim.site_kind(), ora.site_kind())
+    sim.close()
+    ora.close()
+
+
+def test_spheres_256cubed_500_moving_full_size_fp32():
+    """The D3Q19 256^3 workload (tau 0.6, 500 spheres r = 6, density ratio
+    1.2, gravity 1e-6, zero-net-force frame) with seeded initial velocities of
+    up to 0.03 lu/step per component, 40 steps in FP32; every site compared,
+    z-slab by z-slab."""
+    cfg = wl.spheres_3d_config()
+    p = dict(cfg["particles"])
+    p["u"] = wl.seeded_velocities(len(p["radius"]), 3, 0.03, seed=12)
+    sim, ora = _pair(cfg, p, "fp32")
+    w, g, k, ms = sim.autotune(reps=2)
+    _say("D3Q19 256^3, 500 spheres, fp32, sweep launch (%d, %d, %d) %.3f ms" % (w, g, k, ms))
+    sc = Scales(6.0)
+    k0 = sim.shifts()
+    for t in range(0, 40, 10):
+        sim.step(10)
+        ora.step(10)
+        ko = sc.check(sim, ora, 1e-4, "step %d" % (t + 10))
+    moved = int((ko != k0).any(axis=1).sum())
+    _say("  spheres whose shift changed: %d of 500" % moved)
+    assert moved >= 100
+    _, wts = oracle.lattice(19)
+    fo = ora.get_f()
+    fg = sim.get_distributions()
+    check_f(fg, fo, wts, "fp32", "40 steps, every site")
+    del fg, fo
+    assert np.array_equal(sim.site_kind(), ora.site_kind())
+    sim.close()
+    ora.close()
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_shift_along_three_axes_in_one_step(storage):
+    """A kinematic sphere (r = 4.3) moving along (1, 1, 1) at 0.03 lu/step per
+    axis crosses the half-integer on all three axes in the same step (step
+    17), next to a free heavy sphere moving the same way; every site and the
+    forces are compared at every step from 14 to 20."""
+    box = (32, 30, 28)
+    v = 0.03
+    p = {"x": np.array([[12.3, 13.1, 11.8], [24.6, 21.4, 19.9]]),
+         "u": np.array([[v, v, v], [v, v, v]]), "omega": np.array([[0.0, 0.0, 0.0], [1e-3, -2e-3, 5e-4]]),
+         "radius": np.array([4.3, 3.1])}
+    m, inertia = wl.solid_body(3, p["radius"], 3.0)
+    p["mass"] = np.array([np.inf, m[1]])
+    p["inertia"] = np.array([np.inf, inertia[1]])
+    cfg = {"q": 19, "box": box, "tau": 0.65, "gravity": (0.0, 0.0, -1e-5)}
+    sim, ora = _pair(cfg, p, storage)
+    tol = 1e-12 if storage == "fp64" else 1e-4
+    sc = Scales(4.3)
+    _, wts = oracle.lattice(19)
+    sim.step(14)
+    ora.step(14)
+    jumped = False
+    for t in range(14, 21):
+        before = ora.shifts()
+        sim.step(1)
+        ora.step(1)
+        ko = sc.check(sim, ora, tol, "step %d" % (t + 1))
+        if np.all(ko[0] - before[0] == 1):
+            _say("  step %d: shift of sphere 0 %s -> %s" % (t + 1, before[0], ko[0]))
+            jumped = True
+        check_f(sim.get_distributions(), ora.get_f(), wts, storage, "step %d" % (t + 1))
+        assert np.array_equal(sim.site_kind(), ora.site_kind())
+    assert jumped
+    sim.close()
+    ora.close()

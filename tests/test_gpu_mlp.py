@@ -104,3 +104,153 @@ def test_training_on_gpu_fits_a_smooth_target():
           flush=True)
     assert l1 < 0.1 * l0
     assert abs(lo - l1) <= 1e-3 * lo
+
+
+# ---------------------------------------------------------------------------
+# Against the exact FP64 network, with bounds derived from the arithmetic
+# (the quantised model of oracle/mlp.py plays no part here).
+#
+# What the problem fixes: FP16 weights, and FP16 operands on the matrix cores
+# with FP32 sums (so the inputs and hidden activations are FP16 too).  What
+# the kernels choose: tanh in FP32 as 1 - 2/(exp(2z) + 1), and backward
+# signals scaled by S before their FP16 rounding.
+#
+# Forward: a rigorous running error bound follows the exact FP64 network
+# (weights and inputs unrounded) through the kernel's operations: an FP16
+# rounding adds u16 |v| + 2^-25 (unit roundoff 2^-11, half the subnormal
+# spacing), an FP32 operation u32 |v| (2^-24), a sum of k terms
+# k u32 sum|terms|, tanh_fast (16 + 4|z|) u32, and errors propagate through
+# products and tanh' = 1 - tanh^2.  Every output must lie within it.
+#
+# Gradient: worst-case bounds of sums over hundreds of samples exceed the
+# gradient itself, so the gate is statistical.  The reference is the exact
+# FP64 gradient of the network whose weights and inputs are their FP16 values
+# (the problem's FP16 weights; that rounding is common to all samples and is
+# taken exactly, not bounded).  Every other rounding (activations, backward
+# signals, FP32 sums, tanh) is independent from sample to sample; each is
+# modelled as uniform in +-u|v|, variance (u v)^2 / 3, and the variances are
+# propagated to first order.  Each loss and gradient value must lie within
+# 8 standard deviations of the reference.
+U16, U32, SUB = 2.0 ** -11, 2.0 ** -24, 2.0 ** -25
+
+
+def _r16(v, E=0.0):
+    """Error bound after rounding a value with error bound E to FP16."""
+    return E + U16 * np.abs(v) + SUB
+
+
+def _mm(A, EA, B, EB):
+    """Bound of the FP32 product of operands with error bounds EA, EB."""
+    aA, aB = np.abs(A), np.abs(B)
+    k = A.shape[1]
+    return aA @ EB + EA @ aB + EA @ EB + k * U32 * (aA @ aB)
+
+
+def _forward_bound(theta, X):
+    p = omlp.unpack(theta)
+    x = np.asarray(X, dtype=np.float64)
+    W1, W2, W3 = p["W1"], p["W2"], p["W3"]
+    z1 = x @ W1 + p["b1"]
+    Ez1 = _mm(x, _r16(x), W1, _r16(W1)) + U32 * np.abs(z1)
+    h1 = np.tanh(z1)
+    Eh1 = _r16(h1, (1 - h1 ** 2) * Ez1 + (16 + 4 * np.abs(z1)) * U32)
+    z2 = h1 @ W2 + p["b2"]
+    Ez2 = _mm(h1, Eh1, W2, _r16(W2)) + U32 * np.abs(z2)
+    h2 = np.tanh(z2)
+    Eh2 = _r16(h2, (1 - h2 ** 2) * Ez2 + (16 + 4 * np.abs(z2)) * U32)
+    y = h2 @ W3 + p["b3"]
+    return y, _mm(h2, Eh2, W3, _r16(W3)) + U32 * np.abs(y)
+
+
+def _v16(v, V=0.0):
+    """Variance after an FP16 rounding of a value with variance V."""
+    return V + ((U16 * v) ** 2 + SUB ** 2) / 3.0
+
+
+def _v32(v, V=0.0, k=1):
+    return V + k * (U32 * v) ** 2 / 3.0
+
+
+def _gradient_reference(theta, X, T, S):
+    """Loss and gradient of the FP16-weight network in exact arithmetic, and
+    the standard deviations of the kernel's other roundings around them."""
+    p = omlp.unpack(theta)
+    f16 = lambda a: np.asarray(a, dtype=np.float16).astype(np.float64)
+    x = f16(X)
+    W1, W2, W3 = f16(p["W1"]), f16(p["W2"]), f16(p["W3"])
+    T = np.asarray(T, dtype=np.float64)
+    B = x.shape[0]
+    z1 = x @ W1 + p["b1"]
+    h1 = np.tanh(z1)
+    Vh1 = _v16(h1, (1 - h1 ** 2) ** 2 * _v32(np.abs(x) @ np.abs(W1), 0.0, 16) + ((16 + 4 * np.abs(z1)) * U32) ** 2 / 3)
+    z2 = h1 @ W2 + p["b2"]
+    Vz2 = Vh1 @ W2 ** 2 + _v32(np.abs(h1) @ np.abs(W2), 0.0, 64)
+    h2 = np.tanh(z2)
+    Vh2 = _v16(h2, (1 - h2 ** 2) ** 2 * Vz2 + ((16 + 4 * np.abs(z2)) * U32) ** 2 / 3)
+    y = h2 @ W3 + p["b3"]
+    Vy = Vh2 @ W3 ** 2 + _v32(np.abs(h2) @ np.abs(W3), 0.0, 64)
+    e = y - T
+    Ve = _v32(np.abs(y) + np.abs(T), Vy)
+    loss = float((e * e).sum() / B)
+    Vloss = float(((2 * e) ** 2 * Ve).sum() / B ** 2 + B * (U32 * loss) ** 2)
+    gy = S * 2.0 * e / B
+    Vgy = _v16(gy, _v32(gy, (2 * S / B) ** 2 * Ve))
+
+    def back(g, Vg, W, h, Vh):
+        acc = g @ W.T
+        Vacc = Vg @ (W.T) ** 2 + _v32(np.abs(g) @ np.abs(W.T), 0.0, W.shape[1])
+        fac = 1.0 - h ** 2
+        Vfac = (2 * h) ** 2 * Vh + (2 * U32) ** 2 / 3
+        z = acc * fac
+        return z, _v16(z, _v32(z, fac ** 2 * Vacc + acc ** 2 * Vfac))
+
+    gz2, Vgz2 = back(gy, Vgy, W3, h2, Vh2)
+    gz1, Vgz1 = back(gz2, Vgz2, W2, h1, Vh1)
+
+    def wgrad(a, Va, g, Vg):
+        v = a.T @ g / S
+        return v, (Va.T @ g ** 2 + (a ** 2).T @ Vg + B * (U32 ** 2 / 3) * ((a ** 2).T @ g ** 2)) / S ** 2
+
+    def bgrad(g, Vg):
+        v = g.sum(axis=0) / S
+        return v, (Vg.sum(axis=0) + B * (U32 ** 2 / 3) * (g ** 2).sum(axis=0)) / S ** 2
+
+    parts = {"W3": wgrad(h2, Vh2, gy, Vgy), "b3": bgrad(gy, Vgy), "W2": wgrad(h1, Vh1, gz2, Vgz2),
+             "b2": bgrad(gz2, Vgz2), "W1": wgrad(x, 0.0 * x, gz1, Vgz1), "b1": bgrad(gz1, Vgz1)}
+    g = omlp.pack({k: v[0] for k, v in parts.items()})
+    sd = np.sqrt(omlp.pack({k: v[1] for k, v in parts.items()}))
+    return loss, float(np.sqrt(Vloss)), g, sd
+
+
+@pytest.mark.parametrize("n", [1, 17, 1000, 65537])
+def test_forward_within_bound_of_exact_network(n):
+    theta = _params(1)
+    X, _ = _data(n, 2)
+    y = lbm.mlp_forward(_t(theta), _t(X)).cpu().numpy().astype(np.float64)
+    y64, Ey = _forward_bound(theta, X)
+    ratio = np.abs(y - y64) / Ey
+    print("forward n=%d: |y - y_exact| / bound max %.3f mean %.3f; bound / max|y| mean %.2e"
+          % (n, ratio.max(), ratio.mean(), Ey.mean() / np.abs(y64).max()), flush=True)
+    assert np.all(np.abs(y - y64) <= Ey)
+
+
+@pytest.mark.parametrize("n", [64, 777])
+@pytest.mark.parametrize("S", [1.0, 1024.0])
+def test_gradient_within_rounding_spread_of_exact_gradient(n, S):
+    theta = _params(3)
+    X, T = _data(n, 4)
+    loss, g = lbm.mlp_gradient(_t(theta), _t(X), _t(T), loss_scale=S)
+    g = g.cpu().numpy().astype(np.float64)
+    lref, lsd, gref, sd = _gradient_reference(theta, X, T, S)
+    lg = float(loss.item())
+    print("gradient n=%d S=%g: loss %.7e exact %.7e (%.1f sd)" % (n, S, lg, lref, abs(lg - lref) / lsd), flush=True)
+    assert abs(lg - lref) <= 8 * lsd
+    z = np.abs(g - gref) / sd
+    k = 0
+    for name, shp in omlp.SHAPES:
+        m = int(np.prod(shp))
+        print("  %s: max %.2f sd, rms %.2f sd; sd / |g| (L2) %.1e" % (
+            name, z[k:k + m].max(), np.sqrt((z[k:k + m] ** 2).mean()),
+            np.linalg.norm(sd[k:k + m]) / np.linalg.norm(gref[k:k + m])), flush=True)
+        k += m
+    assert np.all(np.abs(g - gref) <= 8 * sd), int(np.argmax(z))
