@@ -468,7 +468,7 @@ def main():
             # the AA pattern alternates two sweep kernels (layouts 1 and 2)
             halves = ["1", "2"] if aa else ["0"]
             vks = [sweep_kernel(vl["width"], q, tn, bool(args.particles), h).replace(",", ", ") for h in halves]
-            vk = vks[0] if not aa else vks[0][:-1] + "1/2>"
+            vk = vks[0] if not aa else vks[0][:-2] + "1/2>"
             vt = None
             if args.particles == len(cfg["particles"]["radius"]):
                 ts = [measured_traffic(k_, cfg["name"], cfg["box"], vl) for k_ in vks]

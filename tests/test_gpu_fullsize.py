@@ -4,8 +4,8 @@ oracle on the same seeded inputs, with particles that move: their integer
 shifts change, so the map is rebuilt and the IS substep is imposed at new
 positions (section 2.2, third and fourth substeps; eq. 13-15).
 
-  - D2Q9 1024^2, 200 disks r = 10, FP32: every site, every F and T, the
-    shifts, the owner map and the site kinds.
+  - D2Q9 1024^2, 200 disks r = 10, FP32, 300 steps: every site, every F and
+    T, the shifts, the owner map and the site kinds.
   - D3Q19 256^3, 500 spheres r = 6, FP32: every site (compared slab by slab),
     every F and T, the shifts.
   - A sphere whose shift changes along all three axes in one step (not a
@@ -108,27 +108,33 @@ def test_disks_1024sq_200_full_size_fp32():
 def test_spheres_256cubed_500_moving_full_size_fp32():
     """The D3Q19 256^3 workload (tau 0.6, 500 spheres r = 6, density ratio
     1.2, gravity 1e-6, zero-net-force frame) with seeded initial velocities of
-    up to 0.03 lu/step per component, 40 steps in FP32; every site compared,
-    z-slab by z-slab."""
+    up to 0.03 lu/step per component, 60 steps in FP32; every site compared,
+    z-slab by z-slab.  A free sphere of density ratio 1.2 hands most of its
+    momentum to the fluid within a few steps (each step its 475 boundary sites
+    take its velocity), so every fourth sphere is kinematic (m = I = infinity,
+    its velocity imposed) to keep shifts changing."""
     cfg = wl.spheres_3d_config()
     p = dict(cfg["particles"])
-    p["u"] = wl.seeded_velocities(len(p["radius"]), 3, 0.03, seed=12)
+    n = len(p["radius"])
+    p["u"] = wl.seeded_velocities(n, 3, 0.03, seed=12)
+    p["mass"] = np.where(np.arange(n) % 4 == 0, np.inf, p["mass"])
+    p["inertia"] = np.where(np.arange(n) % 4 == 0, np.inf, p["inertia"])
     sim, ora = _pair(cfg, p, "fp32")
     w, g, k, ms = sim.autotune(reps=2)
     _say("D3Q19 256^3, 500 spheres, fp32, sweep launch (%d, %d, %d) %.3f ms" % (w, g, k, ms))
     sc = Scales(6.0)
     k0 = sim.shifts()
-    for t in range(0, 40, 10):
-        sim.step(10)
-        ora.step(10)
-        ko = sc.check(sim, ora, 1e-4, "step %d" % (t + 10))
+    for t in range(0, 60, 15):
+        sim.step(15)
+        ora.step(15)
+        ko = sc.check(sim, ora, 1e-4, "step %d" % (t + 15))
     moved = int((ko != k0).any(axis=1).sum())
     _say("  spheres whose shift changed: %d of 500" % moved)
-    assert moved >= 100
+    assert moved >= 50
     _, wts = oracle.lattice(19)
     fo = ora.get_f()
     fg = sim.get_distributions()
-    check_f(fg, fo, wts, "fp32", "40 steps, every site")
+    check_f(fg, fo, wts, "fp32", "60 steps, every site")
     del fg, fo
     assert np.array_equal(sim.site_kind(), ora.site_kind())
     sim.close()
