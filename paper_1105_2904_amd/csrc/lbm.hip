@@ -1,7 +1,8 @@
 // MI355X (gfx950) hot path of the site-based suspension lattice Boltzmann
 // method of dos Santos & Philippi, behind the C ABI of include/lbm.h.
 //
-// One time step is five launches on the caller's stream:
+// One time step is four launches on the caller's stream (five with the
+// near-contact closure):
 //   sweep      one streaming pass over every site, A -> B (HBM bound; SoA,
 //              x fastest, coalesced): pull-propagation of the previous step
 //              (whose IS substep is already in A), BGK collision with body
@@ -11,24 +12,26 @@
 //   reduce     one workgroup per particle: momentum dp and angular momentum dl
 //              of every owned BS site from its slot (no owner-map lookup:
 //              unowned slots carry a mark), deterministic wave-shuffle + LDS
-//              sums, release of the particle's stamps, and
-//              the list of particles close enough to collide.         eq. 6-9
+//              sums, the list of particles close enough to collide, and the
+//              list of particles whose sites may coincide with this one's
+//              after the translation.                                eq. 6-9
 //   particles  one workgroup per box: Newton-Euler update with buoyancy-
 //              corrected weight, hard-core collisions in lexicographic pair
 //              order, translation and integer shift.        eq. 10-11, 13, 16-19
-//   stamp      one to eight workgroups per particle: rebuild the owner map at
-//              the new shifts (lowest BS/IS entry index, hence lowest
-//              particle id; stored as 2e + [IS]).
-//                                                                    eq. 14-15
-//   prepare    one to eight workgroups per particle: the IS substep at the new
-//              positions (eq. 12) written in place into the post-collision
-//              state -- f^eq_i(rho_I, u_p' + omega_p' x r) at every owned IS
-//              site -- the flag of every ball site (every entry at a site
-//              writes the same value, read off the owner map) and, by the
-//              owning entry, the record of every owned BS site: the
+//   prepare    one to eight workgroups per particle: site ownership at the new
+//              shifts (lowest particle id among the BS/IS entries on a site,
+//              read from the kind grids of the particles that may share it),
+//              the IS substep at the new positions (eq. 12) written in place
+//              into the post-collision state -- f^eq_i(rho_I, u_p' + omega_p'
+//              x r) at every owned IS site -- the flags of the ball sites of a
+//              particle whose shift changed (and of the sites it left), and,
+//              by the owning entry, the record of every owned BS site: the
 //              rigid-body velocity u_p + omega x r of its next BS substep
 //              (eq. 5) and the owner entry; a BS entry whose site is held by
 //              another particle or a wall marks its slot unowned instead.
+// Balls too large for kind grids keep an owner map instead: reduce releases
+// it, a stamp launch rebuilds it at the new shifts (eq. 14-15) and prepare
+// reads it, one thread per entry.
 // The IS substep of step t acts on the post-collision populations of IS sites
 // just before they propagate; written into the state, it is what the sweep of
 // step t+1 pulls.  Outside every ball the sweep reads one flag byte and
@@ -38,6 +41,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -60,6 +64,14 @@ constexpr uint8_t kSiteBall = 1;  // site flag: some ball covers the site
 constexpr uint8_t kSiteBS = 2;    // site flag: an owned BS site (its record is valid)
 constexpr int kCandMax = 64;        // close neighbours listed per particle
 constexpr double kMargin = 1.0;     // candidate search margin (lattice units)
+// Particles whose site sets could share a site at the new shifts of a step:
+// centres within r_i + r_j + kShareMargin at the start of the step.  Each
+// centre moves by less than 1/2 in a step (the collision bound) and the
+// translated template's centre x0 + k lies within sqrt(3)/2 of the true one,
+// so two balls that share a site after the step started closer than
+// r_i + r_j + 2 (1/2 + sqrt(3)/2) = r_i + r_j + 2.74.
+constexpr double kShareMargin = 3.0;
+constexpr int kNbrMax = 128;        // such neighbours listed per particle
 constexpr int kSweepBlock = 256;
 constexpr int kTileMax = 512;        // widest tile of the ensemble sweep
 constexpr int kBoundaryBlock = 256;  // reduce workgroup (128 for balls of at most kSmallBall entries)
@@ -196,6 +208,11 @@ struct DevParticles {
   double* fc;                                              // [n][3] closure force of the step
   int *cand;                                               // [n][kCandMax]
   int *pairs;                                              // [n*kCandMax][2]
+  // kind grids (per-particle ownership, no owner map in the step):
+  int *orgp, *moved;     // [n][3] origin before the last translation; [n] shift changed in it
+  int *kg0, *kgR;        // [n] first byte of the particle's kind grid, its half-width R
+  int *nbr_n, *nbr;      // [n], [n][kNbrMax]: particles that may share a site with it
+  uint8_t* kgrid;        // per particle (2R+1)^d kinds of its template (0 none, 1 BS, 2 IS, 3 interior)
 };
 
 __device__ __forceinline__ Geo geo_of(const Boxes& B, const DevParticles& P, int p) {
@@ -736,7 +753,7 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int dim, Boxes
     // inputs first, as above
     const double m = P.m[p], r = P.rad[p];
     double u[3], x[3], x0[3];
-    int k0[3], b0[3];
+    int k0[3], b0[3], og[3];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
       u[a] = staged ? s_u[a * kStageParticles + p - p0] : P.u[3 * p + a];
@@ -744,6 +761,7 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int dim, Boxes
       x0[a] = P.x0[3 * p + a];
       k0[a] = P.k[3 * p + a];
       b0[a] = P.b0[3 * p + a];
+      og[a] = P.org[3 * p + a];
     }
     if (G.walls && !isinf(m)) {
       // contact with a wall after the pairs: the normal velocity reverses
@@ -755,7 +773,10 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int dim, Boxes
       }
     }
     int moved = 0;
-    for (int a = 0; a < 3; a++) P.u[3 * p + a] = u[a];
+    for (int a = 0; a < 3; a++) {
+      P.u[3 * p + a] = u[a];
+      P.orgp[3 * p + a] = og[a];  // the site sets before this translation
+    }
     for (int a = 0; a < dim; a++) {
       const double xn = x[a] + u[a];
       P.x[3 * p + a] = xn;
@@ -767,6 +788,7 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int dim, Boxes
     // a shift along all three axes at once (not a D3Q19 link) can take an IS
     // site outside the ball the sweep kept densities for
     P.jump[p] = moved == 3;
+    P.moved[p] = moved != 0;
   }
 }
 
@@ -775,14 +797,18 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int dim, Boxes
 // of the particle's stamps, and the list of particles close enough to collide
 // this step.  One workgroup per particle.
 // ---------------------------------------------------------------------------
-template <int NB>
+// GRID: site ownership is settled from kind grids after the particle update,
+// so the map and flags are not released here, and the particles that may
+// share a site with this one (both directions) are listed for it; otherwise
+// every claim and flag of the particle is released at its current shift.
+template <int NB, bool GRID>
 __global__ __launch_bounds__(NB) void k_reduce(int* __restrict__ own,
                                                             uint8_t* __restrict__ flag, const double* __restrict__ slot,
                                                             DevParticles P, DevEntries E, Boxes BX,
                                                             double rho0, double margin, int* status) {
   constexpr int kWaves = NB / 64;
   __shared__ double s_part[kWaves][6];
-  __shared__ int s_cnt[kWaves];
+  __shared__ int s_cnt[kWaves], s_cnt2[kWaves];
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
@@ -801,21 +827,20 @@ __global__ __launch_bounds__(NB) void k_reduce(int* __restrict__ own,
   const double xpx = P.x[3 * p], xpy = P.x[3 * p + 1], xpz = P.x[3 * p + 2];
   const double rp = P.rad[p];
   const int np = G.p1;
-  auto close_to = [&](double xj, double yj, double zj, double rj) {
+  // squared minimum-image distance to (xj, yj, zj)
+  auto dist2 = [&](double xj, double yj, double zj) {
     double dx = xj - xpx, dy = yj - xpy, dz = zj - xpz;
     dx -= G.nx * floor(dx / G.nx + 0.5);
     dy -= G.ny * floor(dy / G.ny + 0.5);
     if (G.nz > 1) dz -= G.nz * floor(dz / G.nz + 0.5);
-    const double lim = rp + rj + margin;
-    return dx * dx + dy * dy + dz * dz <= lim * lim;
+    return dx * dx + dy * dy + dz * dz;
   };
-  auto is_close = [&](int j) {
-    if (j >= np) return false;
-    return close_to(P.x[3 * j], P.x[3 * j + 1], P.x[3 * j + 2], P.rad[j]);
-  };
+  // the scan runs over j > p, or over the whole box for the site-sharing list
+  const int bq = BX.nbox == 1 ? 0 : P.box[p];
+  const int jstart = GRID ? (bq == 0 ? 0 : BX.tab[bq - 1].p1) : p + 1;
   // the first chunk's positions, loaded without a branch (lanes past the box's
   // last particle load this particle's own) and tested after the sums
-  const int j1 = p + 1 + tid;
+  const int j1 = jstart + tid;
   const int jc = j1 < np ? j1 : p;
   const double xj1 = P.x[3 * jc], yj1 = P.x[3 * jc + 1], zj1 = P.x[3 * jc + 2], rj1 = P.rad[jc];
 
@@ -865,11 +890,14 @@ __global__ __launch_bounds__(NB) void k_reduce(int* __restrict__ own,
       const int t = tb + j * NB + tid;
       if (t >= ne) continue;
       const int pk = pkv[j];
-      const int s = site_of(G, wrap1(ox0 + off_x(pk), G.nx), wrap1(oy0 + off_y(pk), G.ny), wrap1(oz0 + off_z(pk), G.nz));
-      flag[s] = 0;
-      // every claim at s is released this step, the owner's among them, so
-      // each BS/IS entry clears s without asking whose it is
-      if (entry_kind(pk) != 3) own[s] = kEmpty;
+      if constexpr (!GRID) {
+        const int s = site_of(G, wrap1(ox0 + off_x(pk), G.nx), wrap1(oy0 + off_y(pk), G.ny),
+                              wrap1(oz0 + off_z(pk), G.nz));
+        flag[s] = 0;
+        // every claim at s is released this step, the owner's among them, so
+        // each BS/IS entry clears s without asking whose it is
+        if (entry_kind(pk) != 3) own[s] = kEmpty;
+      }
     }
   }
 #pragma unroll
@@ -891,29 +919,57 @@ __global__ __launch_bounds__(NB) void k_reduce(int* __restrict__ own,
   // the collision test this step while every speed stays below kMargin / 2
   // (checked in the particle update), and, with margin >= the closure's gap,
   // every pair the closure acts on.
-  int base = 0;
-  for (int j0 = p + 1; j0 < np; j0 += NB) {
+  // With GRID, the same scan lists in increasing j every other particle of
+  // the box within r_p + r_j + kShareMargin: those whose sites may coincide
+  // with this particle's after the translation of this step.
+  int base = 0, nbase = 0;
+  for (int j0 = jstart; j0 < np; j0 += NB) {
     const int j = j0 + tid;
-    const bool close = j0 == p + 1 ? j < np && close_to(xj1, yj1, zj1, rj1) : is_close(j);
+    const int jj = j < np ? j : p;
+    double xj = xj1, yj = yj1, zj = zj1, rj = rj1;
+    if (j0 != jstart) {
+      xj = P.x[3 * jj];
+      yj = P.x[3 * jj + 1];
+      zj = P.x[3 * jj + 2];
+      rj = P.rad[jj];
+    }
+    const double d2 = dist2(xj, yj, zj);
+    const double lim = rp + rj + margin, lims = rp + rj + kShareMargin;
+    const bool close = j < np && j > p && d2 <= lim * lim;
+    const bool share = GRID && j < np && j != p && d2 <= lims * lims;
     const unsigned long long bal = __ballot(close);
-    if (lane == 0) s_cnt[wv] = __popcll(bal);
+    const unsigned long long bal2 = __ballot(share);
+    if (lane == 0) {
+      s_cnt[wv] = __popcll(bal);
+      s_cnt2[wv] = __popcll(bal2);
+    }
     __syncthreads();
-    int off = base;
-    int tot = 0;
+    int off = base, off2 = nbase;
+    int tot = 0, tot2 = 0;
     for (int w = 0; w < kWaves; w++) {
-      if (w < wv) off += s_cnt[w];
+      if (w < wv) {
+        off += s_cnt[w];
+        off2 += s_cnt2[w];
+      }
       tot += s_cnt[w];
+      tot2 += s_cnt2[w];
     }
     if (close) {
       const int idx = off + __popcll(bal & ((1ull << lane) - 1ull));
       if (idx < kCandMax) P.cand[p * kCandMax + idx] = j;
     }
+    if (share) {
+      const int idx = off2 + __popcll(bal2 & ((1ull << lane) - 1ull));
+      if (idx < kNbrMax) P.nbr[(size_t)p * kNbrMax + idx] = j;
+    }
     base += tot;
+    nbase += tot2;
     __syncthreads();
   }
   if (tid == 0) {
     P.cand_n[p] = base < kCandMax ? base : kCandMax;
-    if (base > kCandMax) atomicOr(status, kStatusCollision);
+    if (GRID) P.nbr_n[p] = nbase < kNbrMax ? nbase : kNbrMax;
+    if (base > kCandMax || (GRID && nbase > kNbrMax)) atomicOr(status, kStatusCollision);
   }
 
 }
@@ -1209,20 +1265,50 @@ __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own,
   else if (entry_kind(pk) == 1) slot[4 * (size_t)e] = kSlotUnowned;
 }
 
-// The same per particle (one workgroup each): the particle's box, origin and
-// velocities are uniform loads, and its entries, in raster order, give
-// row-coalesced loads of the owner map and of the densities at their own
-// sites (four entries per thread in flight at once).
+// ---------------------------------------------------------------------------
+// K5 with kind grids (balls of at most kPrepareLocalMax bounding-box sites):
+// the work of k_prepare, one to eight workgroups per particle (rows of
+// kGridBlock entries dealt round-robin; entries in raster order, so the
+// loads at their own sites are row-coalesced), with the owner of a site
+// settled without an owner map.  A site is owned by the lowest particle id among those whose
+// BS or IS entry lies on it at the new shifts (none on wall sites); only the
+// particles listed as sharing candidates (k_reduce) can have such an entry on
+// one of this particle's sites, and their kind grids say which.  Flags are
+// written only where they can change: at the sites of a particle whose shift
+// changed in this step (its new sites, and its old sites that no ball of it
+// covers any more, cleared or handed to the neighbour covering them) and, with
+// flags_all, at every ball site (after particles are added).  Every writer of
+// a flag computes it from the same final map, so they agree.
+// ---------------------------------------------------------------------------
+// Kind of particle q's template at site (x, y, z) of its box, with q's
+// origin (og) and kind-grid half-width R: 0 unless the site is one of its
+// ball sites.  Template offsets are shorter than half the box, so the
+// minimum-image offset is the only candidate.
+template <int DIM>
+__device__ __forceinline__ int kind_at(const uint8_t* __restrict__ kg, int R, int ox, int oy, int oz, const Geo& G,
+                                       int x, int y, int z) {
+  int dx = x - ox, dy = y - oy, dz = z - oz;
+  dx += dx > G.nx / 2 ? -G.nx : (dx < -(G.nx / 2) ? G.nx : 0);
+  dy += dy > G.ny / 2 ? -G.ny : (dy < -(G.ny / 2) ? G.ny : 0);
+  dz += dz > G.nz / 2 ? -G.nz : (dz < -(G.nz / 2) ? G.nz : 0);
+  if (dx < -R || dx > R || dy < -R || dy > R || dz < -R || dz > R) return 0;
+  const int W = 2 * R + 1;
+  return kg[DIM == 3 ? ((dz + R) * W + (dy + R)) * W + (dx + R) : (dy + R) * W + (dx + R)];
+}
+
+constexpr int kGridBlock = kPrepareBlock;
+
 template <int Q, typename T, bool NTS>
-__global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __restrict__ own,
-                                                        uint8_t* __restrict__ flag, typename Store<T>::C* __restrict__ vel,
-                                                        double* __restrict__ slot,
-                                                        const typename Store<T>::C* __restrict__ drho,
-                                                        T* __restrict__ S, DevParticles P, DevEntries E, Boxes BX,
-                                                        double rho0, int pending, int lay, int split) {
+__global__ __launch_bounds__(kGridBlock) void k_prepare_grid(uint8_t* __restrict__ flag,
+                                                             typename Store<T>::C* __restrict__ vel,
+                                                             double* __restrict__ slot,
+                                                             const typename Store<T>::C* __restrict__ drho,
+                                                             T* __restrict__ S, DevParticles P, DevEntries E, Boxes BX,
+                                                             double rho0, int pending, int lay, int split,
+                                                             int flags_all) {
   using C = typename Store<T>::C;
-  // split workgroups per particle: rows of kPrepareBlock consecutive entries
-  // are dealt to them round-robin, kEnt rows per pass
+  constexpr int DIM = Q == 9 ? 2 : 3;
+  __shared__ int s_nb[kNbrMax][6];  // neighbour id, origin, kind-grid start and half-width
   const int p = blockIdx.x / split, part = blockIdx.x % split;
   const int tid = threadIdx.x;
   const Geo G = geo_of(BX, P, p);
@@ -1233,38 +1319,78 @@ __global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __re
   const C cupx = (C)upx, cupy = (C)upy, cupz = (C)upz, cwx = (C)wx, cwy = (C)wy, cwz = (C)wz;
   const int e0 = P.ent0[p], ne = P.nbs[p] + P.nis[p] + P.nin[p];
   const bool jump = P.jump[p] != 0;
+  const bool moved = P.moved[p] != 0;
+  const bool flags = flags_all != 0 || moved;
+  const int nn = P.nbr_n[p];
+  const int Rp = P.kgR[p];
+  const uint8_t* kgp = P.kgrid + P.kg0[p];
+  if (nn > 0) {
+    for (int t = tid; t < nn; t += kGridBlock) {
+      const int q = P.nbr[(size_t)p * kNbrMax + t];
+      s_nb[t][0] = q;
+      s_nb[t][1] = P.org[3 * q];
+      s_nb[t][2] = P.org[3 * q + 1];
+      s_nb[t][3] = P.org[3 * q + 2];
+      s_nb[t][4] = P.kg0[q];
+      s_nb[t][5] = P.kgR[q];
+    }
+    __syncthreads();
+  }
+  // owner (lowest id claiming the site, INT_MAX for none) and its kind at
+  // (x, y, z), given this particle's own kind there (0 if none); cov: some
+  // ball covers the site
+  auto settle = [&](int x, int y, int z, int kp, int& oid, int& okind, bool& cov) {
+    const bool wall = G.walls && wall_site(G, x, y, z);
+    oid = INT_MAX;
+    okind = 0;
+    cov = kp != 0;
+    if (!wall && (kp == 1 || kp == 2)) {
+      oid = p;
+      okind = kp;
+    }
+    for (int t = 0; t < nn; t++) {
+      const int q = s_nb[t][0];
+      if (q > oid && cov) break;  // ascending ids: no lower claimer left
+      const int kq = kind_at<DIM>(P.kgrid + s_nb[t][4], s_nb[t][5], s_nb[t][1], s_nb[t][2], s_nb[t][3], G, x, y, z);
+      cov = cov || kq != 0;
+      if (!wall && (kq == 1 || kq == 2) && q < oid) {
+        oid = q;
+        okind = kq;
+      }
+    }
+  };
   constexpr int kEnt = 4;
-  for (int rb = part; rb * kPrepareBlock < ne; rb += split * kEnt) {
-    // loads without per-lane branches, so that all of them are in flight
-    // together: lanes past the last entry load the last entry again and drop
-    // it (a row wholly past it is skipped by the whole workgroup)
-    int pkv[kEnt], sv[kEnt], ov[kEnt];
+  for (int rb = part; rb * kGridBlock < ne; rb += split * kEnt) {
+    int pkv[kEnt];
     C dv[kEnt];
+    int sv[kEnt];
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
-      const int t0 = (rb + j * split) * kPrepareBlock;
+      const int t0 = (rb + j * split) * kGridBlock;
       if (t0 >= ne) break;  // the same for the whole workgroup
       pkv[j] = E.off[e0 + min(t0 + tid, ne - 1)];
     }
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
-      if ((rb + j * split) * kPrepareBlock >= ne) break;
+      if ((rb + j * split) * kGridBlock >= ne) break;
       const int pk = pkv[j];
       sv[j] = site_of(G, wrap1(ox0 + off_x(pk), G.nx), wrap1(oy0 + off_y(pk), G.ny), wrap1(oz0 + off_z(pk), G.nz));
-      ov[j] = own[sv[j]];
       dv[j] = drho[sv[j]];  // used only at an IS site the substep claims
     }
 #pragma unroll 1
     for (int j = 0; j < kEnt; j++) {
-      const int t = (rb + j * split) * kPrepareBlock + tid;
+      const int t = (rb + j * split) * kGridBlock + tid;
       if (t >= ne) continue;
       const int e = e0 + t;
       const int pk = pkv[j];
-      const int ox = off_x(pk), oy = off_y(pk), oz = off_z(pk);
+      const int ox = off_x(pk), oy = off_y(pk), oz = off_z(pk), kp = entry_kind(pk);
       const int s = sv[j];
-      const int o = ov[j];
-      if (pending && o == 2 * e + 1) {
-        const int sxx = wrap1(ox0 + ox, G.nx), syy = wrap1(oy0 + oy, G.ny), szz = wrap1(oz0 + oz, G.nz);
+      const int sxx = wrap1(ox0 + ox, G.nx), syy = wrap1(oy0 + oy, G.ny), szz = wrap1(oz0 + oz, G.nz);
+      int oid, okind;
+      bool cov;
+      settle(sxx, syy, szz, kp, oid, okind, cov);
+      const bool mine = oid == p;
+      if (pending && mine && kp == 2) {
         double dr;
         if (jump) {
           dr = 0;
@@ -1273,20 +1399,31 @@ __global__ __launch_bounds__(kPrepareBlock) void k_prepare_local(const int* __re
         } else {
           dr = (double)dv[j];
         }
-        impose_is<Q, T, NTS>(S, BX.PS, lay, G, sxx, syy, szz, dr, (C)((double)ox - phx), (C)((double)oy - phy), (C)((double)oz - phz), cupx,
-                        cupy, cupz, cwx, cwy, cwz, rho0);
+        impose_is<Q, T, NTS>(S, BX.PS, lay, G, sxx, syy, szz, dr, (C)((double)ox - phx), (C)((double)oy - phy),
+                             (C)((double)oz - phz), cupx, cupy, cupz, cwx, cwy, cwz, rho0);
       }
-      // every entry at s writes the same flag, from the owner map
-      flag[s] = o != kEmpty && !(o & 1) ? kSiteBS : kSiteBall;
-      if (o == 2 * e) {
-        // the owner's record: its particle's velocities are at hand
+      if (flags) flag[s] = okind == 1 ? kSiteBS : kSiteBall;
+      if (mine && kp == 1) {
         const double rx = (double)ox - phx, ry = (double)oy - phy, rz = (double)oz - phz;
         vel[4 * (size_t)s] = (C)(upx + (wy * rz - wz * ry));
         vel[4 * (size_t)s + 1] = (C)(upy + (wz * rx - wx * rz));
         vel[4 * (size_t)s + 2] = (C)(upz + (wx * ry - wy * rx));
         vel[4 * (size_t)s + 3] = idx_as<C>(e);
-      } else if (entry_kind(pk) == 1) {
+      } else if (kp == 1) {
         slot[4 * (size_t)e] = kSlotUnowned;  // a BS entry whose site another particle or a wall holds
+      }
+      if (moved) {
+        // the site this entry held before the translation: cleared unless a
+        // ball still covers it (this particle's new ball covers it through
+        // one of its own entries, which writes the flag there)
+        const int xo = wrap1(P.orgp[3 * p] + ox, G.nx), yo = wrap1(P.orgp[3 * p + 1] + oy, G.ny),
+                  zo = wrap1(P.orgp[3 * p + 2] + oz, G.nz);
+        if (kind_at<DIM>(kgp, Rp, ox0, oy0, oz0, G, xo, yo, zo) == 0) {
+          int qo, qk;
+          bool qc;
+          settle(xo, yo, zo, 0, qo, qk, qc);
+          flag[site_of(G, xo, yo, zo)] = !qc ? 0 : (qk == 1 ? kSiteBS : kSiteBall);
+        }
       }
     }
   }
@@ -1378,6 +1515,7 @@ struct Layout {
   size_t f[2], drho, own, flag, status, stage;
   size_t x, x0, u, om, phi, fext, dP, dL, F, T, m, I, rad, b0, k, org, ent0, nbs, nis, nin, jump, box, cand_n, cand,
       pairs;
+  size_t orgp, moved, kg0, kgR, nbr_n, nbr, kgrid;
   size_t off, pid, slot, vel;
   size_t boxes, fbt, tiles, fc, clo;
   int64_t max_ent, max_tiles;
@@ -1406,15 +1544,36 @@ BoxSet make_boxset(int nbox, const int32_t* dims) {
 
 size_t store_size(int storage) { return storage == LBM_FP64 ? 8 : storage == LBM_FP32 ? 4 : 2; }
 
-// Population planes are padded past a multiple of 256 sites by 256 more:
-// plane strides that are multiples of large powers of two put a site's
-// populations on the same DRAM banks (measured on the 256^3 sweep: 2.7 %
-// slower with two arrays, 6 % for the odd half of the AA pattern).
-int64_t plane_stride(int64_t sites) { return (sites + 255) / 256 * 256 + 256; }
+// Population planes are padded past a multiple of 256 sites: plane strides
+// that are multiples of large powers of two put a site's populations on the
+// same DRAM banks (with 256 sites of padding the 256^3 two-array sweep ran
+// 2.7 % faster than unpadded, the odd half of the AA pattern 6 %).  The best
+// padding of a large plane differs with the storage size (measured on the
+// 256^3 box with 500 spheres, whole step, paddings of 64 to 8448 sites):
+// FP64 256 sites; FP32 2048 (1.4 % faster than 256); FP16 and BF16 8448
+// (0.7 %).  Planes under 2^20 sites keep 256.
+int64_t plane_stride(int64_t sites, int storage) {
+  const int64_t pad = sites < ((int64_t)1 << 20) || storage == LBM_FP64 ? 256 : storage == LBM_FP32 ? 2048 : 8448;
+  return (sites + 255) / 256 * 256 + pad;
+}
 
 // The sweep addresses a site within a population plane with a 32-bit byte
 // offset (the plane's own base is a 64-bit scalar).
 bool plane_fits(int storage, int64_t sites) { return (uint64_t)sites * store_size(storage) <= ((uint64_t)1 << 32); }
+
+// Bytes of one particle's kind grid: offsets of a template lie within
+// floor(r + 1/2) of its origin along every axis (|o - phi| <= r, |phi| <= 1/2).
+int kind_grid_half(double r) { return (int)std::floor(r + 0.5); }
+size_t kind_grid_bytes(int dim, double r) {
+  const size_t w = 2 * (size_t)kind_grid_half(r) + 1;
+  return dim == 2 ? w * w : w * w * w;
+}
+
+// Balls whose bounding box holds at most kPrepareLocalMax sites take the
+// per-particle kernels and settle site ownership from kind grids; larger ones
+// keep an owner map that every step rebuilds, and a prepare pass with one
+// thread per entry.
+bool uses_kind_grids(int dim, double rmax) { return kind_grid_bytes(dim, rmax) <= (size_t)kPrepareLocalMax; }
 
 int64_t entries_per_particle(int dim, double rmax) {
   const int64_t e = 2 * (int64_t)std::ceil(rmax) + 1;
@@ -1434,7 +1593,7 @@ Layout make_layout(const lbm_params& p, const BoxSet& bs) {
     cur += (bytes + kAlign - 1) / kAlign * kAlign;
     return at;
   };
-  const size_t fb = (size_t)p.lattice * plane_stride(N) * store_size(p.storage);
+  const size_t fb = (size_t)p.lattice * plane_stride(N, p.storage) * store_size(p.storage);
   L.f[0] = take(fb);
   L.f[1] = p.aa ? L.f[0] : take(fb);  // the AA pattern updates one array in place
   L.drho = take((size_t)N * (p.storage == LBM_FP64 ? 8 : 4));
@@ -1451,6 +1610,13 @@ Layout make_layout(const lbm_params& p, const BoxSet& bs) {
   L.ent0 = take(sizeof(int) * np); L.nbs = take(sizeof(int) * np); L.nis = take(sizeof(int) * np);
   L.nin = take(sizeof(int) * np);
   L.jump = take(sizeof(int) * np);
+  L.orgp = take(sizeof(int) * 3 * np);
+  L.moved = take(sizeof(int) * np);
+  L.kg0 = take(sizeof(int) * np);
+  L.kgR = take(sizeof(int) * np);
+  L.nbr_n = take(sizeof(int) * np);
+  L.nbr = take(sizeof(int) * np * kNbrMax);
+  L.kgrid = take(uses_kind_grids(dim, p.max_radius) ? (size_t)np * kind_grid_bytes(dim, p.max_radius) : 0);
   L.box = take(sizeof(int) * np);
   L.cand_n = take(sizeof(int) * np);
   L.cand = take(sizeof(int) * np * kCandMax);
@@ -1572,7 +1738,9 @@ struct lbm_ctx {
   int64_t nent;
   std::vector<double> h_x0, h_rad, h_m, h_I, h_fext;
   std::vector<int> h_off, h_pid, h_nbs, h_nis, h_nin;
-  bool prep_local;    // prepare with workgroups per particle (else one thread per entry)
+  bool grids;         // kind grids settle ownership in the per-particle prepare (else an
+                      // owner map rebuilt every step and one thread per entry)
+  size_t kg_used;     // bytes of kind grids in use
   int prep_split;     // most workgroups per particle of the per-particle prepare
   bool small_ball;    // the largest ball holds at most kSmallBall entries
   bool prof;
@@ -1618,15 +1786,15 @@ Boxes boxes_arg(const lbm_ctx* c) {
 // every ball site for the next sweep.  Up to eight workgroups per particle for
 // balls of moderate size, one thread per entry otherwise.
 template <int Q, typename T, bool NTS>
-int launch_prepare_as(lbm_ctx* c, int pending) {
+int launch_prepare_as(lbm_ctx* c, int pending, int flags_all) {
   using C = typename Store<T>::C;
-  if (c->prep_local) {
+  if (c->grids) {
     // split workgroups per particle only while the particles alone leave the
     // GPU short of workgroups (about 8 per CU)
     const int split = std::max(1, std::min(c->prep_split, 2048 / std::max(c->np, 1)));
-    k_prepare_local<Q, T, NTS><<<c->np * split, kPrepareBlock, 0, c->stream>>>(
-        c->own, c->flag, (C*)c->vel, c->slot, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
-        c->prm.rho0, pending, state_layout(c), split);
+    k_prepare_grid<Q, T, NTS><<<c->np * split, kGridBlock, 0, c->stream>>>(
+        c->flag, (C*)c->vel, c->slot, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c), c->prm.rho0,
+        pending, state_layout(c), split, flags_all);
   } else {
     k_prepare<Q, T, NTS><<<blocks_for(c->nent), 256, 0, c->stream>>>(
         c->own, c->flag, (C*)c->vel, c->slot, (const C*)c->drho, (T*)c->f[c->cur], c->P, c->E, boxes_arg(c),
@@ -1637,11 +1805,11 @@ int launch_prepare_as(lbm_ctx* c, int pending) {
 }
 
 template <int Q, typename T>
-int launch_prepare(lbm_ctx* c, int pending) {
+int launch_prepare(lbm_ctx* c, int pending, int flags_all) {
   if (c->nent == 0) return LBM_OK;
   // streaming IS stores for the AA pattern only
-  return state_layout(c) == kLayAB ? launch_prepare_as<Q, T, false>(c, pending)
-                                   : launch_prepare_as<Q, T, true>(c, pending);
+  return state_layout(c) == kLayAB ? launch_prepare_as<Q, T, false>(c, pending, flags_all)
+                                   : launch_prepare_as<Q, T, true>(c, pending, flags_all);
 }
 
 // Tile list {box, y, z, x0} of width w, box by box, rows in z, y order.
@@ -1775,12 +1943,21 @@ int launch_step(lbm_ctx* c) {
     const double margin = c->closure ? std::max(kMargin, c->clo_h) : kMargin;
     // half-size workgroups for many small balls: two waves then hold every
     // entry, and twice as many particles' workgroups fit the GPU at once
-    if (c->small_ball && c->np > 1024)
-      k_reduce<128><<<c->np, 128, 0, c->stream>>>(c->own, c->flag, c->slot, c->P, c->E, bx, c->prm.rho0, margin,
-                                                  c->status);
-    else
-      k_reduce<kBoundaryBlock><<<c->np, kBoundaryBlock, 0, c->stream>>>(c->own, c->flag, c->slot, c->P, c->E, bx,
-                                                                          c->prm.rho0, margin, c->status);
+    if (c->small_ball && c->np > 1024) {
+      if (c->grids)
+        k_reduce<128, true><<<c->np, 128, 0, c->stream>>>(c->own, c->flag, c->slot, c->P, c->E, bx, c->prm.rho0,
+                                                          margin, c->status);
+      else
+        k_reduce<128, false><<<c->np, 128, 0, c->stream>>>(c->own, c->flag, c->slot, c->P, c->E, bx, c->prm.rho0,
+                                                           margin, c->status);
+    } else {
+      if (c->grids)
+        k_reduce<kBoundaryBlock, true><<<c->np, kBoundaryBlock, 0, c->stream>>>(c->own, c->flag, c->slot, c->P, c->E,
+                                                                                bx, c->prm.rho0, margin, c->status);
+      else
+        k_reduce<kBoundaryBlock, false><<<c->np, kBoundaryBlock, 0, c->stream>>>(
+            c->own, c->flag, c->slot, c->P, c->E, bx, c->prm.rho0, margin, c->status);
+    }
     if (c->closure)
       k_closure<<<1, 256, 0, c->stream>>>(c->P, c->np, bx, c->d_clo, c->clo_h,
                                           c->prm.rho0 * (c->prm.tau - 0.5) / 3.0, c->prm.tau, c->status);
@@ -1788,12 +1965,14 @@ int launch_step(lbm_ctx* c) {
       k_particles<kParticleBlock><<<1, kParticleBlock, 0, c->stream>>>(c->P, c->dim, bx, c->status);
     else
       k_particles<kBoxParticleBlock><<<c->nbox, kBoxParticleBlock, 0, c->stream>>>(c->P, c->dim, bx, c->status);
-    const int split = std::max(1, std::min(c->prep_split, 2048 / std::max(c->np, 1)));  // as for prepare
-    k_stamp_particles<<<c->np * split, 256, 0, c->stream>>>(c->own, c->P, c->E, bx, split);
+    if (!c->grids) {
+      const int split = std::max(1, std::min(c->prep_split, 2048 / std::max(c->np, 1)));  // as for prepare
+      k_stamp_particles<<<c->np * split, 256, 0, c->stream>>>(c->own, c->P, c->E, bx, split);
+    }
     HIP_TRY(hipGetLastError());
   }
   c->cur = 1 - c->cur;  // f[cur] now holds this step's post-collision state
-  if (c->np > 0) return launch_prepare<Q, T>(c, 1);
+  if (c->np > 0) return launch_prepare<Q, T>(c, 1, 0);
   return LBM_OK;
 }
 
@@ -1876,6 +2055,18 @@ void build_template(int q, double r, const double phi[3], std::vector<int>& out,
         out.push_back(pack_entry(x, y, z, kind));
         (kind == 1 ? *nbs : kind == 2 ? *nis : *nin) += 1;
       }
+}
+
+// The owner map of the current shifts, for read-outs: contexts with kind
+// grids keep none between steps, so every site is emptied and every BS/IS
+// entry claims its site again (lowest entry, hence lowest particle id).
+int refresh_owner_map(lbm_ctx* c) {
+  if (!c->grids) return LBM_OK;
+  k_fill<int><<<blocks_for(c->NT), 256, 0, c->stream>>>(c->own, c->NT, kEmpty);
+  if (c->nent > 0)
+    k_stamp<<<blocks_for(c->nent), 256, 0, c->stream>>>(c->own, c->P, c->E, boxes_arg(c), 0, (int)c->nent);
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
 }
 
 int check_status(lbm_ctx* c) {
@@ -1974,7 +2165,7 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
   c->dim = prm->lattice == LBM_D2Q9 ? 2 : 3;
   c->nbox = nbox;
   c->NT = bset.NT;
-  c->PS = plane_stride(bset.NT);
+  c->PS = plane_stride(bset.NT, prm->storage);
   int64_t off = 0;
   for (int b = 0; b < nbox; b++) {
     const int nx = dims[3 * b], ny = dims[3 * b + 1], nz = dims[3 * b + 2];
@@ -2030,7 +2221,11 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
                       (int*)(w + L.ent0),    (int*)(w + L.nbs),    (int*)(w + L.nis),
                       (int*)(w + L.nin),     (int*)(w + L.cand_n), (int*)(w + L.jump),
                       (int*)(w + L.box),     (double*)(w + L.fc),
-                      (int*)(w + L.cand),    (int*)(w + L.pairs)};
+                      (int*)(w + L.cand),    (int*)(w + L.pairs),
+                      (int*)(w + L.orgp),    (int*)(w + L.moved),
+                      (int*)(w + L.kg0),     (int*)(w + L.kgR),
+                      (int*)(w + L.nbr_n),   (int*)(w + L.nbr),
+                      (uint8_t*)(w + L.kgrid)};
   c->d_clo = (float*)(w + L.clo);
   c->closure = 0;
   c->clo_h = 0.0;
@@ -2047,8 +2242,8 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
     // one workgroup per particle while the largest ball's bounding box, (2 floor(r + 1/2)
     // + 1)^d sites and so a bound on its entries, stays within kPrepareLocalMax; larger
     // balls spread their entries over the grid
-    const int64_t W = 2 * (int64_t)std::floor(prm->max_radius + 0.5) + 1;
-    c->prep_local = (c->dim == 3 ? W * W * W : W * W) <= kPrepareLocalMax;
+    c->grids = uses_kind_grids(c->dim, prm->max_radius);
+    c->kg_used = 0;
     // about one workgroup per kPrepareBlock entries of the largest ball (its
     // volume), so that a particle's scattered IS stores spread over CUs
     const double r = prm->max_radius;
@@ -2182,6 +2377,45 @@ static int add_impl(lbm_ctx* c, int32_t bx, int32_t n, const double* x, const do
     hpid.insert(hpid.end(), (size_t)(nb + ni + nn), c->np + j);
   }
   if (c->nent + (int64_t)hoff.size() > c->L.max_ent) return LBM_ECAPACITY;
+  // Kind grids of the new particles and the lists of particles that may share
+  // a site (the box's particles, old and new, within r_i + r_j + kShareMargin)
+  std::vector<uint8_t> hkg;
+  std::vector<int> hkg0(n), hkgR(n), hnbr_n, hnbr;
+  int pbox0 = c->np;  // first particle of box bx
+  while (pbox0 > 0 && c->h_box[pbox0 - 1] == bx) pbox0--;
+  if (c->grids) {
+    size_t at = c->kg_used;
+    for (int j = 0; j < n; j++) {
+      const int R = kind_grid_half(radius[j]), W = 2 * R + 1;
+      const size_t nb = dim == 2 ? (size_t)W * W : (size_t)W * W * W;
+      const size_t g0 = hkg.size();
+      hkg.resize(g0 + nb, 0);
+      const int eb = hent0[j] - (int)c->nent, ee = eb + hnbs[j] + hnis[j] + hnin[j];
+      for (int e = eb; e < ee; e++) {
+        const int v = hoff[e];
+        const int ox = (int)(int8_t)(v & 0xff), oy = (int)(int8_t)((v >> 8) & 0xff), oz = (int)(int8_t)((v >> 16) & 0xff);
+        if (std::abs(ox) > R || std::abs(oy) > R || std::abs(oz) > R) return LBM_EINVAL;  // cannot happen
+        const size_t idx = dim == 2 ? (size_t)(oy + R) * W + (ox + R) : ((size_t)(oz + R) * W + (oy + R)) * W + (ox + R);
+        hkg[g0 + idx] = (uint8_t)entry_kind(v);
+      }
+      hkg0[j] = (int)(at + g0);
+      hkgR[j] = R;
+    }
+    const int nb_all = c->np + n - pbox0;
+    hnbr_n.assign(nb_all, 0);
+    hnbr.assign((size_t)nb_all * kNbrMax, 0);
+    auto pos = [&](int q) { return q < c->np ? &cur[3 * q] : &x[3 * (q - c->np)]; };
+    auto rad = [&](int q) { return q < c->np ? c->h_rad[q] : radius[q - c->np]; };
+    for (int a = pbox0; a < c->np + n; a++)
+      for (int b = pbox0; b < c->np + n; b++) {
+        if (a == b) continue;
+        const double lim = rad(a) + rad(b) + kShareMargin;
+        if (dist2(pos(a), pos(b)) > lim * lim) continue;
+        int& cnt = hnbr_n[a - pbox0];
+        if (cnt >= kNbrMax) return LBM_ECAPACITY;
+        hnbr[(size_t)(a - pbox0) * kNbrMax + cnt++] = b;
+      }
+  }
   // Every argument has been checked: from here on only a HIP error can fail
   // the call.  The host bookkeeping is then put back as it was, and the
   // context is marked failed (the device map may already hold stamps of the
@@ -2229,18 +2463,29 @@ static int add_impl(lbm_ctx* c, int32_t bx, int32_t n, const double* x, const do
   UP(c->P.F + 3 * p0, zero.data(), 3 * (size_t)n);
   UP(c->P.T + 3 * p0, zero.data(), 3 * (size_t)n);
   UP(c->P.fc + 3 * p0, zero.data(), 3 * (size_t)n);
+  UP(c->P.orgp + 3 * p0, horg.data(), 3 * (size_t)n);
+  const std::vector<int> izero((size_t)n, 0);
+  UP(c->P.moved + p0, izero.data(), (size_t)n);
+  UP(c->P.jump + p0, izero.data(), (size_t)n);
+  if (c->grids) {
+    UP(c->P.kgrid + c->kg_used, hkg.data(), hkg.size());
+    UP(c->P.kg0 + p0, hkg0.data(), (size_t)n);
+    UP(c->P.kgR + p0, hkgR.data(), (size_t)n);
+    UP(c->P.nbr_n + pbox0, hnbr_n.data(), hnbr_n.size());
+    UP(c->P.nbr + (size_t)pbox0 * kNbrMax, hnbr.data(), hnbr.size());
+  }
 #undef UP
   // stamp the new entries into the current map (existing owners have lower ids)
   for (int b = bx; b < c->nbox; b++) c->boxes[b].p1 = c->np + n;  // later boxes are still empty
   c->G = c->boxes[0];
-  if (e1 > e0) {  // particles this small may hold no site at all
+  if (e1 > e0 && !c->grids) {  // particles this small may hold no site at all
     k_stamp<<<blocks_for(e1 - e0), 256, 0, c->stream>>>(c->own, c->P, c->E, boxes_arg(c), (int)e0, (int)e1);
     if (hipGetLastError() != hipSuccess) return fail(LBM_EHIP);
   }
   c->nent = e1;
   c->np += n;
-  // records of every ball site, with nothing pending (written into the state above)
-  const int prc = DISPATCH(c, launch_prepare, c, 0);
+  // flags and records of every ball site, with nothing pending
+  const int prc = DISPATCH(c, launch_prepare, c, 0, 1);
   if (prc != LBM_OK) return fail(prc);
   if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(LBM_EHIP);
   // fluid body force of every box: user value, plus the opposite of the
@@ -2257,6 +2502,7 @@ static int add_impl(lbm_ctx* c, int32_t bx, int32_t n, const double* x, const do
           c->prm.body_force[a] - (c->prm.zero_net_force ? tot[3 * b + a] / (double)c->boxes[b].N : 0.0);
   if (upload_boxes(c) != LBM_OK) return fail(LBM_EHIP);
   // the call has succeeded: the host copies of the particle set grow
+  c->kg_used += hkg.size();
   for (int j = 0; j < n; j++) {
     c->h_x0.insert(c->h_x0.end(), &hx[3 * j], &hx[3 * j] + 3);
     c->h_rad.push_back(radius[j]);
@@ -2519,6 +2765,8 @@ int lbm_fields(lbm_ctx* c, double* rho, double* u, int32_t* owner) {
     }
   }
   if (owner) {
+    const int orc = refresh_owner_map(c);
+    if (orc != LBM_OK) return orc;
     std::vector<int> m(c->NT);
     HIP_TRY(hipMemcpyAsync(m.data(), c->own, sizeof(int) * c->NT, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -2530,6 +2778,8 @@ int lbm_fields(lbm_ctx* c, double* rho, double* u, int32_t* owner) {
 int lbm_site_kind(lbm_ctx* c, int8_t* kind) {
   if (!c || !kind) return LBM_EINVAL;
   if (c->failed) return LBM_EHIP;
+  const int orc = refresh_owner_map(c);
+  if (orc != LBM_OK) return orc;
   std::vector<int> m(c->NT);
   HIP_TRY(hipMemcpyAsync(m.data(), c->own, sizeof(int) * c->NT, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));

@@ -76,7 +76,8 @@ def test_plane_limit_and_aa_layout():
     rc1, n1 = _rc_workspace(aa=True)
     assert rc1 == rc2 == 0
     # one FP32 array of q planes less (planes padded to a multiple of 256 sites
-    # plus 256), one 4-double-per-site staging area more (256-B alignment)
+    # plus 256 below 2^20 sites), one 4-double-per-site staging area more
+    # (256-B alignment)
     N = 16 ** 3
     stride = (N + 255) // 256 * 256 + 256
     expect = 19 * stride * 4 - 4 * 8 * N
