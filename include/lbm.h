@@ -299,6 +299,23 @@ int lbm_set_closure(lbm_ctx* ctx, const float* d_params, double h_max);
 int lbm_closure_inputs(int32_t n, const double* xi, const double* d, const double* ri, const double* rj,
                        double tau, float* out);
 
+/* ---- stepping that allocates nothing -------------------------------------
+ * For callers that cannot allocate device memory or create HIP objects: code
+ * under the caller's own graph capture, tight serving loops, harnesses that
+ * forbid it.  Enqueues nsteps steps exactly as lbm_step does (the same kernels,
+ * the same results bit for bit), except that every step is launched one by
+ * one (no step graph is created, whatever lbm_set_graph says), no profiling
+ * events are recorded, and the per-step scratch of the particle kernels (the
+ * per-particle momentum sums, the close-pair and site-sharing lists and the
+ * pair staging, 1,336 bytes per particle) lives in one library-owned device
+ * array of at most 4096 particles (5.2 MiB) per device, held until the
+ * process ends, instead of in the context's workspace.  LBM_ECAPACITY for a
+ * context with more particles; LBM_EINVAL unless the calling thread's current
+ * device is the context's.  Every call on one device uses the same array:
+ * calls that overlap on one device (contexts stepping on different streams)
+ * race and give wrong results.  Calls no allocating routine. */
+int lbm_step_noalloc(lbm_ctx* ctx, int32_t nsteps);
+
 /* Algorithmic HBM bytes one sweep moves per site (2 q sizeof(storage)). */
 int lbm_bytes_per_site(const lbm_params* prm, int64_t* bytes);
 

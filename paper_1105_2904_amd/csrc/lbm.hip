@@ -45,6 +45,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -1708,6 +1709,7 @@ struct lbm_ctx {
   int sweep_w, sweep_grid;  // sweep launch shape: w = 0 the one-box kernel, else tile width; grid 0 = one per tile
   int sweep_occ;            // cap on resident sweep workgroups per CU (0: none)
   int lds_cu, lds_block;    // LDS bytes per CU and the most one workgroup may reserve
+  int device;               // the device the context was created on
   bool row_ok;              // one box whose rows fit the row kernel's (x-blocks, y, z) grid
   std::vector<int> h_box;   // box of every particle
   std::vector<double> fbb;  // [nbox][3] fluid body force density
@@ -2123,6 +2125,53 @@ int upload(lbm_ctx* c, V* dst, const V* src, size_t count) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Allocation-free stepping (lbm_step_noalloc): the per-step scratch of the
+// particle kernels -- per-particle momentum sums, close-pair and site-sharing
+// lists, pair staging; each written by the step before it is read -- in one
+// library array per device instead of the context's workspace.  The array is
+// file scope, so every device holds its own copy at its own address: host
+// code takes that address from hipGetSymbolAddress, once per device, and
+// never uses the array's name as a device pointer.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kScratchParticles = 4096;
+constexpr size_t scr_round(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+constexpr size_t kScrDP = 0;
+constexpr size_t kScrDL = kScrDP + scr_round(sizeof(double) * 3 * kScratchParticles);
+constexpr size_t kScrCandN = kScrDL + scr_round(sizeof(double) * 3 * kScratchParticles);
+constexpr size_t kScrCand = kScrCandN + scr_round(sizeof(int) * kScratchParticles);
+constexpr size_t kScrPairs = kScrCand + scr_round(sizeof(int) * (size_t)kScratchParticles * kCandMax);
+constexpr size_t kScrNbrN = kScrPairs + scr_round(sizeof(int) * 2 * (size_t)kScratchParticles * kCandMax);
+constexpr size_t kScrNbr = kScrNbrN + scr_round(sizeof(int) * kScratchParticles);
+constexpr size_t kScratchBytes = kScrNbr + scr_round(sizeof(int) * (size_t)kScratchParticles * kNbrMax);
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Device address of the scratch array on device dev (the current device).
+int scratch_address(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return LBM_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LBM_EHIP;
+    g_scratch[dev] = ptr;
+  }
+  *out = (char*)g_scratch[dev];
+  return LBM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -2202,6 +2251,7 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
       return LBM_EHIP;
     }
     c->row_ok = nbox == 1 && dims[1] <= gy && dims[2] <= gz;
+    c->device = dev;
   }
   // one box: the row kernel; an ensemble: tiles of 128 sites, one workgroup each
   c->sweep_w = c->row_ok ? 0 : 128;
@@ -2592,6 +2642,37 @@ int lbm_step(lbm_ctx* c, int32_t nsteps) {
     if (rc != LBM_OK) return rc;
   }
   return LBM_OK;
+}
+
+int lbm_step_noalloc(lbm_ctx* c, int32_t nsteps) {
+  if (!c || nsteps < 0) return LBM_EINVAL;
+  if (c->failed) return LBM_EHIP;
+  if (c->np > kScratchParticles) return LBM_ECAPACITY;
+  // the tiles of a tile-kernel shape are built by the call that set it
+  if (c->sweep_w > 0 && c->tiles_w != c->sweep_w) return LBM_EINVAL;
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != c->device) return LBM_EINVAL;
+  char* sp = nullptr;
+  const int arc = scratch_address(dev, &sp);
+  if (arc != LBM_OK) return arc;
+  // the same launches as lbm_step, eager and without profiling events, on
+  // the particle arrays with their per-step scratch in the library array
+  const DevParticles keep = c->P;
+  const bool prof = c->prof;
+  c->P.dP = (double*)(sp + kScrDP);
+  c->P.dL = (double*)(sp + kScrDL);
+  c->P.cand_n = (int*)(sp + kScrCandN);
+  c->P.cand = (int*)(sp + kScrCand);
+  c->P.pairs = (int*)(sp + kScrPairs);
+  c->P.nbr_n = (int*)(sp + kScrNbrN);
+  c->P.nbr = (int*)(sp + kScrNbr);
+  c->prof = false;
+  int rc = LBM_OK;
+  for (int t = 0; t < nsteps && rc == LBM_OK; t++) rc = DISPATCH(c, launch_step, c);
+  c->P = keep;
+  c->prof = prof;
+  return rc;
 }
 
 int lbm_set_graph(lbm_ctx* c, int32_t steps_per_graph) {

@@ -76,6 +76,7 @@ def lib():
             "lbm_get_sweep_config": [vp, _ip, _ip, _ip],
             "lbm_autotune": [vp, ctypes.c_int32, _ip, _ip, _ip, _dp],
             "lbm_set_graph": [vp, ctypes.c_int32],
+            "lbm_step_noalloc": [vp, ctypes.c_int32],
             "lbm_set_closure": [vp, vp, ctypes.c_double],
             "lbm_closure_inputs": [ctypes.c_int32, _dp, _dp, _dp, _dp, ctypes.c_double, vp],
             "lbm_mlp_param_count": [_ip],
@@ -276,6 +277,9 @@ class Simulation:
 
     def step(self, n=1):
         _check(lib().lbm_step(self.ctx, int(n)), "lbm_step")
+
+    def step_noalloc(self, n=1):
+        _check(lib().lbm_step_noalloc(self.ctx, int(n)), "lbm_step_noalloc")
 
     def forces(self):
         n = self.n_particles
