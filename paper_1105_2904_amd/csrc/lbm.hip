@@ -366,45 +366,24 @@ __device__ __forceinline__ const T* plane_at(const T* p, int i, int64_t N, int s
 __device__ __forceinline__ float recip(float v) { return __builtin_amdgcn_rcpf(v); }
 __device__ __forceinline__ double recip(double v) { return 1.0 / v; }
 
-// The work of one site (x, y, z) of a box of nx x ny x nz sites whose first
-// site is `off`; fbt holds 3 w_i c_i . f_b of that box.  NTL: streaming
-// (non-temporal) population loads.  Each pulled value is read once, so on
-// long rows they only keep dead lines out of the caches; in an ensemble of
-// narrow boxes the lines shared by neighbouring tiles are worth keeping.
-template <int Q, typename T, bool PART, int LAY, bool NTL>
-__device__ __forceinline__ void sweep_site(const T* A, T* B, const SweepArgs<Q, typename Store<T>::C>& a,
-                                           const SiteArgs<T>& sa, int x, int y, int z, int nx, int ny, int nz,
-                                           int off, const typename Store<T>::C (&fbt)[Q]) {
+// Collision of one site from the populations g it pulled, in place: BGK with
+// body force (eq. 1-3), the site's density deviation kept at ball sites, the
+// BS substep at an owned BS site (eq. 5-7; its post-collision moments to the
+// owner entry's slot) and the wall equilibrium on wall layers.  s is the
+// site, fl its flag (0 without particles).  16-bit storage collides on the
+// stored numbers h_i = g_i / (w_i sigma): there the weight cancels from the
+// equilibrium, h_i^eq = (drho + rho (3cu + 9/2 cu^2 - 3/2 u^2)) / sigma,
+// which saves the per-direction scalings; FP32/FP64 collide on the
+// deviations g_i.
+template <int Q, typename T, bool PART>
+__device__ __forceinline__ void collide_site(typename Store<T>::C (&g)[Q],
+                                             const SweepArgs<Q, typename Store<T>::C>& a, const SiteArgs<T>& sa,
+                                             int s, int fl, int x, int y, int z, int nx, int ny, int nz,
+                                             const typename Store<T>::C (&fbt)[Q]) {
   using L = Lattice<Q>;
   using C = typename Store<T>::C;
-  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-  const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
-  const int s = off + x + nx * (y + ny * z);
-
-  // the flag is issued first and waited on only after the collision
-  const int fl = PART ? (int)sa.flag[s] : 0;
-  // 16-bit storage collides on the stored numbers h_i = g_i / (w_i sigma):
-  // there the weight cancels from the equilibrium, h_i^eq = (drho + rho (3cu
-  // + 9/2 cu^2 - 3/2 u^2)) / sigma, which saves the per-direction scalings;
-  // FP32/FP64 collide on the deviations g_i.
   constexpr bool kRaw = std::is_same<T, _Float16>::value || std::is_same<T, bf16s>::value;
   const C inv_sig = (C)(1.0 / pop_unit<T>(1.0));
-  // Addresses: the plane of population i starts at a wave-uniform base (scalar
-  // registers) and the site is a 32-bit byte offset into it (a context keeps
-  // N sizeof(T) <= 2^32), so no 64-bit vector arithmetic per access.
-  C g[Q];
-#pragma unroll
-  for (int i = 0; i < Q; i++) {
-    // f_i arriving at x: pulled from x - c_i, or found at x itself in the
-    // post-propagation half of the AA pattern
-    const int sx = LAY == kLayAAStream ? x : (L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x));
-    const int sy = LAY == kLayAAStream ? y : (L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y));
-    const int sz = LAY == kLayAAStream ? z : (L::cz(i) > 0 ? zm : (L::cz(i) < 0 ? zp : z));
-    const T* src = plane_at(A, LAY == kLayAASwap ? opposite<Q>(i) : i, a.N, off + sx + nx * (sy + ny * sz));
-    const C h = NTL ? Store<T>::ldnt(src) : Store<T>::ld(src);
-    g[i] = kRaw ? h : h * (C)pop_unit<T>(L::w(i));
-  }
   C drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int i = 0; i < Q; i++) {
@@ -491,6 +470,43 @@ __device__ __forceinline__ void sweep_site(const T* A, T* B, const SweepArgs<Q, 
       }
     }
   }
+}
+
+// The work of one site (x, y, z) of a box of nx x ny x nz sites whose first
+// site is `off`; fbt holds 3 w_i c_i . f_b of that box.  NTL: streaming
+// (non-temporal) population loads.  Each pulled value is read once, so on
+// long rows they only keep dead lines out of the caches; in an ensemble of
+// narrow boxes the lines shared by neighbouring tiles are worth keeping.
+template <int Q, typename T, bool PART, int LAY, bool NTL>
+__device__ __forceinline__ void sweep_site(const T* A, T* B, const SweepArgs<Q, typename Store<T>::C>& a,
+                                           const SiteArgs<T>& sa, int x, int y, int z, int nx, int ny, int nz,
+                                           int off, const typename Store<T>::C (&fbt)[Q]) {
+  using L = Lattice<Q>;
+  using C = typename Store<T>::C;
+  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+  const int s = off + x + nx * (y + ny * z);
+
+  // the flag is issued first and waited on only after the collision
+  const int fl = PART ? (int)sa.flag[s] : 0;
+  constexpr bool kRaw = std::is_same<T, _Float16>::value || std::is_same<T, bf16s>::value;
+  // Addresses: the plane of population i starts at a wave-uniform base (scalar
+  // registers) and the site is a 32-bit byte offset into it (a context keeps
+  // N sizeof(T) <= 2^32), so no 64-bit vector arithmetic per access.
+  C g[Q];
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    // f_i arriving at x: pulled from x - c_i, or found at x itself in the
+    // post-propagation half of the AA pattern
+    const int sx = LAY == kLayAAStream ? x : (L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x));
+    const int sy = LAY == kLayAAStream ? y : (L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y));
+    const int sz = LAY == kLayAAStream ? z : (L::cz(i) > 0 ? zm : (L::cz(i) < 0 ? zp : z));
+    const T* src = plane_at(A, LAY == kLayAASwap ? opposite<Q>(i) : i, a.N, off + sx + nx * (sy + ny * sz));
+    const C h = NTL ? Store<T>::ldnt(src) : Store<T>::ld(src);
+    g[i] = kRaw ? h : h * (C)pop_unit<T>(L::w(i));
+  }
+  collide_site<Q, T, PART>(g, a, sa, s, fl, x, y, z, nx, ny, nz, fbt);
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     // f*_i(x): at x in the next array, in the opposite slot at x, or pushed to
@@ -1755,6 +1771,9 @@ struct lbm_ctx {
 // halves with the step parity (cur), kept like the buffer index of two arrays.
 int state_layout(const lbm_ctx* c) { return c->prm.aa ? (c->cur == 0 ? kLayAAStream : kLayAASwap) : kLayAB; }
 
+// Launch shapes: widths 64..512 are the tile kernel, 0 the row kernel of one box.
+bool tile_width(int w) { return w == 64 || w == 128 || w == 256 || w == 512; }
+
 #define HIP_TRY(expr)                          \
   do {                                         \
     if ((expr) != hipSuccess) return LBM_EHIP; \
@@ -2313,7 +2332,8 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
   else
     k_fill_records<float><<<blocks_for(c->NT), 256, 0, c->stream>>>((float*)c->vel, c->NT);
   if (hipGetLastError() != hipSuccess || upload_boxes(c) != LBM_OK ||
-      (c->sweep_w > 0 && build_tiles(c, c->sweep_w) != LBM_OK) || hipStreamSynchronize(c->stream) != hipSuccess) {
+      (tile_width(c->sweep_w) && build_tiles(c, c->sweep_w) != LBM_OK) ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
     delete c;
     return LBM_EHIP;
   }
@@ -2625,7 +2645,7 @@ static int ensure_graph(lbm_ctx* c) {
 int lbm_step(lbm_ctx* c, int32_t nsteps) {
   if (!c || nsteps < 0) return LBM_EINVAL;
   if (c->failed) return LBM_EHIP;
-  if (c->sweep_w > 0) {
+  if (tile_width(c->sweep_w)) {
     const int rc = build_tiles(c, c->sweep_w);
     if (rc != LBM_OK) return rc;
   }
@@ -2649,7 +2669,7 @@ int lbm_step_noalloc(lbm_ctx* c, int32_t nsteps) {
   if (c->failed) return LBM_EHIP;
   if (c->np > kScratchParticles) return LBM_ECAPACITY;
   // the tiles of a tile-kernel shape are built by the call that set it
-  if (c->sweep_w > 0 && c->tiles_w != c->sweep_w) return LBM_EINVAL;
+  if (tile_width(c->sweep_w) && c->tiles_w != c->sweep_w) return LBM_EINVAL;
   int dev = -1;
   HIP_TRY(hipGetDevice(&dev));
   if (dev != c->device) return LBM_EINVAL;
@@ -2685,14 +2705,14 @@ int lbm_set_graph(lbm_ctx* c, int32_t steps_per_graph) {
 
 int lbm_set_sweep_config(lbm_ctx* c, int32_t width, int32_t grid, int32_t blocks_per_cu) {
   if (!c || grid < 0 || !occ_ok(c, blocks_per_cu)) return LBM_EINVAL;
-  if (width != 0 && width != 64 && width != 128 && width != 256 && width != 512) return LBM_EINVAL;
+  if (width != 0 && !tile_width(width)) return LBM_EINVAL;
   if (width == 0 && !c->row_ok) return LBM_EINVAL;  // the row kernel covers one box
-  if (width > 0) {
+  if (tile_width(width)) {
     const int rc = build_tiles(c, width);
     if (rc != LBM_OK) return rc;
   }
   c->sweep_w = width;
-  c->sweep_grid = width > 0 ? grid : 0;
+  c->sweep_grid = tile_width(width) ? grid : 0;
   c->sweep_occ = blocks_per_cu;
   return LBM_OK;
 }
@@ -2734,7 +2754,7 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* width, int32_t* grid, int32_
   double best = 1e300;
   Cand win = {c->sweep_w, c->sweep_grid, c->sweep_occ};
   for (const Cand& cd : cands) {
-    if (cd.w > 0 && (rc = build_tiles(c, cd.w)) != LBM_OK) break;
+    if (tile_width(cd.w) && (rc = build_tiles(c, cd.w)) != LBM_OK) break;
     if ((rc = DISPATCH(c, launch_sweep, c, cd.w, cd.g, cd.occ)) != LBM_OK) break;  // warm-up
     if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = LBM_EHIP; break; }
     for (int r = 0; r < reps && rc == LBM_OK; r++) rc = DISPATCH(c, launch_sweep, c, cd.w, cd.g, cd.occ);
