@@ -7,7 +7,7 @@ particle update, map rebuild, IS substep) over the box.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage fp32|fp64|fp16|bf16]
                   [--no-cpu-baseline] [--no-variants] [--no-autotune] [--workload spheres-3d|disks-2d]
-                  [--accuracy-steps N]
+                  [--accuracy-steps N] [--no-batched] [--no-disks-2d]
 
 The FP32 run also times the FP16 and BF16 storage variants of the same
 workload ("variants") and, outside every timed region, runs the workload for
@@ -336,6 +336,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip timing the 64-box D2Q9 ensemble (batched) variant")
     ap.add_argument("--batched-steps", type=int, default=200)
+    ap.add_argument("--no-disks-2d", action="store_true",
+                    help="skip timing the D2Q9 1024^2 workload with 200 disks (disks_2d)")
     ap.add_argument("--accuracy-steps", type=int, default=2000,
                     help="steps of the storage-accuracy leg (FP32/FP16/BF16 against FP64; 0 skips it)")
     args = ap.parse_args()
@@ -498,8 +500,9 @@ def main():
         print("closure network timed", file=sys.stderr, flush=True)
         out["batched"] = ensemble_rates(torch, lbm, wl, args.batched_steps, args.warmup)
         print("batched ensemble timed", file=sys.stderr, flush=True)
-        out["disks_2d"] = disks_2d_rates(torch, lbm, wl, 2000, args.warmup)
-        print("D2Q9 1024^2 workload timed", file=sys.stderr, flush=True)
+        if not args.no_disks_2d:
+            out["disks_2d"] = disks_2d_rates(torch, lbm, wl, 2000, args.warmup)
+            print("D2Q9 1024^2 workload timed", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline and args.workload == "spheres-3d":
         print("cpu baseline: %d + %d oracle steps" % (args.cpu_steps, args.cpu_steps_all), file=sys.stderr,
               flush=True)
