@@ -192,7 +192,7 @@ struct Boxes {
   const Geo* tab;
   int nbox;
   int64_t NT;  // sites of all boxes
-  int64_t PS;  // stride of a population plane (NT padded; see plane_stride)
+  int64_t PS;  // stride N of the population array (see pop_elem, plane_stride)
 };
 
 // A site of the wall layers of a closed axis (particles never own these).
@@ -351,15 +351,42 @@ __device__ __forceinline__ bool wall_velocity(const SweepArgs<Q, C>& a, int x, i
   return true;
 }
 
-// Element `site` of plane i of a [q][N] array: uniform plane base plus a
-// 32-bit byte offset (valid while N sizeof(T) <= 2^32).
+// Population layout.  16-bit storage keeps q planes [q][N] (N the padded
+// plane stride); FP32 and FP64 keep blocks of kPopBlock consecutive sites,
+// each block holding its q populations one after another:
+// [N / kPopBlock][q][kPopBlock], N a multiple of kPopBlock.  A row of 256
+// sites then writes one contiguous 19 KB block instead of 19 pieces 64 MB
+// apart (particle-free FP32 D3Q19 256^3 sweep: 412-416 us blocked against
+// 423-432 us in planes; FP16 is 12 us slower blocked).
+constexpr int kPopBlock = 256;
+inline bool pop_blocked(int storage) { return storage == LBM_FP32 || storage == LBM_FP64; }
 template <typename T>
-__device__ __forceinline__ T* plane_at(T* p, int i, int64_t N, int site) {
-  return (T*)((char*)p + (size_t)i * (size_t)N * sizeof(T) + (uint32_t)site * (uint32_t)sizeof(T));
+__host__ __device__ constexpr bool pop_blocked_t() {
+  return std::is_same<T, float>::value || std::is_same<T, double>::value;
 }
-template <typename T>
-__device__ __forceinline__ const T* plane_at(const T* p, int i, int64_t N, int site) {
-  return (const T*)((const char*)p + (size_t)i * (size_t)N * sizeof(T) + (uint32_t)site * (uint32_t)sizeof(T));
+// Element of f_i at site s of a population array with stride N.
+__host__ __device__ __forceinline__ int64_t pop_elem(bool blocked, int q, int i, int64_t s, int64_t N) {
+  return blocked ? (s / kPopBlock) * ((int64_t)q * kPopBlock) + (int64_t)i * kPopBlock + s % kPopBlock
+                 : (int64_t)i * N + s;
+}
+template <int Q, typename T>
+__host__ __device__ __forceinline__ int64_t pop_elem(int i, int64_t s, int64_t N) {
+  return pop_elem(pop_blocked_t<T>(), Q, i, s, N);
+}
+// Address of f_i at `site` (the sweep's form): planes take a wave-uniform
+// plane base plus a 32-bit byte offset (valid while N sizeof(T) <= 2^32);
+// blocks take the block's byte offset from one 32 x 32 -> 64-bit product.
+template <int Q, typename T>
+__device__ __forceinline__ T* pop_at(T* p, int i, int64_t N, int site) {
+  if constexpr (pop_blocked_t<T>())
+    return (T*)((char*)p + (size_t)((uint32_t)site / kPopBlock) * (size_t)(Q * kPopBlock * sizeof(T)) +
+                (uint32_t)(i * kPopBlock + (int)((uint32_t)site % kPopBlock)) * (uint32_t)sizeof(T));
+  else
+    return (T*)((char*)p + (size_t)i * (size_t)N * sizeof(T) + (uint32_t)site * (uint32_t)sizeof(T));
+}
+template <int Q, typename T>
+__device__ __forceinline__ const T* pop_at(const T* p, int i, int64_t N, int site) {
+  return pop_at<Q, T>(const_cast<T*>(p), i, N, site);
 }
 
 // 1/rho: the hardware reciprocal in FP32 (1 ulp), a division in FP64.
@@ -502,7 +529,7 @@ __device__ __forceinline__ void sweep_site(const T* A, T* B, const SweepArgs<Q, 
     const int sx = LAY == kLayAAStream ? x : (L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x));
     const int sy = LAY == kLayAAStream ? y : (L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y));
     const int sz = LAY == kLayAAStream ? z : (L::cz(i) > 0 ? zm : (L::cz(i) < 0 ? zp : z));
-    const T* src = plane_at(A, LAY == kLayAASwap ? opposite<Q>(i) : i, a.N, off + sx + nx * (sy + ny * sz));
+    const T* src = pop_at<Q, T>(A, LAY == kLayAASwap ? opposite<Q>(i) : i, a.N, off + sx + nx * (sy + ny * sz));
     const C h = NTL ? Store<T>::ldnt(src) : Store<T>::ld(src);
     g[i] = kRaw ? h : h * (C)pop_unit<T>(L::w(i));
   }
@@ -514,7 +541,7 @@ __device__ __forceinline__ void sweep_site(const T* A, T* B, const SweepArgs<Q, 
     const int dx = LAY == kLayAASwap ? (L::cx(i) > 0 ? xp : (L::cx(i) < 0 ? xm : x)) : x;
     const int dy = LAY == kLayAASwap ? (L::cy(i) > 0 ? yp : (L::cy(i) < 0 ? ym : y)) : y;
     const int dz = LAY == kLayAASwap ? (L::cz(i) > 0 ? zp : (L::cz(i) < 0 ? zm : z)) : z;
-    T* dst = plane_at(B, LAY == kLayAAStream ? opposite<Q>(i) : i, a.N, off + dx + nx * (dy + ny * dz));
+    T* dst = pop_at<Q, T>(B, LAY == kLayAAStream ? opposite<Q>(i) : i, a.N, off + dx + nx * (dy + ny * dz));
     if constexpr (kRaw)
       Store<T>::st(dst, g[i]);
     else
@@ -1183,12 +1210,13 @@ __global__ __launch_bounds__(256) void k_closure(DevParticles P, int np, Boxes B
 // ---------------------------------------------------------------------------
 // Element of f*_i of site (x, y, z) of box G in a post-collision state of
 // layout lay (kLayAB, or either half of the AA pattern).
-template <int Q>
+template <int Q, typename T>
 __device__ __forceinline__ size_t coll_index(int lay, int i, const Geo& G, int x, int y, int z, int64_t NT) {
   using L = Lattice<Q>;
   if (lay == kLayAAStream)
-    return (size_t)i * NT + site_of(G, wrap1(x + L::cx(i), G.nx), wrap1(y + L::cy(i), G.ny), wrap1(z + L::cz(i), G.nz));
-  return (size_t)(lay == kLayAASwap ? opposite<Q>(i) : i) * NT + site_of(G, x, y, z);
+    return (size_t)pop_elem<Q, T>(
+        i, site_of(G, wrap1(x + L::cx(i), G.nx), wrap1(y + L::cy(i), G.ny), wrap1(z + L::cz(i), G.nz)), NT);
+  return (size_t)pop_elem<Q, T>(lay == kLayAASwap ? opposite<Q>(i) : i, site_of(G, x, y, z), NT);
 }
 
 // Streaming store of one stored population value.
@@ -1218,7 +1246,7 @@ __device__ __forceinline__ void impose_is(T* __restrict__ S, int64_t NT, int lay
   for (int i = 0; i < Q; i++) {
     const C cu = C(L::cx(i)) * vx + C(L::cy(i)) * vy + C(L::cz(i)) * vz;
     const T v = pop_enc<Q, T>(i, (double)(C(L::w(i)) * (dc + rho * (C(3) * cu + C(4.5) * cu * cu - usq))));
-    T* const dst = S + coll_index<Q>(lay, i, G, x, y, z, NT);
+    T* const dst = S + coll_index<Q, T>(lay, i, G, x, y, z, NT);
     // NTS (the AA pattern, whose next sweep reads and rewrites these lines in
     // place): streaming stores keep the partly written lines out of the
     // caches; with two arrays they only move the same cost from the sweep here
@@ -1267,7 +1295,7 @@ __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own,
     if (P.jump[p]) {
       dr = 0;
 #pragma unroll
-      for (int j = 0; j < Q; j++) dr += (double)pop_ld<Q, T>(S + coll_index<Q>(lay, j, G, x, y, z, BX.PS), j);
+      for (int j = 0; j < Q; j++) dr += (double)pop_ld<Q, T>(S + coll_index<Q, T>(lay, j, G, x, y, z, BX.PS), j);
     } else {
       dr = (double)drho[s];
     }
@@ -1412,7 +1440,7 @@ __global__ __launch_bounds__(kGridBlock) void k_prepare_grid(uint8_t* __restrict
         if (jump) {
           dr = 0;
 #pragma unroll
-          for (int k = 0; k < Q; k++) dr += (double)pop_ld<Q, T>(S + coll_index<Q>(lay, k, G, sxx, syy, szz, BX.PS), k);
+          for (int k = 0; k < Q; k++) dr += (double)pop_ld<Q, T>(S + coll_index<Q, T>(lay, k, G, sxx, syy, szz, BX.PS), k);
         } else {
           dr = (double)dv[j];
         }
@@ -1450,7 +1478,7 @@ __global__ __launch_bounds__(kGridBlock) void k_prepare_grid(uint8_t* __restrict
 // Read-out and set-up kernels (off the step loop).
 // ---------------------------------------------------------------------------
 // Moments of sites s0 .. s0 + cnt - 1 of box G (box-local indices); PS is
-// the stride of a population plane.
+// the stride of the population array.
 template <int Q, typename T>
 __global__ void k_moments(const T* __restrict__ A, double* __restrict__ rho, double* __restrict__ u,
                           Geo G, int64_t PS, double rho0, int64_t s0, int64_t cnt, int lay) {
@@ -1467,7 +1495,7 @@ __global__ void k_moments(const T* __restrict__ A, double* __restrict__ rho, dou
     const int sx = here ? x : wrap(x - L::cx(i), G.nx), sy = here ? y : wrap(y - L::cy(i), G.ny),
               sz = here ? z : wrap(z - L::cz(i), G.nz);
     const int plane = lay == kLayAASwap ? opposite<Q>(i) : i;
-    const double g = (double)pop_ld<Q, T>(A + (size_t)plane * PS + site_of(G, sx, sy, sz), i);
+    const double g = (double)pop_ld<Q, T>(A + pop_elem<Q, T>(plane, site_of(G, sx, sy, sz), PS), i);
     drho += g;
     j[0] += L::cx(i) * g;
     j[1] += L::cy(i) * g;
@@ -1490,7 +1518,7 @@ __global__ void k_shift(const T* __restrict__ A, T* __restrict__ B, Geo G, int64
   for (int i = 0; i < Q; i++) {
     const int sx = wrap(x - dir * L::cx(i), G.nx), sy = wrap(y - dir * L::cy(i), G.ny),
               sz = wrap(z - dir * L::cz(i), G.nz);
-    B[(size_t)i * PS + G.off + s] = A[(size_t)i * PS + site_of(G, sx, sy, sz)];
+    B[pop_elem<Q, T>(i, G.off + s, PS)] = A[pop_elem<Q, T>(i, site_of(G, sx, sy, sz), PS)];
   }
 }
 
@@ -1561,21 +1589,22 @@ BoxSet make_boxset(int nbox, const int32_t* dims) {
 
 size_t store_size(int storage) { return storage == LBM_FP64 ? 8 : storage == LBM_FP32 ? 4 : 2; }
 
-// Population planes are padded past a multiple of 256 sites: plane strides
-// that are multiples of large powers of two put a site's populations on the
-// same DRAM banks (with 256 sites of padding the 256^3 two-array sweep ran
-// 2.7 % faster than unpadded, the odd half of the AA pattern 6 %).  The best
-// padding of a large plane differs with the storage size (measured on the
-// 256^3 box with 500 spheres, whole step, paddings of 64 to 8448 sites):
-// FP64 256 sites; FP32 2048 (1.4 % faster than 256); FP16 and BF16 8448
-// (0.7 %).  Planes under 2^20 sites keep 256.
+// Stride N of the population array (see pop_elem).  Blocked storages: the
+// sites rounded up to whole blocks.  Planes are padded past a multiple of 256
+// sites: plane strides that are multiples of large powers of two put a site's
+// populations on the same DRAM banks (with 256 sites of padding the 256^3
+// two-array sweep ran 2.7 % faster than unpadded).  For 16-bit planes of at
+// least 2^20 sites 8448 sites of padding were best (0.7 % faster than 256;
+// whole 256^3 step with 500 spheres, paddings of 64 to 8448 sites).
 int64_t plane_stride(int64_t sites, int storage) {
-  const int64_t pad = sites < ((int64_t)1 << 20) || storage == LBM_FP64 ? 256 : storage == LBM_FP32 ? 2048 : 8448;
+  if (pop_blocked(storage)) return (sites + kPopBlock - 1) / kPopBlock * kPopBlock;
+  const int64_t pad = sites < ((int64_t)1 << 20) ? 256 : 8448;
   return (sites + 255) / 256 * 256 + pad;
 }
 
 // The sweep addresses a site within a population plane with a 32-bit byte
-// offset (the plane's own base is a 64-bit scalar).
+// offset (the plane's own base is a 64-bit scalar); blocked storages need no
+// such bound, but every storage keeps it.
 bool plane_fits(int storage, int64_t sites) { return (uint64_t)sites * store_size(storage) <= ((uint64_t)1 << 32); }
 
 // Bytes of one particle's kind grid: offsets of a template lie within
@@ -1715,7 +1744,7 @@ struct lbm_ctx {
   Geo G;                    // box 0 (the box of a single-box context)
   int nbox;
   int64_t NT;               // sites of all boxes
-  int64_t PS;               // population plane stride
+  int64_t PS;               // population array stride (see pop_elem)
   std::vector<Geo> boxes;   // host copy of the box table
   Geo* d_boxes;
   void* d_fbt;              // [nbox][q] 3 w_i c_i . f_b per box, compute type
@@ -1873,7 +1902,7 @@ SweepArgs<Q, typename Store<T>::C> sweep_args(const lbm_ctx* c) {
   a.ny = c->G.ny;
   a.nz = c->G.nz;
   a.nxb = (c->G.nx + kSweepBlock - 1) / kSweepBlock;
-  a.N = c->PS;  // the sweep's plane stride
+  a.N = c->PS;  // the sweep's population array stride
   a.omega = (C)(1.0 / c->prm.tau);
   a.rho0 = (C)c->prm.rho0;
   a.walls = c->prm.walls;
@@ -2920,6 +2949,7 @@ int lbm_get_distributions(lbm_ctx* c, double* f) {
   HIP_TRY(hipStreamSynchronize(c->stream));
   // element of the host copy that holds f_i of site s
   const int lay = state_layout(c);
+  const bool blk = pop_blocked(c->prm.storage);
   std::vector<int64_t> src;
   if (lay == kLayAASwap) {
     src.resize((size_t)c->q * c->NT);
@@ -2934,14 +2964,14 @@ int lbm_get_distributions(lbm_ctx* c, double* f) {
               const int o = c->q == 9 ? opposite<9>(i) : opposite<19>(i);
               const int64_t from = g.off + wrap(x - cx, g.nx) + (int64_t)g.nx * (wrap(y - cy, g.ny) +
                                                                                   (int64_t)g.ny * wrap(z - cz, g.nz));
-              src[(size_t)i * c->NT + g.off + x + (int64_t)g.nx * (y + (int64_t)g.ny * z)] = (int64_t)o * c->PS + from;
+              src[(size_t)i * c->NT + g.off + x + (int64_t)g.nx * (y + (int64_t)g.ny * z)] = pop_elem(blk, c->q, o, from, c->PS);
             }
   }
   for (int i = 0; i < c->q; i++) {
     const double w = lattice_w(c->q, i);
     const double base = w * c->prm.rho0;
     for (int64_t s = 0; s < c->NT; s++) {
-      const int64_t k = src.empty() ? (int64_t)i * c->PS + s : src[(size_t)i * c->NT + s];
+      const int64_t k = src.empty() ? pop_elem(blk, c->q, i, s, c->PS) : src[(size_t)i * c->NT + s];
       double g;
       switch (c->prm.storage) {
         case LBM_FP64: g = ((const double*)h.data())[k]; break;
@@ -2965,11 +2995,12 @@ int lbm_set_distributions(lbm_ctx* c, const double* f) {
   const int64_t n = (int64_t)c->q * c->PS;  // device planes (padded; padding zero)
   const int ss = (int)store_size(c->prm.storage);
   std::vector<unsigned char> h((size_t)n * ss, 0);
+  const bool blk = pop_blocked(c->prm.storage);
   for (int i = 0; i < c->q; i++) {
     const double w = lattice_w(c->q, i);
     const double base = w * c->prm.rho0;
     for (int64_t s = 0; s < c->NT; s++) {
-      const int64_t k = (int64_t)i * c->PS + s;
+      const int64_t k = pop_elem(blk, c->q, i, s, c->PS);
       const double g = f[(int64_t)i * c->NT + s] - base;
       switch (c->prm.storage) {
         case LBM_FP64: ((double*)h.data())[k] = g; break;

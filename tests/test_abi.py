@@ -75,11 +75,11 @@ def test_plane_limit_and_aa_layout():
     rc2, n2 = _rc_workspace()
     rc1, n1 = _rc_workspace(aa=True)
     assert rc1 == rc2 == 0
-    # one FP32 array of q planes less (planes padded to a multiple of 256 sites
-    # plus 256 below 2^20 sites), one 4-double-per-site staging area more
-    # (256-B alignment)
+    # one FP32 population array less (blocks of 256 sites: the sites rounded
+    # up to whole blocks), one 4-double-per-site staging area more (256-B
+    # alignment)
     N = 16 ** 3
-    stride = (N + 255) // 256 * 256 + 256
+    stride = (N + 255) // 256 * 256
     expect = 19 * stride * 4 - 4 * 8 * N
     assert abs((n2 - n1) - expect) <= 512
     p = lbm.make_params(19, 16, 16, 16, tau=0.6, max_particles=4, max_radius=3.0)
