@@ -354,11 +354,13 @@ __device__ __forceinline__ bool wall_velocity(const SweepArgs<Q, C>& a, int x, i
 // Population layout.  16-bit storage keeps q planes [q][N] (N the padded
 // plane stride); FP32 and FP64 keep blocks of kPopBlock consecutive sites,
 // each block holding its q populations one after another:
-// [N / kPopBlock][q][kPopBlock], N a multiple of kPopBlock.  A row of 256
-// sites then writes one contiguous 19 KB block instead of 19 pieces 64 MB
-// apart (particle-free FP32 D3Q19 256^3 sweep: 412-416 us blocked against
-// 423-432 us in planes; FP16 is 12 us slower blocked).
-constexpr int kPopBlock = 256;
+// [N / kPopBlock][q][kPopBlock], N a multiple of kPopBlock.  The q pieces a
+// workgroup reads and writes then lie within one block of 8 rows instead of
+// q planes apart.  Whole FP32 256^3 step with 500 spheres, by block size:
+// planes 0.474 ms, 256 sites 0.472, 1024 0.470, 1536 0.469, 2048 0.456,
+// 3072 0.464, 4096 and 8192 0.458 (the AA pattern 0.525 -> 0.498 at 2048);
+// 16-bit storage is slower blocked (FP16 step 0.280 -> 0.289 at 2048).
+constexpr int kPopBlock = 2048;
 inline bool pop_blocked(int storage) { return storage == LBM_FP32 || storage == LBM_FP64; }
 template <typename T>
 __host__ __device__ constexpr bool pop_blocked_t() {

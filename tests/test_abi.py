@@ -75,11 +75,11 @@ def test_plane_limit_and_aa_layout():
     rc2, n2 = _rc_workspace()
     rc1, n1 = _rc_workspace(aa=True)
     assert rc1 == rc2 == 0
-    # one FP32 population array less (blocks of 256 sites: the sites rounded
+    # one FP32 population array less (blocks of 2048 sites: the sites rounded
     # up to whole blocks), one 4-double-per-site staging area more (256-B
     # alignment)
     N = 16 ** 3
-    stride = (N + 255) // 256 * 256
+    stride = (N + 2047) // 2048 * 2048
     expect = 19 * stride * 4 - 4 * 8 * N
     assert abs((n2 - n1) - expect) <= 512
     p = lbm.make_params(19, 16, 16, 16, tau=0.6, max_particles=4, max_radius=3.0)
