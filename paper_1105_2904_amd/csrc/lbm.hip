@@ -674,6 +674,12 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int dim, Boxes
   const int lane = tid & 63, wv = tid >> 6;
   const int L[3] = {G.nx, G.ny, G.nz};
   double vmax = 0;
+  // one particle per thread: the translation's inputs and the candidate
+  // count are loaded with the first phase's, not after the pair pass
+  const bool one = p1 - p0 <= NT;
+  double xr[3] = {0, 0, 0}, x0r[3] = {0, 0, 0};
+  int k0r[3] = {0, 0, 0}, b0r[3] = {0, 0, 0}, ogr[3] = {0, 0, 0};
+  int cnr = 0;
   for (int p = p0 + tid; p < p1; p += NT) {
     // every input is loaded before the first store: the particle arrays
     // could alias as far as the compiler knows, and a load after a store
@@ -689,6 +695,17 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int dim, Boxes
       fe[a] = P.fext[3 * p + a];
       om[a] = P.om[3 * p + a];
       x[a] = P.x[3 * p + a];
+    }
+    if (one) {
+#pragma unroll
+      for (int a = 0; a < 3; a++) {
+        x0r[a] = P.x0[3 * p + a];
+        k0r[a] = P.k[3 * p + a];
+        b0r[a] = P.b0[3 * p + a];
+        ogr[a] = P.org[3 * p + a];
+        xr[a] = x[a];
+      }
+      cnr = P.cand_n[p];
     }
     double v2 = 0;
 #pragma unroll
@@ -724,7 +741,7 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int dim, Boxes
   int total = 0;
   for (int c0 = p0; c0 < p1; c0 += NT) {
     const int p = c0 + tid;
-    const int c = p < p1 ? P.cand_n[p] : 0;
+    const int c = p < p1 ? (one ? cnr : P.cand_n[p]) : 0;
     int chunk;
     const int excl = total + block_excl_scan<NT>(c, s_scan, chunk);
     for (int t = 0; t < c; t++) {
@@ -803,11 +820,11 @@ __global__ __launch_bounds__(NT) void k_particles(DevParticles P, int dim, Boxes
 #pragma unroll
     for (int a = 0; a < 3; a++) {
       u[a] = staged ? s_u[a * kStageParticles + p - p0] : P.u[3 * p + a];
-      x[a] = P.x[3 * p + a];
-      x0[a] = P.x0[3 * p + a];
-      k0[a] = P.k[3 * p + a];
-      b0[a] = P.b0[3 * p + a];
-      og[a] = P.org[3 * p + a];
+      x[a] = one ? xr[a] : P.x[3 * p + a];
+      x0[a] = one ? x0r[a] : P.x0[3 * p + a];
+      k0[a] = one ? k0r[a] : P.k[3 * p + a];
+      b0[a] = one ? b0r[a] : P.b0[3 * p + a];
+      og[a] = one ? ogr[a] : P.org[3 * p + a];
     }
     if (G.walls && !isinf(m)) {
       // contact with a wall after the pairs: the normal velocity reverses
