@@ -78,6 +78,7 @@ constexpr int kTileMax = 512;        // widest tile of the ensemble sweep
 constexpr int kBoundaryBlock = 256;  // reduce workgroup (128 for balls of at most kSmallBall entries)
 constexpr int kSmallBall = 512;
 constexpr int kPrepareBlock = 256;   // workgroup of the per-particle prepare
+constexpr size_t kCacheResidentBytes = (size_t)128 << 20;  // half the 256 MB last-level cache
 constexpr int kPrepareLocalMax = 8192;  // bound on one ball's entries for the per-particle prepare
 constexpr int kParticleBlock = 1024;   // particle update of a one-box context
 constexpr int kBoxParticleBlock = 256; // particle update, per box of an ensemble
@@ -1876,9 +1877,14 @@ int launch_prepare_as(lbm_ctx* c, int pending, int flags_all) {
 template <int Q, typename T>
 int launch_prepare(lbm_ctx* c, int pending, int flags_all) {
   if (c->nent == 0) return LBM_OK;
-  // streaming IS stores for the AA pattern only
-  return state_layout(c) == kLayAB ? launch_prepare_as<Q, T, false>(c, pending, flags_all)
-                                   : launch_prepare_as<Q, T, true>(c, pending, flags_all);
+  // Streaming IS stores for the AA pattern (the in-place sweep pays most for
+  // partly written lines) and for two arrays small enough to stay in the
+  // last-level cache (D2Q9 1024^2, 75 MB: step 33.2 -> 32.0 us); larger
+  // two-array states keep plain stores (256^3 FP32: 0.456 against 0.464 ms).
+  const size_t both = 2 * (size_t)c->q * c->PS * store_size(c->prm.storage);
+  const bool nts = state_layout(c) != kLayAB || both <= kCacheResidentBytes;
+  return nts ? launch_prepare_as<Q, T, true>(c, pending, flags_all)
+             : launch_prepare_as<Q, T, false>(c, pending, flags_all);
 }
 
 // Tile list {box, y, z, x0} of width w, box by box, rows in z, y order.
