@@ -356,8 +356,9 @@ __device__ __forceinline__ bool wall_velocity(const SweepArgs<Q, C>& a, int x, i
 // plane stride); FP32 and FP64 keep blocks of kPopBlock consecutive sites,
 // each block holding its q populations one after another:
 // [N / kPopBlock][q][kPopBlock], N a multiple of kPopBlock.  The q pieces a
-// workgroup reads and writes then lie within one block of 8 rows instead of
-// q planes apart.  Whole FP32 256^3 step with 500 spheres, by block size:
+// row of the 256^3 box writes then lie within one block of 8 rows, and the
+// pieces it pulls within the blocks of its own plane and the two next to it,
+// instead of q planes apart.  Whole FP32 256^3 step with 500 spheres, by block size:
 // planes 0.474 ms, 256 sites 0.472, 1024 0.470, 1536 0.469, 2048 0.456,
 // 3072 0.464, 4096 and 8192 0.458 (the AA pattern 0.525 -> 0.498 at 2048);
 // 16-bit storage is slower blocked (FP16 step 0.280 -> 0.289 at 2048).
