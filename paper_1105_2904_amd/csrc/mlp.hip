@@ -65,16 +65,28 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ P
   mlp::load_weights(w, P, tid, 256);
   __syncthreads();
   const int64_t ntiles = (n + 15) / 16;
-  for (int64_t t = (int64_t)blockIdx.x * kWaves + wv; t < ntiles; t += (int64_t)gridDim.x * kWaves) {
-    const int64_t row0 = 16 * t;
-    const int r = lane & 15, g = lane >> 4;
-    const int64_t row = row0 + r;
+  const int64_t stride = (int64_t)gridDim.x * kWaves;
+  const int r = lane & 15, g = lane >> 4;
+  // lane (r, g < 2) holds inputs 4g .. 4g+3 of row 16 t + r, one 16-byte load;
+  // the next tile's inputs are loaded while this one runs
+  auto load_tile = [&](int64_t t) {
+    const int64_t row = 16 * t + r;
+    f4 v = {0.f, 0.f, 0.f, 0.f};
+    if (g < 2 && row < n) v = *(const f4*)(X + row * mlp::kIn + 4 * g);
+    return v;
+  };
+  int64_t t = (int64_t)blockIdx.x * kWaves + wv;
+  f4 xnext = t < ntiles ? load_tile(t) : f4{0.f, 0.f, 0.f, 0.f};
+  for (; t < ntiles; t += stride) {
+    const f4 xc = xnext;
+    if (t + stride < ntiles) xnext = load_tile(t + stride);
     h4 xb;
 #pragma unroll
-    for (int i = 0; i < 4; i++) xb[i] = (g < 2 && row < n) ? (_Float16)X[row * mlp::kIn + 4 * g + i] : (_Float16)0.0f;
+    for (int i = 0; i < 4; i++) xb[i] = (_Float16)xc[i];
     h4 h1[4], h2[4];
     f4 y;
     mlp::forward_tile(w, xb, h1, h2, y, lane);
+    const int64_t row = 16 * t + r;
     if (g == 0 && row < n) {
       Y[row * mlp::kOut] = y[0] + w.b3[0];
       Y[row * mlp::kOut + 1] = y[1] + w.b3[1];
