@@ -36,26 +36,40 @@ MALL_BYTES = 256 << 20  # MI355X last-level (Infinity) cache
 COUNTERS = os.path.join(ROOT, "profiles", "k_sweep_d3q19_256cubed_500spheres_hbm_counters.json")
 
 
-def sweep_geometry(box, launch):
+def pair_rows(tname, layout, nx):
+    """True when the row kernel of this storage takes two sites per lane
+    (16-bit storage, two arrays, an even row length)."""
+    return tname in ("_Float16", "bf16s") and layout == "0" and nx % 2 == 0
+
+
+def sweep_geometry(box, launch, pairs=False):
     """Workgroup size and grid (threads) of the sweep launch (width, grid,
     blocks_per_cu) on one box: the row kernel runs 256-wide workgroups over
-    ceil(nx/256) blocks per row; tiles are w consecutive sites of the box, one
-    per workgroup unless a smaller persistent grid is set."""
+    ceil(nx/256) blocks per row, or with two sites per lane one 64-lane wave
+    per 128 sites of a row, four waves to a workgroup; tiles are w
+    consecutive sites of the box, one per workgroup unless a smaller
+    persistent grid is set."""
     import math
     nx, ny, nz = box
     w, g = launch["width"], launch["grid"]
+    if w == 0 and pairs:
+        return 256, math.ceil(math.ceil(nx / 128) * ny * nz / 4) * 256
     if w == 0:
         return 256, math.ceil(nx / 256) * ny * nz * 256
     nt = math.ceil(nx * ny * nz / w)
     return w, (g if 0 < g < nt else nt) * w
 
 
-def sweep_kernel(width, q, tname, particles, layout):
+def sweep_kernel(width, q, tname, particles, layout, nx):
     """Name of a one-box sweep kernel as the profiler lists it: the row kernel
-    (width 0) or the tile kernel with streaming loads."""
+    (width 0; k_sweep_pairs where it takes two sites per lane) or the tile
+    kernel with streaming loads."""
+    part = "true" if particles else "false"
+    if width == 0 and pair_rows(tname, layout, nx):
+        return "k_sweep_pairs<%d,%s,%s>" % (q, tname, part)
     if width == 0:
-        return "k_sweep<%d,%s,%s,%s>" % (q, tname, "true" if particles else "false", layout)
-    return "k_sweep_tiles<%d,%s,%s,%s,true>" % (q, tname, "true" if particles else "false", layout)
+        return "k_sweep<%d,%s,%s,%s>" % (q, tname, part, layout)
+    return "k_sweep_tiles<%d,%s,%s,%s,true>" % (q, tname, part, layout)
 
 
 def measured_traffic(kernel, workload, box, launch):
@@ -76,7 +90,7 @@ def measured_traffic(kernel, workload, box, launch):
             h.update(fh.read())
     if h.hexdigest() != c["source_sha256"]:
         return None
-    wg, grid = sweep_geometry(box, launch)
+    wg, grid = sweep_geometry(box, launch, pairs=kernel.startswith("k_sweep_pairs"))
     col = {k: i for i, k in enumerate(c["columns"])}
     for e in c["entries"]:
         if (e[col["kernel"]], e[col["workgroup_size"]], e[col["grid_threads"]]) == (kernel, wg, grid):
@@ -147,8 +161,8 @@ def storage_accuracy(lbm, cfg, steps):
 
 
 def disks_2d_rates(torch, lbm, wl, steps, warmup, graph_steps=20):
-    """The D2Q9 1024^2 workload with 200 disks (FP32): the autotuned launch
-    replayed in step graphs.  Its two population arrays (75 MB) fit the
+    """The D2Q9 1024^2 workload with 200 disks (FP32): the launch tuned in
+    whole steps, replayed in step graphs.  Its two population arrays (75 MB) fit the
     256 MB last-level cache, so its ceiling is a copy of the same footprint."""
     cfg = wl.disks_2d_config()
     p = cfg["particles"]
@@ -158,8 +172,8 @@ def disks_2d_rates(torch, lbm, wl, steps, warmup, graph_steps=20):
                          storage="fp32", max_particles=len(p["radius"]), max_radius=float(np.max(p["radius"])))
     sim.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
     sim.step(warmup)
-    w, g, k, _ = sim.autotune(reps=10)
-    sim.set_graph(graph_steps)
+    sim.set_graph(graph_steps)  # the tuner then times whole graphs
+    w, g, k, _, _ = sim.autotune_steps(steps=graph_steps)
     sim.step(max(warmup, graph_steps))
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -226,7 +240,7 @@ def cpu_baseline(cfg, steps_one, steps_all):
 def ensemble_rates(torch, lbm, wl, steps, warmup, graph_steps=20):
     """The 64-box D2Q9 ensemble (seeded sides 128..512, 10..80 disks of radius
     6..12): MLUPS of one ensemble context with eager launches, of the same
-    context after autotuning and with step graphs, and of a loop over 64
+    context after tuning its launch in whole steps and with step graphs, and of a loop over 64
     one-box contexts (each box's steps launched back to back)."""
     cfg = wl.ensemble_2d_config()
     dims = [tuple(int(v) for v in d) for d in cfg["boxes"]]
@@ -249,8 +263,8 @@ def ensemble_rates(torch, lbm, wl, steps, warmup, graph_steps=20):
         ens.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"], box=b)
     ens.step(warmup)
     ms_eager = clock(lambda: ens.step(steps))
-    width, grid, occ, _ = ens.autotune(reps=5)
-    ens.set_graph(graph_steps)
+    ens.set_graph(graph_steps)  # the tuner then times whole graphs
+    width, grid, occ, _, _ = ens.autotune_steps(steps=graph_steps)
     ens.step(max(warmup, graph_steps))
     ms_graph = clock(lambda: ens.step(steps))
     assert np.isfinite(ens.forces()[0]).all()
@@ -372,11 +386,12 @@ def main():
         the summed time and count of the sweep launches of a further
         min(steps, 100) steps bracketed by HIP events on the sim's stream (the
         events cost about 1 % of a step, so they stay out of the step time).
-        Unless --no-autotune, the library's autotuner picks the sweep launch
-        on the live state after the warm-up, outside the timed region."""
+        Unless --no-autotune, the library's in-step tuner picks the sweep
+        launch after the warm-up (its steps are further warm-up), outside the
+        timed region."""
         sim_.step(warmup)
-        if not args.no_autotune and not sim_.params.aa:
-            sim_.autotune(reps=5)
+        if not args.no_autotune:
+            sim_.autotune_steps(steps=4)
             sim_.step(2)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -411,7 +426,7 @@ def main():
     if footprint <= MALL_BYTES * 3 // 4:
         cache_ceiling = copy_ceiling(torch, lbm, stream, nbytes=footprint // 32 * 16, reps=200)
     launch = dict(zip(("width", "grid", "blocks_per_cu"), sim.sweep_config()))
-    kernel = sweep_kernel(launch["width"], q, kname, bool(args.particles), "0")
+    kernel = sweep_kernel(launch["width"], q, kname, bool(args.particles), "0", nx)
     traffic = None
     if args.particles == len(cfg["particles"]["radius"]):
         traffic = measured_traffic(kernel.replace(",", ", "), cfg["name"], cfg["box"], launch)
@@ -461,16 +476,14 @@ def main():
                                max_radius=float(np.max(cfg["particles"]["radius"])), aa=aa)
             if args.particles:
                 v.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
-            if aa:  # an AA context cannot be autotuned: the FP32 context's launch
-                v.set_sweep_config(launch["width"], launch["grid"], launch["blocks_per_cu"])
             vms, (vsw, vn) = timed(v, args.steps, args.warmup, True)
             vb = lbm.lbm_bytes_per_site(v.params)
             vl = dict(zip(("width", "grid", "blocks_per_cu"), v.sweep_config()))
             tn = {"fp16": "_Float16", "bf16": "bf16s", "fp32": "float"}[st]
             # the AA pattern alternates two sweep kernels (layouts 1 and 2)
             halves = ["1", "2"] if aa else ["0"]
-            vks = [sweep_kernel(vl["width"], q, tn, bool(args.particles), h).replace(",", ", ") for h in halves]
-            vk = vks[0] if not aa else vks[0][:-2] + "1/2>"
+            vks = [sweep_kernel(vl["width"], q, tn, bool(args.particles), h, nx).replace(",", ", ") for h in halves]
+            vk = vks[0] if not aa else sweep_kernel(vl["width"], q, tn, bool(args.particles), "1/2", nx)
             vt = None
             if args.particles == len(cfg["particles"]["radius"]):
                 ts = [measured_traffic(k_, cfg["name"], cfg["box"], vl) for k_ in vks]

@@ -226,20 +226,39 @@ int lbm_box_info(lbm_ctx* ctx, int32_t box, int32_t* dims, int64_t* first_site, 
  * LDS each workgroup reserves (floor(LDS per CU / blocks_per_cu), whole KiB;
  * LBM_EINVAL if that exceeds what one workgroup may reserve or is below
  * 1 KiB); 0 leaves residency to the register count.  Fewer resident waves
- * can stream faster: fewer DRAM rows open at once.  Every shape computes the
- * same values bit for bit.  Defaults: width 0 (one box) or 128, grid 0, no
- * cap. */
+ * can stream faster: fewer DRAM rows open at once.  With FP16/BF16 storage,
+ * two arrays and an even nx the row kernel takes two sites per lane (one
+ * 64-wide wave per 128 sites of a row, four waves to a workgroup).  Every
+ * shape computes the same values bit for bit.  Defaults: width 0 (one box) or
+ * 128, grid 0, no cap. */
 int lbm_set_sweep_config(lbm_ctx* ctx, int32_t width, int32_t grid, int32_t blocks_per_cu);
 int lbm_get_sweep_config(lbm_ctx* ctx, int32_t* width, int32_t* grid, int32_t* blocks_per_cu);
 
 /* Time every sweep shape (widths 0 (one box), 64, 128, 256, 512; grids 0 and
  * 4, 8, 16, 32 per CU; caps none, 6, 5, 4, 3, 2 workgroups per CU; reps
- * launches each, after one warm-up) on the context's own state and keep the
- * fastest; returns it and its time per sweep in ms (any output pointer may be
- * NULL).  Sweeping again from the same state recomputes the same values, so
- * the simulation is unchanged.  Synchronises. */
+ * launches each, after one warm-up) on the context's own state, time the four
+ * fastest again in two alternating rounds of 2 reps launches, and keep the
+ * fastest of those; returns it and its time per sweep in ms (any output
+ * pointer may be NULL).  Sweeping again from the same state recomputes the
+ * same values, so the simulation is unchanged.  Synchronises. */
 int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* width, int32_t* grid, int32_t* blocks_per_cu,
                  double* best_ms);
+
+/* The same candidates timed inside whole steps instead of bare repeated
+ * sweeps: for each, 2 untimed and `steps` (rounded up to even) timed steps,
+ * or with step graphs set (lbm_set_graph) one untimed graph and `steps`
+ * rounded up to whole graphs; then the four fastest again in two alternating
+ * rounds of twice the steps.  Keeps the fastest and returns it and its time
+ * per step in ms.  The step around a sweep changes which launch is fastest
+ * (what the previous kernels leave in the caches, how the sweep's last waves
+ * overlap the next kernel), so this is the tuner for production runs.
+ * Unlike lbm_autotune it ADVANCES the simulation by every step it times
+ * (about 130 times the steps per candidate; their number goes to
+ * *steps_done), works on AA contexts, and discards pending profiling
+ * events.  Any output pointer may be NULL.  Returns the status of those steps
+ * (e.g. LBM_ECOLLISION).  Synchronises. */
+int lbm_autotune_steps(lbm_ctx* ctx, int32_t steps, int32_t* width, int32_t* grid, int32_t* blocks_per_cu,
+                       double* best_ms, int64_t* steps_done);
 
 /* steps_per_graph > 0 (even): lbm_step replays a HIP graph of that many
  * steps, captured on the first use and again after the particle set, the

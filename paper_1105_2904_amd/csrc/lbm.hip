@@ -192,8 +192,6 @@ struct Boxes {
   Geo g0;
   const Geo* tab;
   int nbox;
-  int64_t NT;  // sites of all boxes
-  int64_t PS;  // stride N of the population array (see pop_elem, plane_stride)
 };
 
 // A site of the wall layers of a closed axis (particles never own these).
@@ -316,7 +314,6 @@ constexpr int kLayAB = 0, kLayAAStream = 1, kLayAASwap = 2;
 template <int Q, typename C>
 struct SweepArgs {
   int nx, ny, nz, nxb;
-  int64_t N;
   C omega;   // 1 / tau
   C rho0;
   C fbt[Q];  // 3 w_i c_i . f_b
@@ -352,50 +349,54 @@ __device__ __forceinline__ bool wall_velocity(const SweepArgs<Q, C>& a, int x, i
   return true;
 }
 
-// Population layout.  16-bit storage keeps q planes [q][N] (N the padded
-// plane stride); FP32 and FP64 keep blocks of kPopBlock consecutive sites,
-// each block holding its q populations one after another:
-// [N / kPopBlock][q][kPopBlock], N a multiple of kPopBlock.  The q pieces a
-// row of the 256^3 box writes then lie within one block of 8 rows, and the
-// pieces it pulls within the blocks of its own plane and the two next to it,
-// instead of q planes apart.  Whole FP32 256^3 step with 500 spheres, by block size:
+// Population layout: blocks of kPopBlock consecutive sites, each block
+// holding its q populations one after another: [N / kPopBlock][q][kPopBlock],
+// N the sites rounded up to whole blocks.  The q pieces a row of the 256^3
+// box writes then lie within one block of 8 rows, and the pieces it pulls
+// within the blocks of its own plane and the two next to it, instead of q
+// planes apart.  Whole FP32 256^3 step with 500 spheres, by block size:
 // planes 0.474 ms, 256 sites 0.472, 1024 0.470, 1536 0.469, 2048 0.456,
-// 3072 0.464, 4096 and 8192 0.458 (the AA pattern 0.525 -> 0.498 at 2048);
-// 16-bit storage is slower blocked (FP16 step 0.280 -> 0.289 at 2048).
+// 3072 0.464, 4096 and 8192 0.458 (the AA pattern 0.525 -> 0.498 at 2048).
+// 16-bit storage with one site per lane was slower blocked (FP16 step 0.280
+// -> 0.289 ms); with two sites per lane (k_sweep_pairs) its particle-free
+// sweep takes 199 us blocked against 211 us in planes.
 constexpr int kPopBlock = 2048;
-inline bool pop_blocked(int storage) { return storage == LBM_FP32 || storage == LBM_FP64; }
-template <typename T>
-__host__ __device__ constexpr bool pop_blocked_t() {
-  return std::is_same<T, float>::value || std::is_same<T, double>::value;
+// Element of f_i at site s of a population array of q populations.
+__host__ __device__ __forceinline__ int64_t pop_elem(int q, int i, int64_t s) {
+  return (s / kPopBlock) * ((int64_t)q * kPopBlock) + (int64_t)i * kPopBlock + s % kPopBlock;
 }
-// Element of f_i at site s of a population array with stride N.
-__host__ __device__ __forceinline__ int64_t pop_elem(bool blocked, int q, int i, int64_t s, int64_t N) {
-  return blocked ? (s / kPopBlock) * ((int64_t)q * kPopBlock) + (int64_t)i * kPopBlock + s % kPopBlock
-                 : (int64_t)i * N + s;
+// Address of f_i at `site` (the sweep's form): the block's byte offset from
+// one 32 x 32 -> 64-bit product plus a 32-bit offset within the block.
+template <int Q, typename T>
+__device__ __forceinline__ T* pop_at(T* p, int i, int site) {
+  return (T*)((char*)p + (size_t)((uint32_t)site / kPopBlock) * (size_t)(Q * kPopBlock * sizeof(T)) +
+              (uint32_t)(i * kPopBlock + (int)((uint32_t)site % kPopBlock)) * (uint32_t)sizeof(T));
 }
 template <int Q, typename T>
-__host__ __device__ __forceinline__ int64_t pop_elem(int i, int64_t s, int64_t N) {
-  return pop_elem(pop_blocked_t<T>(), Q, i, s, N);
-}
-// Address of f_i at `site` (the sweep's form): planes take a wave-uniform
-// plane base plus a 32-bit byte offset (valid while N sizeof(T) <= 2^32);
-// blocks take the block's byte offset from one 32 x 32 -> 64-bit product.
-template <int Q, typename T>
-__device__ __forceinline__ T* pop_at(T* p, int i, int64_t N, int site) {
-  if constexpr (pop_blocked_t<T>())
-    return (T*)((char*)p + (size_t)((uint32_t)site / kPopBlock) * (size_t)(Q * kPopBlock * sizeof(T)) +
-                (uint32_t)(i * kPopBlock + (int)((uint32_t)site % kPopBlock)) * (uint32_t)sizeof(T));
-  else
-    return (T*)((char*)p + (size_t)i * (size_t)N * sizeof(T) + (uint32_t)site * (uint32_t)sizeof(T));
-}
-template <int Q, typename T>
-__device__ __forceinline__ const T* pop_at(const T* p, int i, int64_t N, int site) {
-  return pop_at<Q, T>(const_cast<T*>(p), i, N, site);
+__device__ __forceinline__ const T* pop_at(const T* p, int i, int site) {
+  return pop_at<Q, T>(const_cast<T*>(p), i, site);
 }
 
 // 1/rho: the hardware reciprocal in FP32 (1 ulp), a division in FP64.
 __device__ __forceinline__ float recip(float v) { return __builtin_amdgcn_rcpf(v); }
 __device__ __forceinline__ double recip(double v) { return 1.0 / v; }
+
+// Fused multiply-add in the compute type (always one rounding).
+__device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// c . v for a lattice direction (components -1, 0, 1): additions only.
+template <typename Lt, typename C>
+__device__ __forceinline__ C dot_c(int i, C vx, C vy, C vz) {
+  C r = 0;
+  if (Lt::cx(i) > 0) r += vx;
+  if (Lt::cx(i) < 0) r -= vx;
+  if (Lt::cy(i) > 0) r += vy;
+  if (Lt::cy(i) < 0) r -= vy;
+  if (Lt::cz(i) > 0) r += vz;
+  if (Lt::cz(i) < 0) r -= vz;
+  return r;
+}
 
 // Collision of one site from the populations g it pulled, in place: BGK with
 // body force (eq. 1-3), the site's density deviation kept at ball sites, the
@@ -405,12 +406,25 @@ __device__ __forceinline__ double recip(double v) { return 1.0 / v; }
 // stored numbers h_i = g_i / (w_i sigma): there the weight cancels from the
 // equilibrium, h_i^eq = (drho + rho (3cu + 9/2 cu^2 - 3/2 u^2)) / sigma,
 // which saves the per-direction scalings; FP32/FP64 collide on the
-// deviations g_i.
+// deviations g_i.  rec is the site's record when fl is kSiteBS (loaded by
+// the caller as soon as the flag is in, so that its latency overlaps the
+// population loads).  No contraction is left to the compiler (every fused
+// multiply-add is written out), so every kernel that inlines this function,
+// once or twice per lane, rounds every site the same way.
+template <typename T>
+using RecOf = decltype(ld_rec((const typename Store<T>::C*)nullptr));
+template <typename T>
+__device__ __forceinline__ RecOf<T> site_record(const SiteArgs<T>& sa, int s, int fl) {
+  RecOf<T> r{};
+  if (fl == kSiteBS) r = ld_rec(sa.vel + 4 * (size_t)s);
+  return r;
+}
 template <int Q, typename T, bool PART>
 __device__ __forceinline__ void collide_site(typename Store<T>::C (&g)[Q],
                                              const SweepArgs<Q, typename Store<T>::C>& a, const SiteArgs<T>& sa,
-                                             int s, int fl, int x, int y, int z, int nx, int ny, int nz,
-                                             const typename Store<T>::C (&fbt)[Q]) {
+                                             int s, int fl, const RecOf<T>& rec, int x, int y, int z, int nx,
+                                             int ny, int nz, const typename Store<T>::C (&fbt)[Q]) {
+#pragma clang fp contract(off)
   using L = Lattice<Q>;
   using C = typename Store<T>::C;
   constexpr bool kRaw = std::is_same<T, _Float16>::value || std::is_same<T, bf16s>::value;
@@ -430,21 +444,21 @@ __device__ __forceinline__ void collide_site(typename Store<T>::C (&g)[Q],
   const C rho = a.rho0 + drho;
   const C inv = recip(rho);
   const C ux = jx * inv, uy = jy * inv, uz = jz * inv;
-  const C usq = C(1.5) * (ux * ux + uy * uy + uz * uz);
+  const C usq = C(1.5) * fmac(ux, ux, fmac(uy, uy, uz * uz));
   if constexpr (kRaw) {
-    const C kA = inv_sig * (drho - rho * usq), kB = inv_sig * C(3) * rho, kC = inv_sig * C(4.5) * rho;
+    const C kA = inv_sig * fmac(-rho, usq, drho), kB = inv_sig * C(3) * rho, kC = inv_sig * C(4.5) * rho;
 #pragma unroll
     for (int i = 0; i < Q; i++) {
-      const C cu = C(L::cx(i)) * ux + C(L::cy(i)) * uy + C(L::cz(i)) * uz;
-      const C he = fmaf(fmaf(kC, cu, kB), cu, kA);
-      g[i] = fmaf(a.omega, he - g[i], g[i]) + fbt[i] * (C)(1.0 / pop_unit<T>(L::w(i)));
+      const C cu = dot_c<L>(i, ux, uy, uz);
+      const C he = fmac(fmac(kC, cu, kB), cu, kA);
+      g[i] = fmac(fbt[i], (C)(1.0 / pop_unit<T>(L::w(i))), fmac(a.omega, he - g[i], g[i]));
     }
   } else {
 #pragma unroll
     for (int i = 0; i < Q; i++) {
-      const C cu = C(L::cx(i)) * ux + C(L::cy(i)) * uy + C(L::cz(i)) * uz;
-      const C geq = C(L::w(i)) * (drho + rho * (C(3) * cu + C(4.5) * cu * cu - usq));
-      g[i] = g[i] + a.omega * (geq - g[i]) + fbt[i];
+      const C cu = dot_c<L>(i, ux, uy, uz);
+      const C geq = C(L::w(i)) * fmac(rho, fmac(C(4.5) * cu, cu, fmac(C(3), cu, -usq)), drho);
+      g[i] = fmac(a.omega, geq - g[i], g[i]) + fbt[i];
     }
   }
   if (PART && fl != 0) {
@@ -453,7 +467,6 @@ __device__ __forceinline__ void collide_site(typename Store<T>::C (&g)[Q],
       // BS substep at an owned BS site: its post-collision moments go to the
       // owner's slot (FP64 sums), and the populations become f^eq(rho_B,
       // u_B') with the rigid-body velocity u_B' = u_p + omega x r of the site
-      const auto rec = ld_rec(sa.vel + 4 * (size_t)s);
       const C vx = rec.x, vy = rec.y, vz = rec.z;
       const int bs = as_idx<C>(rec.w);
       double dr = 0, bx = 0, by = 0, bz = 0;
@@ -461,9 +474,12 @@ __device__ __forceinline__ void collide_site(typename Store<T>::C (&g)[Q],
       for (int i = 0; i < Q; i++) {
         const double v = kRaw ? (double)g[i] * pop_unit<T>(L::w(i)) : (double)g[i];
         dr += v;
-        bx += L::cx(i) * v;
-        by += L::cy(i) * v;
-        bz += L::cz(i) * v;
+        if (L::cx(i) > 0) bx += v;
+        if (L::cx(i) < 0) bx -= v;
+        if (L::cy(i) > 0) by += v;
+        if (L::cy(i) < 0) by -= v;
+        if (L::cz(i) > 0) bz += v;
+        if (L::cz(i) < 0) bz -= v;
       }
       if ((unsigned)bs < (unsigned)sa.nent) {
         double* sl = sa.slot + 4 * (size_t)bs;
@@ -478,11 +494,11 @@ __device__ __forceinline__ void collide_site(typename Store<T>::C (&g)[Q],
       }
       const C drB = (C)dr;
       const C rhoB = a.rho0 + drB;
-      const C usqB = C(1.5) * (vx * vx + vy * vy + vz * vz);
+      const C usqB = C(1.5) * fmac(vx, vx, fmac(vy, vy, vz * vz));
 #pragma unroll
       for (int i = 0; i < Q; i++) {
-        const C cu = C(L::cx(i)) * vx + C(L::cy(i)) * vy + C(L::cz(i)) * vz;
-        const C e = drB + rhoB * (C(3) * cu + C(4.5) * cu * cu - usqB);
+        const C cu = dot_c<L>(i, vx, vy, vz);
+        const C e = fmac(rhoB, fmac(C(4.5) * cu, cu, fmac(C(3), cu, -usqB)), drB);
         g[i] = kRaw ? inv_sig * e : C(L::w(i)) * e;
       }
     }
@@ -492,11 +508,11 @@ __device__ __forceinline__ void collide_site(typename Store<T>::C (&g)[Q],
     // particle owns a wall site, so no BS exchange above touched it)
     C vx, vy, vz;
     if (wall_velocity(a, x, y, z, nx, ny, nz, vx, vy, vz)) {
-      const C usqW = C(1.5) * (vx * vx + vy * vy + vz * vz);
+      const C usqW = C(1.5) * fmac(vx, vx, fmac(vy, vy, vz * vz));
 #pragma unroll
       for (int i = 0; i < Q; i++) {
-        const C cu = C(L::cx(i)) * vx + C(L::cy(i)) * vy + C(L::cz(i)) * vz;
-        const C e = drho + rho * (C(3) * cu + C(4.5) * cu * cu - usqW);
+        const C cu = dot_c<L>(i, vx, vy, vz);
+        const C e = fmac(rho, fmac(C(4.5) * cu, cu, fmac(C(3), cu, -usqW)), drho);
         g[i] = kRaw ? inv_sig * e : C(L::w(i)) * e;
       }
     }
@@ -522,9 +538,8 @@ __device__ __forceinline__ void sweep_site(const T* A, T* B, const SweepArgs<Q, 
   // the flag is issued first and waited on only after the collision
   const int fl = PART ? (int)sa.flag[s] : 0;
   constexpr bool kRaw = std::is_same<T, _Float16>::value || std::is_same<T, bf16s>::value;
-  // Addresses: the plane of population i starts at a wave-uniform base (scalar
-  // registers) and the site is a 32-bit byte offset into it (a context keeps
-  // N sizeof(T) <= 2^32), so no 64-bit vector arithmetic per access.
+  // Addresses: the block's byte offset from one 32 x 32 -> 64-bit product and
+  // a 32-bit offset within the block (pop_at).
   C g[Q];
 #pragma unroll
   for (int i = 0; i < Q; i++) {
@@ -533,11 +548,12 @@ __device__ __forceinline__ void sweep_site(const T* A, T* B, const SweepArgs<Q, 
     const int sx = LAY == kLayAAStream ? x : (L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x));
     const int sy = LAY == kLayAAStream ? y : (L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y));
     const int sz = LAY == kLayAAStream ? z : (L::cz(i) > 0 ? zm : (L::cz(i) < 0 ? zp : z));
-    const T* src = pop_at<Q, T>(A, LAY == kLayAASwap ? opposite<Q>(i) : i, a.N, off + sx + nx * (sy + ny * sz));
+    const T* src = pop_at<Q, T>(A, LAY == kLayAASwap ? opposite<Q>(i) : i, off + sx + nx * (sy + ny * sz));
     const C h = NTL ? Store<T>::ldnt(src) : Store<T>::ld(src);
     g[i] = kRaw ? h : h * (C)pop_unit<T>(L::w(i));
   }
-  collide_site<Q, T, PART>(g, a, sa, s, fl, x, y, z, nx, ny, nz, fbt);
+  const RecOf<T> rec = PART ? site_record(sa, s, fl) : RecOf<T>{};
+  collide_site<Q, T, PART>(g, a, sa, s, fl, rec, x, y, z, nx, ny, nz, fbt);
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     // f*_i(x): at x in the next array, in the opposite slot at x, or pushed to
@@ -545,7 +561,7 @@ __device__ __forceinline__ void sweep_site(const T* A, T* B, const SweepArgs<Q, 
     const int dx = LAY == kLayAASwap ? (L::cx(i) > 0 ? xp : (L::cx(i) < 0 ? xm : x)) : x;
     const int dy = LAY == kLayAASwap ? (L::cy(i) > 0 ? yp : (L::cy(i) < 0 ? ym : y)) : y;
     const int dz = LAY == kLayAASwap ? (L::cz(i) > 0 ? zp : (L::cz(i) < 0 ? zm : z)) : z;
-    T* dst = pop_at<Q, T>(B, LAY == kLayAAStream ? opposite<Q>(i) : i, a.N, off + dx + nx * (dy + ny * dz));
+    T* dst = pop_at<Q, T>(B, LAY == kLayAAStream ? opposite<Q>(i) : i, off + dx + nx * (dy + ny * dz));
     if constexpr (kRaw)
       Store<T>::st(dst, g[i]);
     else
@@ -561,6 +577,133 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(const T* A, T* B, SweepAr
   const int x = (int)blockIdx.x * kSweepBlock + (int)threadIdx.x;
   if (x >= a.nx) return;
   sweep_site<Q, T, PART, LAY, true>(A, B, a, sa, x, (int)blockIdx.y, (int)blockIdx.z, a.nx, a.ny, a.nz, 0, a.fbt);
+}
+
+// 16-bit storage, two arrays, nx even: two sites per lane.  A wave takes 128
+// consecutive sites of a row (64 site pairs, x even), so each population is
+// one aligned 4-byte load per lane, 256 bytes per wave as FP32 moves with one
+// site per lane (2-byte loads of one site per lane stream about 10 % slower).
+// The pull's shift by one site along x (populations with c_x != 0) is rebuilt
+// from the neighbouring lane's word (DPP wave shift by one lane) and, at the
+// wave's two ends, from the word past the end: the last word of the wave
+// before it in the row (periodic) or the first word of the one after it.
+// Those waves load these words for themselves; when they belong to the same
+// workgroup (every wave of the 256^3 box: two rows of two waves) the words
+// are passed through LDS, otherwise loaded once more with a wave-uniform
+// load (such loads missed the caches and fetched a line from HBM each).
+// Each site collides as in sweep_site (collide_site), so the results are the
+// same bits.  Lanes past the row's end repeat its last pair and store
+// nothing; waves past the last row repeat it and store nothing, so that
+// every wave of the workgroup meets its barrier.
+template <typename T>
+__device__ __forceinline__ float half_lo(uint32_t v) {
+  if constexpr (std::is_same<T, _Float16>::value)
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(v & 0xffffu));
+  else
+    return bf16_bits_to_f32((uint16_t)(v & 0xffffu));
+}
+template <typename T>
+__device__ __forceinline__ uint32_t half_bits(float v) {
+  if constexpr (std::is_same<T, _Float16>::value)
+    return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)v);
+  else
+    return (uint32_t)f32_to_bf16_bits(v);
+}
+constexpr int kPairRow = 128;  // sites of a row per wave of k_sweep_pairs
+// Index of population i among those with c_x != 0 (and their count, i = Q).
+template <typename Lt>
+__host__ __device__ constexpr int x_shifted_before(int i) {
+  int n = 0;
+  for (int k = 0; k < i; k++) n += Lt::cx(k) != 0;
+  return n;
+}
+
+template <int Q, typename T, bool PART>
+__global__ __launch_bounds__(kSweepBlock) void k_sweep_pairs(const T* __restrict__ A, T* __restrict__ B,
+                                                              SweepArgs<Q, float> a, SiteArgs<T> sa) {
+  static_assert(sizeof(T) == 2, "two sites per lane: 16-bit storage");
+  using L = Lattice<Q>;
+  constexpr int kWaves = kSweepBlock / 64;
+  constexpr int kShift = x_shifted_before<L>(Q);
+  __shared__ uint32_t s_edge[kWaves][2][kShift];  // [wave][first, last word][shifted population]
+  const int lane = (int)threadIdx.x & 63;
+  // wave-uniform: the row chunk of this wave (the last one for waves past it)
+  const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int cpr = (nx + kPairRow - 1) / kPairRow;
+  const int items = cpr * ny * nz;
+  const int w0 = (int)blockIdx.x * kWaves;
+  const bool live = w0 + wv < items;
+  const int item = live ? w0 + wv : items - 1;
+  const int row = item / cpr, chunk = item - row * cpr, xw = chunk * kPairRow;
+  const int y = row % ny, z = row / ny;
+  const int npair = min(kPairRow / 2, (nx - xw) / 2);
+  const bool act = live && lane < npair;
+  const int x = xw + 2 * min(lane, npair - 1);
+  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+  const int s = x + nx * (y + ny * z);
+  // the pair's two flag bytes (s even: one aligned 2-byte load)
+  const int fl2 = PART ? (int)*(const uint16_t*)(sa.flag + s) : 0;
+  // the waves before and after this one along the row (periodic), and
+  // whether this workgroup holds them; otherwise the word past the end is
+  // loaded here: sites (xl, xl + 1) hold x - 1 of the first site, (xr, xr + 1)
+  // x + 1 of the last
+  const int left = chunk == 0 ? item + cpr - 1 : item - 1;
+  const int right = chunk == cpr - 1 ? item - (cpr - 1) : item + 1;
+  const bool left_here = live && left >= w0 && left < w0 + kWaves;
+  const bool right_here = live && right >= w0 && right < w0 + kWaves;
+  const int xl = xw == 0 ? nx - 2 : xw - 2;
+  const int xr = xw + 2 * npair == nx ? 0 : xw + 2 * npair;
+  uint32_t d[Q], e[Q];
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
+    const int sz = L::cz(i) > 0 ? zm : (L::cz(i) < 0 ? zp : z);
+    const int rs = nx * (sy + ny * sz);
+    d[i] = __builtin_nontemporal_load((const uint32_t*)pop_at<Q, T>(A, i, rs + x));
+    e[i] = 0;
+    if (L::cx(i) > 0 && !left_here) e[i] = *(const uint32_t*)pop_at<Q, T>(A, i, rs + xl);
+    if (L::cx(i) < 0 && !right_here) e[i] = *(const uint32_t*)pop_at<Q, T>(A, i, rs + xr);
+  }
+  // the records of owned BS sites, issued before the populations are waited on
+  const int fa = act ? fl2 & 0xff : 0, fb = act ? fl2 >> 8 : 0;
+  const RecOf<T> ra = PART ? site_record(sa, s, fa) : RecOf<T>{};
+  const RecOf<T> rb = PART ? site_record(sa, s + 1, fb) : RecOf<T>{};
+  // pass the first and last words of the shifted populations to the
+  // neighbouring waves of this workgroup
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    if (L::cx(i) == 0) continue;
+    const int k = x_shifted_before<L>(i);
+    if (lane == 0) s_edge[wv][0][k] = d[i];
+    if (lane == npair - 1) s_edge[wv][1][k] = d[i];
+  }
+  __syncthreads();
+  float ga[Q], gb[Q];
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    uint32_t v = d[i];
+    const int k = x_shifted_before<L>(i);
+    if (L::cx(i) > 0) {  // from x - 1: the high half of the previous word, the low half of this one
+      uint32_t p = __builtin_amdgcn_update_dpp(0u, d[i], 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
+      if (lane == 0) p = left_here ? s_edge[left - w0][1][k] : e[i];
+      v = __builtin_amdgcn_alignbit(d[i], p, 16);
+    } else if (L::cx(i) < 0) {  // from x + 1: the high half of this word, the low half of the next one
+      uint32_t n = __builtin_amdgcn_update_dpp(0u, d[i], 0x130 /* wave_shl:1 */, 0xf, 0xf, false);
+      if (lane == npair - 1) n = right_here ? s_edge[right - w0][0][k] : e[i];
+      v = __builtin_amdgcn_alignbit(n, d[i], 16);
+    }
+    ga[i] = half_lo<T>(v);
+    gb[i] = half_lo<T>(v >> 16);
+  }
+  collide_site<Q, T, PART>(ga, a, sa, s, fa, ra, x, y, z, nx, ny, nz, a.fbt);
+  collide_site<Q, T, PART>(gb, a, sa, s + 1, fb, rb, x + 1, y, z, nx, ny, nz, a.fbt);
+  if (act) {
+#pragma unroll
+    for (int i = 0; i < Q; i++)
+      __builtin_nontemporal_store(half_bits<T>(ga[i]) | (half_bits<T>(gb[i]) << 16), (uint32_t*)pop_at<Q, T>(B, i, s));
+  }
 }
 
 // q = n / d for 0 <= n < 2^31, 1 <= d, from inv = 1/d rounded to FP64: the
@@ -1231,13 +1374,13 @@ __global__ __launch_bounds__(256) void k_closure(DevParticles P, int np, Boxes B
 // ---------------------------------------------------------------------------
 // Element of f*_i of site (x, y, z) of box G in a post-collision state of
 // layout lay (kLayAB, or either half of the AA pattern).
-template <int Q, typename T>
-__device__ __forceinline__ size_t coll_index(int lay, int i, const Geo& G, int x, int y, int z, int64_t NT) {
+template <int Q>
+__device__ __forceinline__ size_t coll_index(int lay, int i, const Geo& G, int x, int y, int z) {
   using L = Lattice<Q>;
   if (lay == kLayAAStream)
-    return (size_t)pop_elem<Q, T>(
-        i, site_of(G, wrap1(x + L::cx(i), G.nx), wrap1(y + L::cy(i), G.ny), wrap1(z + L::cz(i), G.nz)), NT);
-  return (size_t)pop_elem<Q, T>(lay == kLayAASwap ? opposite<Q>(i) : i, site_of(G, x, y, z), NT);
+    return (size_t)pop_elem(
+        Q, i, site_of(G, wrap1(x + L::cx(i), G.nx), wrap1(y + L::cy(i), G.ny), wrap1(z + L::cz(i), G.nz)));
+  return (size_t)pop_elem(Q, lay == kLayAASwap ? opposite<Q>(i) : i, site_of(G, x, y, z));
 }
 
 // Streaming store of one stored population value.
@@ -1249,7 +1392,7 @@ __device__ __forceinline__ void nt_put(bf16s* p, bf16s v) { __builtin_nontempora
 // IS values of site s (offset o of particle p with the particle's velocities
 // in the compute type; the value is stored in it).
 template <int Q, typename T, bool NTS>
-__device__ __forceinline__ void impose_is(T* __restrict__ S, int64_t NT, int lay, const Geo& G, int x, int y, int z,
+__device__ __forceinline__ void impose_is(T* __restrict__ S, int lay, const Geo& G, int x, int y, int z,
                                           double dr, typename Store<T>::C rx,
                                           typename Store<T>::C ry, typename Store<T>::C rz,
                                           typename Store<T>::C upx, typename Store<T>::C upy,
@@ -1267,7 +1410,7 @@ __device__ __forceinline__ void impose_is(T* __restrict__ S, int64_t NT, int lay
   for (int i = 0; i < Q; i++) {
     const C cu = C(L::cx(i)) * vx + C(L::cy(i)) * vy + C(L::cz(i)) * vz;
     const T v = pop_enc<Q, T>(i, (double)(C(L::w(i)) * (dc + rho * (C(3) * cu + C(4.5) * cu * cu - usq))));
-    T* const dst = S + coll_index<Q, T>(lay, i, G, x, y, z, NT);
+    T* const dst = S + coll_index<Q>(lay, i, G, x, y, z);
     // NTS (the AA pattern, whose next sweep reads and rewrites these lines in
     // place): streaming stores keep the partly written lines out of the
     // caches; with two arrays they only move the same cost from the sweep here
@@ -1316,11 +1459,11 @@ __global__ __launch_bounds__(256) void k_prepare(const int* __restrict__ own,
     if (P.jump[p]) {
       dr = 0;
 #pragma unroll
-      for (int j = 0; j < Q; j++) dr += (double)pop_ld<Q, T>(S + coll_index<Q, T>(lay, j, G, x, y, z, BX.PS), j);
+      for (int j = 0; j < Q; j++) dr += (double)pop_ld<Q, T>(S + coll_index<Q>(lay, j, G, x, y, z), j);
     } else {
       dr = (double)drho[s];
     }
-    impose_is<Q, T, NTS>(S, BX.PS, lay, G, x, y, z, dr, (C)((double)off_x(pk) - P.phi[3 * p]),
+    impose_is<Q, T, NTS>(S, lay, G, x, y, z, dr, (C)((double)off_x(pk) - P.phi[3 * p]),
                     (C)((double)off_y(pk) - P.phi[3 * p + 1]),
                     (C)((double)off_z(pk) - P.phi[3 * p + 2]), (C)P.u[3 * p], (C)P.u[3 * p + 1], (C)P.u[3 * p + 2],
                     (C)P.om[3 * p], (C)P.om[3 * p + 1], (C)P.om[3 * p + 2], rho0);
@@ -1461,11 +1604,11 @@ __global__ __launch_bounds__(kGridBlock) void k_prepare_grid(uint8_t* __restrict
         if (jump) {
           dr = 0;
 #pragma unroll
-          for (int k = 0; k < Q; k++) dr += (double)pop_ld<Q, T>(S + coll_index<Q, T>(lay, k, G, sxx, syy, szz, BX.PS), k);
+          for (int k = 0; k < Q; k++) dr += (double)pop_ld<Q, T>(S + coll_index<Q>(lay, k, G, sxx, syy, szz), k);
         } else {
           dr = (double)dv[j];
         }
-        impose_is<Q, T, NTS>(S, BX.PS, lay, G, sxx, syy, szz, dr, (C)((double)ox - phx), (C)((double)oy - phy),
+        impose_is<Q, T, NTS>(S, lay, G, sxx, syy, szz, dr, (C)((double)ox - phx), (C)((double)oy - phy),
                              (C)((double)oz - phz), cupx, cupy, cupz, cwx, cwy, cwz, rho0);
       }
       if (flags) flag[s] = okind == 1 ? kSiteBS : kSiteBall;
@@ -1498,11 +1641,10 @@ __global__ __launch_bounds__(kGridBlock) void k_prepare_grid(uint8_t* __restrict
 // ---------------------------------------------------------------------------
 // Read-out and set-up kernels (off the step loop).
 // ---------------------------------------------------------------------------
-// Moments of sites s0 .. s0 + cnt - 1 of box G (box-local indices); PS is
-// the stride of the population array.
+// Moments of sites s0 .. s0 + cnt - 1 of box G (box-local indices).
 template <int Q, typename T>
 __global__ void k_moments(const T* __restrict__ A, double* __restrict__ rho, double* __restrict__ u,
-                          Geo G, int64_t PS, double rho0, int64_t s0, int64_t cnt, int lay) {
+                          Geo G, double rho0, int64_t s0, int64_t cnt, int lay) {
   using L = Lattice<Q>;
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= cnt) return;
@@ -1516,7 +1658,7 @@ __global__ void k_moments(const T* __restrict__ A, double* __restrict__ rho, dou
     const int sx = here ? x : wrap(x - L::cx(i), G.nx), sy = here ? y : wrap(y - L::cy(i), G.ny),
               sz = here ? z : wrap(z - L::cz(i), G.nz);
     const int plane = lay == kLayAASwap ? opposite<Q>(i) : i;
-    const double g = (double)pop_ld<Q, T>(A + pop_elem<Q, T>(plane, site_of(G, sx, sy, sz), PS), i);
+    const double g = (double)pop_ld<Q, T>(A + pop_elem(Q, plane, site_of(G, sx, sy, sz)), i);
     drho += g;
     j[0] += L::cx(i) * g;
     j[1] += L::cy(i) * g;
@@ -1530,7 +1672,7 @@ __global__ void k_moments(const T* __restrict__ A, double* __restrict__ rho, dou
 // B_i(s) = A_i(s - dir * c_i) over the sites of box G: dir = +1 pulls
 // (state -> post-stream f), dir = -1 pushes (post-stream f -> state).
 template <int Q, typename T>
-__global__ void k_shift(const T* __restrict__ A, T* __restrict__ B, Geo G, int64_t PS, int dir) {
+__global__ void k_shift(const T* __restrict__ A, T* __restrict__ B, Geo G, int dir) {
   using L = Lattice<Q>;
   const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (s >= G.N) return;
@@ -1539,7 +1681,7 @@ __global__ void k_shift(const T* __restrict__ A, T* __restrict__ B, Geo G, int64
   for (int i = 0; i < Q; i++) {
     const int sx = wrap(x - dir * L::cx(i), G.nx), sy = wrap(y - dir * L::cy(i), G.ny),
               sz = wrap(z - dir * L::cz(i), G.nz);
-    B[pop_elem<Q, T>(i, G.off + s, PS)] = A[pop_elem<Q, T>(i, site_of(G, sx, sy, sz), PS)];
+    B[pop_elem(Q, i, G.off + s)] = A[pop_elem(Q, i, site_of(G, sx, sy, sz))];
   }
 }
 
@@ -1610,22 +1752,13 @@ BoxSet make_boxset(int nbox, const int32_t* dims) {
 
 size_t store_size(int storage) { return storage == LBM_FP64 ? 8 : storage == LBM_FP32 ? 4 : 2; }
 
-// Stride N of the population array (see pop_elem).  Blocked storages: the
-// sites rounded up to whole blocks.  Planes are padded past a multiple of 256
-// sites: plane strides that are multiples of large powers of two put a site's
-// populations on the same DRAM banks (with 256 sites of padding the 256^3
-// two-array sweep ran 2.7 % faster than unpadded).  For 16-bit planes of at
-// least 2^20 sites 8448 sites of padding were best (0.7 % faster than 256;
-// whole 256^3 step with 500 spheres, paddings of 64 to 8448 sites).
-int64_t plane_stride(int64_t sites, int storage) {
-  if (pop_blocked(storage)) return (sites + kPopBlock - 1) / kPopBlock * kPopBlock;
-  const int64_t pad = sites < ((int64_t)1 << 20) ? 256 : 8448;
-  return (sites + 255) / 256 * 256 + pad;
-}
+// Sites of the population array: the sites rounded up to whole blocks (see
+// pop_elem); the array holds q times as many values.
+int64_t pop_stride(int64_t sites) { return (sites + kPopBlock - 1) / kPopBlock * kPopBlock; }
 
-// The sweep addresses a site within a population plane with a 32-bit byte
-// offset (the plane's own base is a 64-bit scalar); blocked storages need no
-// such bound, but every storage keeps it.
+// One population of the array spans at most 4 GiB (N sizeof(T) <= 2^32): a
+// limit of the interface, which caps FP64 boxes at 2^29 sites and 16-bit
+// ones at the 2^31 sites the 32-bit site indices of the kernels allow.
 bool plane_fits(int storage, int64_t sites) { return (uint64_t)sites * store_size(storage) <= ((uint64_t)1 << 32); }
 
 // Bytes of one particle's kind grid: offsets of a template lie within
@@ -1660,7 +1793,7 @@ Layout make_layout(const lbm_params& p, const BoxSet& bs) {
     cur += (bytes + kAlign - 1) / kAlign * kAlign;
     return at;
   };
-  const size_t fb = (size_t)p.lattice * plane_stride(N, p.storage) * store_size(p.storage);
+  const size_t fb = (size_t)p.lattice * pop_stride(N) * store_size(p.storage);
   L.f[0] = take(fb);
   L.f[1] = p.aa ? L.f[0] : take(fb);  // the AA pattern updates one array in place
   L.drho = take((size_t)N * (p.storage == LBM_FP64 ? 8 : 4));
@@ -1765,7 +1898,7 @@ struct lbm_ctx {
   Geo G;                    // box 0 (the box of a single-box context)
   int nbox;
   int64_t NT;               // sites of all boxes
-  int64_t PS;               // population array stride (see pop_elem)
+  int64_t PS;               // sites of the population array (see pop_stride)
   std::vector<Geo> boxes;   // host copy of the box table
   Geo* d_boxes;
   void* d_fbt;              // [nbox][q] 3 w_i c_i . f_b per box, compute type
@@ -1848,8 +1981,6 @@ Boxes boxes_arg(const lbm_ctx* c) {
   b.g0 = c->boxes[0];
   b.tab = c->d_boxes;
   b.nbox = c->nbox;
-  b.NT = c->NT;
-  b.PS = c->PS;
   return b;
 }
 
@@ -1928,7 +2059,6 @@ SweepArgs<Q, typename Store<T>::C> sweep_args(const lbm_ctx* c) {
   a.ny = c->G.ny;
   a.nz = c->G.nz;
   a.nxb = (c->G.nx + kSweepBlock - 1) / kSweepBlock;
-  a.N = c->PS;  // the sweep's population array stride
   a.omega = (C)(1.0 / c->prm.tau);
   a.rho0 = (C)c->prm.rho0;
   a.walls = c->prm.walls;
@@ -1961,6 +2091,18 @@ int launch_sweep_as(lbm_ctx* c, int w, int grid, int occ) {
   T* B = (T*)c->f[1 - c->cur];  // the same array under the AA pattern
   const SiteArgs<T> sa = site_args<Q, T>(c);
   if (w == 0) {
+    if constexpr (sizeof(T) == 2 && LAY == kLayAB) {
+      if (a.nx % 2 == 0) {  // two sites per lane: one wave per 128 sites of a row
+        const int64_t waves = (int64_t)((a.nx + kPairRow - 1) / kPairRow) * c->G.ny * c->G.nz;
+        const unsigned g = (unsigned)((waves + kSweepBlock / 64 - 1) / (kSweepBlock / 64));
+        if (c->np > 0)
+          k_sweep_pairs<Q, T, true><<<g, kSweepBlock, lds, c->stream>>>(A, B, a, sa);
+        else
+          k_sweep_pairs<Q, T, false><<<g, kSweepBlock, lds, c->stream>>>(A, B, a, sa);
+        HIP_TRY(hipGetLastError());
+        return LBM_OK;
+      }
+    }
     const dim3 grid3((unsigned)a.nxb, (unsigned)c->G.ny, (unsigned)c->G.nz);
     if (c->np > 0)
       k_sweep<Q, T, true, LAY><<<grid3, kSweepBlock, lds, c->stream>>>(A, B, a, sa);
@@ -2054,7 +2196,7 @@ int launch_step(lbm_ctx* c) {
 
 template <int Q, typename T>
 int launch_moments(lbm_ctx* c, int box, double* d_rho, double* d_u, int64_t s0, int64_t cnt) {
-  k_moments<Q, T><<<blocks_for(cnt), 256, 0, c->stream>>>((const T*)c->f[c->cur], d_rho, d_u, c->boxes[box], c->PS,
+  k_moments<Q, T><<<blocks_for(cnt), 256, 0, c->stream>>>((const T*)c->f[c->cur], d_rho, d_u, c->boxes[box],
                                                           c->prm.rho0, s0, cnt, state_layout(c));
   HIP_TRY(hipGetLastError());
   return LBM_OK;
@@ -2063,7 +2205,7 @@ int launch_moments(lbm_ctx* c, int box, double* d_rho, double* d_u, int64_t s0, 
 template <int Q, typename T>
 int launch_shift(lbm_ctx* c, const void* A, void* B, int dir) {
   for (int b = 0; b < c->nbox; b++)
-    k_shift<Q, T><<<blocks_for(c->boxes[b].N), 256, 0, c->stream>>>((const T*)A, (T*)B, c->boxes[b], c->PS, dir);
+    k_shift<Q, T><<<blocks_for(c->boxes[b].N), 256, 0, c->stream>>>((const T*)A, (T*)B, c->boxes[b], dir);
   HIP_TRY(hipGetLastError());
   return LBM_OK;
 }
@@ -2288,7 +2430,7 @@ static int create_impl(const lbm_params* prm, int nbox, const int32_t* dims, voi
   c->dim = prm->lattice == LBM_D2Q9 ? 2 : 3;
   c->nbox = nbox;
   c->NT = bset.NT;
-  c->PS = plane_stride(bset.NT, prm->storage);
+  c->PS = pop_stride(bset.NT);
   int64_t off = 0;
   for (int b = 0; b < nbox; b++) {
     const int nx = dims[3 * b], ny = dims[3 * b + 1], nz = dims[3 * b + 2];
@@ -2780,6 +2922,22 @@ int lbm_get_sweep_config(lbm_ctx* c, int32_t* width, int32_t* grid, int32_t* blo
   return LBM_OK;
 }
 
+// The sweep launches both tuners try: shapes x occupancy caps (fewer
+// resident waves can stream faster).
+struct SweepCand {
+  int w, g, occ;
+};
+static std::vector<SweepCand> sweep_candidates(const lbm_ctx* c, int ncu) {
+  std::vector<SweepCand> cands;
+  for (int occ : {0, 6, 5, 4, 3, 2}) {
+    if (!occ_ok(c, occ)) continue;
+    if (c->row_ok) cands.push_back({0, 0, occ});
+    for (int w : {64, 128, 256, 512})
+      for (int k : {0, 4, 8, 16, 32}) cands.push_back({w, k * ncu, occ});
+  }
+  return cands;
+}
+
 int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* width, int32_t* grid, int32_t* blocks_per_cu,
                  double* best_ms) {
   if (!c || reps < 1) return LBM_EINVAL;
@@ -2791,39 +2949,57 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* width, int32_t* grid, int32_
   int dev = 0, ncu = 0;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  struct Cand {
-    int w, g, occ;
-  };
-  // shapes x occupancy caps (fewer resident waves can stream faster)
-  std::vector<Cand> cands;
-  for (int occ : {0, 6, 5, 4, 3, 2}) {
-    if (!occ_ok(c, occ)) continue;
-    if (c->row_ok) cands.push_back({0, 0, occ});
-    for (int w : {64, 128, 256, 512})
-      for (int k : {0, 4, 8, 16, 32}) cands.push_back({w, k * ncu, occ});
-  }
+  const std::vector<SweepCand> cands = sweep_candidates(c, ncu);
+  using Cand = SweepCand;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   int rc = LBM_OK;
-  double best = 1e300;
-  Cand win = {c->sweep_w, c->sweep_grid, c->sweep_occ};
-  for (const Cand& cd : cands) {
-    if (tile_width(cd.w) && (rc = build_tiles(c, cd.w)) != LBM_OK) break;
-    if ((rc = DISPATCH(c, launch_sweep, c, cd.w, cd.g, cd.occ)) != LBM_OK) break;  // warm-up
-    if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = LBM_EHIP; break; }
-    for (int r = 0; r < reps && rc == LBM_OK; r++) rc = DISPATCH(c, launch_sweep, c, cd.w, cd.g, cd.occ);
-    if (rc != LBM_OK) break;
+  // time `n` sweeps of one candidate (after one untimed), in ms per sweep
+  auto time_cand = [&](const Cand& cd, int n, double& ms_out) {
+    if (tile_width(cd.w) && (rc = build_tiles(c, cd.w)) != LBM_OK) return false;
+    if ((rc = DISPATCH(c, launch_sweep, c, cd.w, cd.g, cd.occ)) != LBM_OK) return false;  // warm-up
+    if (hipEventRecord(e0, c->stream) != hipSuccess) {
+      rc = LBM_EHIP;
+      return false;
+    }
+    for (int r = 0; r < n && rc == LBM_OK; r++) rc = DISPATCH(c, launch_sweep, c, cd.w, cd.g, cd.occ);
+    if (rc != LBM_OK) return false;
     float ms = 0;
     if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
         hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
       rc = LBM_EHIP;
-      break;
+      return false;
     }
-    if (ms / reps < best) {
-      best = ms / reps;
-      win = cd;
-    }
+    ms_out = ms / n;
+    return true;
+  };
+  // every candidate once, then the four fastest again in two alternating
+  // rounds of twice the sweeps (a single short timing misranks candidates
+  // within a few per cent of each other)
+  std::vector<std::pair<double, int>> first;
+  for (size_t k = 0; k < cands.size(); k++) {
+    double ms = 0;
+    if (!time_cand(cands[k], reps, ms)) break;
+    first.push_back({ms, (int)k});
+  }
+  double best = 1e300;
+  Cand win = {c->sweep_w, c->sweep_grid, c->sweep_occ};
+  if (rc == LBM_OK) {
+    std::sort(first.begin(), first.end());
+    const size_t top = std::min<size_t>(4, first.size());
+    std::vector<double> sum(top, 0.0);
+    for (int round = 0; round < 2 && rc == LBM_OK; round++)
+      for (size_t t = 0; t < top; t++) {
+        double ms = 0;
+        if (!time_cand(cands[first[t].second], 2 * reps, ms)) break;
+        sum[t] += ms;
+      }
+    for (size_t t = 0; t < top && rc == LBM_OK; t++)
+      if (sum[t] / 2 < best) {
+        best = sum[t] / 2;
+        win = cands[first[t].second];
+      }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -2835,6 +3011,89 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* width, int32_t* grid, int32_
   if (blocks_per_cu) *blocks_per_cu = win.occ;
   if (best_ms) *best_ms = best;
   return LBM_OK;
+}
+
+int lbm_autotune_steps(lbm_ctx* c, int32_t steps, int32_t* width, int32_t* grid, int32_t* blocks_per_cu,
+                       double* best_ms, int64_t* steps_done) {
+  if (!c || steps < 1) return LBM_EINVAL;
+  if (c->failed) return LBM_EHIP;
+  int dev = 0, ncu = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const std::vector<SweepCand> cands = sweep_candidates(c, ncu);
+  // whole steps, an even number so that both halves of the AA pattern and
+  // both buffer roles count alike; with step graphs set, whole graphs (short
+  // steps launched one by one can be bound by the host's launch rate)
+  const int gs = c->graph_steps;
+  const int n1 = gs > 0 ? (steps + gs - 1) / gs * gs : steps + (steps & 1);
+  const int warm = gs > 0 ? gs : 2;
+  const bool prof = c->prof;
+  c->prof = false;
+  c->ev_used = 0;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int rc = LBM_OK;
+  int64_t done = 0;
+  auto time_cand = [&](const SweepCand& cd, int n, double& ms_out) {
+    if ((rc = lbm_set_sweep_config(c, cd.w, cd.g, cd.occ)) != LBM_OK) return false;
+    if ((rc = lbm_step(c, warm)) != LBM_OK) return false;  // untimed (captures a graph when set)
+    done += warm;
+    if (hipEventRecord(e0, c->stream) != hipSuccess) {
+      rc = LBM_EHIP;
+      return false;
+    }
+    if ((rc = lbm_step(c, n)) != LBM_OK) return false;
+    done += n;
+    float ms = 0;
+    if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      rc = LBM_EHIP;
+      return false;
+    }
+    ms_out = ms / n;
+    return true;
+  };
+  // every candidate once, then the four fastest again in two alternating
+  // rounds of twice the steps
+  std::vector<std::pair<double, int>> first;
+  for (size_t k = 0; k < cands.size(); k++) {
+    double ms = 0;
+    if (!time_cand(cands[k], n1, ms)) break;
+    first.push_back({ms, (int)k});
+  }
+  double best = 1e300;
+  SweepCand win = {c->sweep_w, c->sweep_grid, c->sweep_occ};
+  if (rc == LBM_OK) {
+    std::sort(first.begin(), first.end());
+    const size_t top = std::min<size_t>(4, first.size());
+    std::vector<double> sum(top, 0.0);
+    for (int round = 0; round < 2 && rc == LBM_OK; round++)
+      for (size_t t = 0; t < top; t++) {
+        double ms = 0;
+        if (!time_cand(cands[first[t].second], 2 * n1, ms)) break;
+        sum[t] += ms;
+      }
+    for (size_t t = 0; t < top && rc == LBM_OK; t++)
+      if (sum[t] / 2 < best) {
+        best = sum[t] / 2;
+        win = cands[first[t].second];
+      }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->prof = prof;
+  if (steps_done) *steps_done = done;
+  if (rc != LBM_OK) return rc;
+  rc = lbm_set_sweep_config(c, win.w, win.g, win.occ);
+  if (rc != LBM_OK) return rc;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (width) *width = win.w;
+  if (grid) *grid = win.g;
+  if (blocks_per_cu) *blocks_per_cu = win.occ;
+  if (best_ms) *best_ms = best;
+  return check_status(c);
 }
 
 int lbm_set_closure(lbm_ctx* c, const float* d_params, double h_max) {
@@ -2960,7 +3219,7 @@ int lbm_particle_info(lbm_ctx* c, int32_t p, int32_t* nbs, int32_t* nis) {
 int lbm_get_distributions(lbm_ctx* c, double* f) {
   if (!c || !f) return LBM_EINVAL;
   if (c->failed) return LBM_EHIP;
-  const int64_t n = (int64_t)c->q * c->PS;  // device planes (padded)
+  const int64_t n = (int64_t)c->q * c->PS;  // the device array (whole blocks)
   const int ss = (int)store_size(c->prm.storage);
   std::vector<unsigned char> h((size_t)n * ss);
   if (c->prm.aa) {
@@ -2975,7 +3234,6 @@ int lbm_get_distributions(lbm_ctx* c, double* f) {
   HIP_TRY(hipStreamSynchronize(c->stream));
   // element of the host copy that holds f_i of site s
   const int lay = state_layout(c);
-  const bool blk = pop_blocked(c->prm.storage);
   std::vector<int64_t> src;
   if (lay == kLayAASwap) {
     src.resize((size_t)c->q * c->NT);
@@ -2990,14 +3248,14 @@ int lbm_get_distributions(lbm_ctx* c, double* f) {
               const int o = c->q == 9 ? opposite<9>(i) : opposite<19>(i);
               const int64_t from = g.off + wrap(x - cx, g.nx) + (int64_t)g.nx * (wrap(y - cy, g.ny) +
                                                                                   (int64_t)g.ny * wrap(z - cz, g.nz));
-              src[(size_t)i * c->NT + g.off + x + (int64_t)g.nx * (y + (int64_t)g.ny * z)] = pop_elem(blk, c->q, o, from, c->PS);
+              src[(size_t)i * c->NT + g.off + x + (int64_t)g.nx * (y + (int64_t)g.ny * z)] = pop_elem(c->q, o, from);
             }
   }
   for (int i = 0; i < c->q; i++) {
     const double w = lattice_w(c->q, i);
     const double base = w * c->prm.rho0;
     for (int64_t s = 0; s < c->NT; s++) {
-      const int64_t k = src.empty() ? pop_elem(blk, c->q, i, s, c->PS) : src[(size_t)i * c->NT + s];
+      const int64_t k = src.empty() ? pop_elem(c->q, i, s) : src[(size_t)i * c->NT + s];
       double g;
       switch (c->prm.storage) {
         case LBM_FP64: g = ((const double*)h.data())[k]; break;
@@ -3018,15 +3276,14 @@ int lbm_set_distributions(lbm_ctx* c, const double* f) {
   for (int64_t i = 0; i < nf; i++)
     if (!std::isfinite(f[i])) return LBM_ENONFINITE;
   void* stage = c->f[1 - c->cur];
-  const int64_t n = (int64_t)c->q * c->PS;  // device planes (padded; padding zero)
+  const int64_t n = (int64_t)c->q * c->PS;  // the device array (whole blocks; the tail zero)
   const int ss = (int)store_size(c->prm.storage);
   std::vector<unsigned char> h((size_t)n * ss, 0);
-  const bool blk = pop_blocked(c->prm.storage);
   for (int i = 0; i < c->q; i++) {
     const double w = lattice_w(c->q, i);
     const double base = w * c->prm.rho0;
     for (int64_t s = 0; s < c->NT; s++) {
-      const int64_t k = pop_elem(blk, c->q, i, s, c->PS);
+      const int64_t k = pop_elem(c->q, i, s);
       const double g = f[(int64_t)i * c->NT + s] - base;
       switch (c->prm.storage) {
         case LBM_FP64: ((double*)h.data())[k] = g; break;

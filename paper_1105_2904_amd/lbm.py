@@ -75,6 +75,7 @@ def lib():
             "lbm_set_sweep_config": [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
             "lbm_get_sweep_config": [vp, _ip, _ip, _ip],
             "lbm_autotune": [vp, ctypes.c_int32, _ip, _ip, _ip, _dp],
+            "lbm_autotune_steps": [vp, ctypes.c_int32, _ip, _ip, _ip, _dp, ctypes.POINTER(ctypes.c_int64)],
             "lbm_set_graph": [vp, ctypes.c_int32],
             "lbm_step_noalloc": [vp, ctypes.c_int32],
             "lbm_set_closure": [vp, vp, ctypes.c_double],
@@ -265,6 +266,15 @@ class Simulation:
         _check(lib().lbm_autotune(self.ctx, int(reps), ctypes.byref(w), ctypes.byref(g), ctypes.byref(k),
                                   ctypes.byref(ms)), "lbm_autotune")
         return w.value, g.value, k.value, ms.value
+
+    def autotune_steps(self, steps=4):
+        """Picks and sets the fastest sweep launch timed inside whole steps;
+        returns (width, grid, blocks_per_cu, ms per step, steps it advanced the
+        simulation by)."""
+        w, g, k, ms, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double(), ctypes.c_int64()
+        _check(lib().lbm_autotune_steps(self.ctx, int(steps), ctypes.byref(w), ctypes.byref(g), ctypes.byref(k),
+                                        ctypes.byref(ms), ctypes.byref(n)), "lbm_autotune_steps")
+        return w.value, g.value, k.value, ms.value, n.value
 
     def set_closure(self, params, h_max=2.0):
         """Near-contact closure with the network parameters `params` (a float32

@@ -181,6 +181,39 @@ def test_ensemble_autotune_keeps_the_state():
     assert _same(runs[0], runs[1])
 
 
+@pytest.mark.parametrize("storage,aa,graph", [("fp16", False, 0), ("fp32", False, 4), ("bf16", True, 0)])
+def test_autotune_in_steps_advances_by_the_steps_it_reports(storage, aa, graph):
+    """The in-step tuner times every launch inside whole steps (whole graph
+    replays when step graphs are set), so it moves the simulation on:
+    afterwards the state is the state after the number of steps it reports
+    (every launch computes the same bits, eager or replayed), for two arrays
+    and for the AA pattern (which the sweep-only tuner refuses), and the
+    context keeps the launch it returns."""
+    q, box, r = 19, (70, 22, 18), 4.0
+    p = wl.suspension(q, box, 3, r, 1.5, seed=91)
+
+    def make():
+        sim = lbm.Simulation(q, *box, tau=0.7, gravity=(0, 0, -2e-5), zero_net_force=True, storage=storage,
+                             max_particles=3, max_radius=r, aa=aa)
+        sim.add_particles(p["x"], radius=p["radius"], mass=p["mass"], inertia=p["inertia"])
+        sim.step(3)
+        return sim
+
+    tuned, ref = make(), make()
+    tuned.set_graph(graph)
+    w, g, k, ms, n = tuned.autotune_steps(steps=2)
+    _say("in-step autotune", storage, "aa" if aa else "", (w, g, k), "%.4f ms/step" % ms, n, "steps")
+    assert tuned.sweep_config() == (w, g, k)
+    assert ms > 0 and n > 100 and (graph == 0 or n % graph == 0)
+    ref.step(n)
+    assert _same(_state(tuned), _state(ref))
+    for sim in (tuned, ref):
+        sim.step(7)
+    assert _same(_state(tuned), _state(ref))
+    tuned.close()
+    ref.close()
+
+
 def test_graph_replays_match_eager_launches():
     """Graph replays of 4 steps, with eager steps, read-outs and a particle
     added in between, give the same bits as eager launches every time."""

@@ -1,6 +1,8 @@
-"""Full-size parity of the benchmark workloads, the HIP path in the launch the
-benchmark times (the autotuner's pick on the live state) against the FP64
-oracle on the same seeded inputs, with particles that move: their integer
+"""Full-size parity of the benchmark workloads, the HIP path in a tuned launch
+(the sweep-only tuner's pick on the live state, which leaves the state as it
+is; every launch, including the one the benchmark's in-step tuner picks,
+computes the same bits) against the FP64 oracle on the same seeded inputs,
+with particles that move: their integer
 shifts change, so the map is rebuilt and the IS substep is imposed at new
 positions (section 2.2, third and fourth substeps; eq. 13-15).
 
