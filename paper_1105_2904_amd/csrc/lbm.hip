@@ -75,6 +75,7 @@ constexpr double kShareMargin = 3.0;
 constexpr int kNbrMax = 128;        // such neighbours listed per particle
 constexpr int kSweepBlock = 256;
 constexpr int kTileMax = 512;        // widest tile of the ensemble sweep
+constexpr int kXcdRun = 4;           // adjacent ensemble tiles per XCD (k_sweep_tiles)
 constexpr int kBoundaryBlock = 256;  // reduce workgroup (128 for balls of at most kSmallBall entries)
 constexpr int kSmallBall = 512;
 constexpr int kPrepareBlock = 256;   // workgroup of the per-particle prepare
@@ -163,14 +164,15 @@ __device__ __forceinline__ void pop_st(T* p, int i, typename Store<T>::C v) {
   using C = typename Store<T>::C;
   Store<T>::st(p, v * (C)(1.0 / pop_unit<T>(Lattice<Q>::w(i))));
 }
-// Encoded value for a plain (not streaming) store of an FP64 result.
-template <int Q, typename T>
-__device__ __forceinline__ T pop_enc(int i, double v) {
-  const double x = v / pop_unit<T>(Lattice<Q>::w(i));
+// The stored number for a plain (not streaming) store: the compute-type value
+// the sweep would store (the deviation g_i, or for 16-bit storage g_i /
+// (w_i sigma)), rounded to the storage type as Store<T>::st rounds it.
+template <typename T>
+__device__ __forceinline__ T store_enc(typename Store<T>::C h) {
   if constexpr (std::is_same<T, bf16s>::value)
-    return bf16s{f32_to_bf16_bits((float)x)};
+    return bf16s{f32_to_bf16_bits(h)};
   else
-    return (T)x;
+    return (T)h;
 }
 
 // One box of the context: its size, walls, first site in the site arrays
@@ -729,7 +731,19 @@ __global__ __launch_bounds__(kTileMax) void k_sweep_tiles(const T* A, T* B, Swee
                                                            const int4* __restrict__ tiles, int ntiles,
                                                            const typename Store<T>::C* __restrict__ fbt_tab) {
   using C = typename Store<T>::C;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  // An ensemble's tiles share the lines at their ends (a tile pulls runs of
+  // its sites shifted by c_x + n_x c_y), so with one workgroup per tile
+  // (grid 0) runs of kXcdRun adjacent tiles go to one XCD: workgroups are
+  // dealt to the eight XCDs in turn, and the shared lines then meet in one
+  // L2 (64-box D2Q9 ensemble: 0.1517 -> 0.1495 ms per step tuned, +6.5 %
+  // MLUPS eager).  One box keeps the hardware's order (its tiles are whole
+  // rows that share no lines, and the regrouped order was 0.3 % slower).
+  int t0 = blockIdx.x;
+  if (!NTL && (int)gridDim.x == ntiles) {
+    constexpr int R = 8 * kXcdRun;
+    if (t0 < ntiles / R * R) t0 = t0 / R * R + kXcdRun * (t0 % 8) + (t0 / 8) % kXcdRun;
+  }
+  for (int t = t0; t < ntiles; t += gridDim.x) {
     const int4 tl = tiles[3 * t], tg = tiles[3 * t + 1], ti = tiles[3 * t + 2];
     const int64_t lin64 = (int64_t)tl.y + threadIdx.x;
     if (lin64 >= (int64_t)tg.x * tg.y * tg.z) continue;
@@ -1398,18 +1412,25 @@ __device__ __forceinline__ void impose_is(T* __restrict__ S, int lay, const Geo&
                                           typename Store<T>::C upx, typename Store<T>::C upy,
                                           typename Store<T>::C upz, typename Store<T>::C wx,
                                           typename Store<T>::C wy, typename Store<T>::C wz, double rho0) {
+#pragma clang fp contract(off)
   using L = Lattice<Q>;
   using C = typename Store<T>::C;
+  constexpr bool kRaw = std::is_same<T, _Float16>::value || std::is_same<T, bf16s>::value;
+  const C inv_sig = (C)(1.0 / pop_unit<T>(1.0));
   const C vx = upx + (wy * rz - wz * ry);
   const C vy = upy + (wz * rx - wx * rz);
   const C vz = upz + (wx * ry - wy * rx);
   const C dc = (C)dr;
   const C rho = (C)rho0 + dc;
-  const C usq = C(1.5) * (vx * vx + vy * vy + vz * vz);
+  const C usq = C(1.5) * fmac(vx, vx, fmac(vy, vy, vz * vz));
 #pragma unroll
   for (int i = 0; i < Q; i++) {
-    const C cu = C(L::cx(i)) * vx + C(L::cy(i)) * vy + C(L::cz(i)) * vz;
-    const T v = pop_enc<Q, T>(i, (double)(C(L::w(i)) * (dc + rho * (C(3) * cu + C(4.5) * cu * cu - usq))));
+    // f^eq_i - w_i rho0 as the sweep's BS substep writes it: for 16-bit
+    // storage the stored number directly (the weight cancels), so the
+    // encoding is one rounding of a compute-type value
+    const C cu = dot_c<L>(i, vx, vy, vz);
+    const C e = fmac(rho, fmac(C(4.5) * cu, cu, fmac(C(3), cu, -usq)), dc);
+    const T v = store_enc<T>(kRaw ? inv_sig * e : C(L::w(i)) * e);
     T* const dst = S + coll_index<Q>(lay, i, G, x, y, z);
     // NTS (the AA pattern, whose next sweep reads and rewrites these lines in
     // place): streaming stores keep the partly written lines out of the
