@@ -1067,7 +1067,9 @@ __global__ __launch_bounds__(NB) void k_reduce(int* __restrict__ own,
   const double xj1 = P.x[3 * jc], yj1 = P.x[3 * jc + 1], zj1 = P.x[3 * jc + 2], rj1 = P.rad[jc];
 
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  const int ne = nbs + nis + nin;
+  // the sums need the BS entries (the first nbs of the particle); releasing
+  // the map and flags (owner-map mode) needs every entry
+  const int ne = GRID ? nbs : nbs + nis + nin;
   constexpr int kEnt = 4;  // entries per thread whose loads are issued together
   for (int tb = 0; tb < ne; tb += NB * kEnt) {
     // every entry's offset and slot, loaded together and without per-lane
@@ -1589,27 +1591,33 @@ __global__ __launch_bounds__(kGridBlock) void k_prepare_grid(uint8_t* __restrict
       }
     }
   };
+  // The entries come kind by kind (BS, IS, interior), so they are dealt in
+  // runs of 64 (one wave each) round-robin over the particle's split
+  // workgroups, which then share the IS substep's stores evenly: run c goes
+  // to workgroup c % split, whose waves take its runs in turn.
   constexpr int kEnt = 4;
-  for (int rb = part; rb * kGridBlock < ne; rb += split * kEnt) {
+  const int wv = tid >> 6, lane = tid & 63;
+  constexpr int kWv = kGridBlock / 64;
+  auto run0 = [&](int m) { return (part + split * (kWv * m + wv)) * 64; };  // this wave's m-th run
+  for (int mb = 0; (part + split * kWv * mb) * 64 < ne; mb += kEnt) {
     int pkv[kEnt];
     C dv[kEnt];
     int sv[kEnt];
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
-      const int t0 = (rb + j * split) * kGridBlock;
-      if (t0 >= ne) break;  // the same for the whole workgroup
-      pkv[j] = E.off[e0 + min(t0 + tid, ne - 1)];
+      if (run0(mb + j) >= ne) break;  // the same for the whole wave
+      pkv[j] = E.off[e0 + min(run0(mb + j) + lane, ne - 1)];
     }
 #pragma unroll
     for (int j = 0; j < kEnt; j++) {
-      if ((rb + j * split) * kGridBlock >= ne) break;
+      if (run0(mb + j) >= ne) break;
       const int pk = pkv[j];
       sv[j] = site_of(G, wrap1(ox0 + off_x(pk), G.nx), wrap1(oy0 + off_y(pk), G.ny), wrap1(oz0 + off_z(pk), G.nz));
       dv[j] = drho[sv[j]];  // used only at an IS site the substep claims
     }
 #pragma unroll 1
     for (int j = 0; j < kEnt; j++) {
-      const int t = (rb + j * split) * kGridBlock + tid;
+      const int t = run0(mb + j) + lane;
       if (t >= ne) continue;
       const int e = e0 + t;
       const int pk = pkv[j];
@@ -2243,8 +2251,9 @@ double lattice_w(int q, int i) { return q == 9 ? Lattice<9>::w(i) : Lattice<19>:
 // Template of one particle (section 2.2): digitised ball |o - phi| <= r, BS
 // = ball sites linked (any lattice velocity) to a site outside the ball, IS =
 // other ball sites linked to a BS site, interior = the remaining ball sites.
-// Entries follow the ball in z, y, x order so that neighbouring threads of
-// the sparse kernels touch neighbouring sites.
+// Entries come kind by kind (BS, then IS, then interior), each kind in z, y,
+// x order so that neighbouring threads of the sparse kernels touch
+// neighbouring sites: the per-particle sums read the BS entries alone.
 void build_template(int q, double r, const double phi[3], std::vector<int>& out, int* nbs, int* nis, int* nin) {
   const int dim = q == 9 ? 2 : 3;
   const int R = (int)std::ceil(r) + 1;
@@ -2285,15 +2294,17 @@ void build_template(int q, double r, const double phi[3], std::vector<int>& out,
             break;
           }
       }
-  for (int z = -Rz; z <= Rz; z++)
-    for (int y = -R; y <= R; y++)
-      for (int x = -R; x <= R; x++) {
-        const size_t g = gi(x, y, z);
-        if (!in[g]) continue;
-        const int kind = bs[g] ? 1 : (is[g] ? 2 : 3);
-        out.push_back(pack_entry(x, y, z, kind));
-        (kind == 1 ? *nbs : kind == 2 ? *nis : *nin) += 1;
-      }
+  for (int want = 1; want <= 3; want++)
+    for (int z = -Rz; z <= Rz; z++)
+      for (int y = -R; y <= R; y++)
+        for (int x = -R; x <= R; x++) {
+          const size_t g = gi(x, y, z);
+          if (!in[g]) continue;
+          const int kind = bs[g] ? 1 : (is[g] ? 2 : 3);
+          if (kind != want) continue;
+          out.push_back(pack_entry(x, y, z, kind));
+          (kind == 1 ? *nbs : kind == 2 ? *nis : *nin) += 1;
+        }
 }
 
 // The owner map of the current shifts, for read-outs: contexts with kind
