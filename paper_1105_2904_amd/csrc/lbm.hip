@@ -717,14 +717,15 @@ __device__ __forceinline__ int div_exact(int n, int d, double inv) {
   return q + (r >= d) - (r < 0);
 }
 
-// Any number of boxes: a tile is blockDim.x consecutive sites of one box in
-// raster order (x fastest, running on into the next row), so every thread of
-// a tile but the box's last has a site and the tile's accesses are contiguous
-// whatever the box width.  Three records per tile: {box, first box-local
-// site, -, -}, the box's {nx, ny, nz, first site}, and 1/nx, 1/ny as FP64
-// bit pairs {lo, hi, lo, hi} for the split of a box-local index into (x, y,
-// z).  A persistent grid walks the tile list (the workgroup width, grid size
-// and occupancy cap are the tunable launch shape).
+// Any number of boxes: a tile is up to blockDim.x consecutive sites of one
+// box in raster order (x fastest, running on into the next row), starting at
+// a multiple of blockDim.x of the whole site range (a box's first tile may be
+// shorter), so the tile's accesses are contiguous whatever the box width and
+// its stores fill whole lines.  Three records per tile: {box, first box-local
+// site, one past its last, -}, the box's {nx, ny, nz, first site}, and 1/nx,
+// 1/ny as FP64 bit pairs {lo, hi, lo, hi} for the split of a box-local index
+// into (x, y, z).  A persistent grid walks the tile list (the workgroup
+// width, grid size and occupancy cap are the tunable launch shape).
 template <int Q, typename T, bool PART, int LAY, bool NTL>
 __global__ __launch_bounds__(kTileMax) void k_sweep_tiles(const T* A, T* B, SweepArgs<Q, typename Store<T>::C> a,
                                                            SiteArgs<T> sa,
@@ -746,7 +747,7 @@ __global__ __launch_bounds__(kTileMax) void k_sweep_tiles(const T* A, T* B, Swee
   for (int t = t0; t < ntiles; t += gridDim.x) {
     const int4 tl = tiles[3 * t], tg = tiles[3 * t + 1], ti = tiles[3 * t + 2];
     const int64_t lin64 = (int64_t)tl.y + threadIdx.x;
-    if (lin64 >= (int64_t)tg.x * tg.y * tg.z) continue;
+    if (lin64 >= tl.z) continue;  // past the tile's last site
     const int lin = (int)lin64;
     const int yz = div_exact(lin, tg.x, __hiloint2double(ti.y, ti.x));
     const int z = div_exact(yz, tg.y, __hiloint2double(ti.w, ti.z));
@@ -1774,7 +1775,7 @@ BoxSet make_boxset(int nbox, const int32_t* dims) {
   for (int i = 0; i < nbox; i++) {
     const int64_t nx = dims[3 * i], ny = dims[3 * i + 1], nz = dims[3 * i + 2];
     b.NT += nx * ny * nz;
-    b.max_tiles += (nx * ny * nz + kTileMin - 1) / kTileMin;
+    b.max_tiles += (nx * ny * nz + kTileMin - 1) / kTileMin + 1;  // + the short first tile
   }
   return b;
 }
@@ -2065,10 +2066,16 @@ int build_tiles(lbm_ctx* c, int w) {
     int4 inv;
     dbl_bits(1.0 / g.nx, inv.x, inv.y);
     dbl_bits(1.0 / g.ny, inv.z, inv.w);
-    for (int64_t s0 = 0; s0 < g.N; s0 += w) {
-      t.push_back(make_int4(b, (int)s0, 0, 0));
+    // tiles start at multiples of w of the whole site range, so that the
+    // streaming stores of a tile fill whole cache lines (boxes start
+    // anywhere); a box's first tile runs up to the first such multiple
+    const int64_t head = (w - g.off % w) % w;
+    for (int64_t s0 = 0; s0 < g.N;) {
+      const int64_t s1 = std::min<int64_t>(g.N, s0 == 0 && head > 0 ? head : s0 + w);
+      t.push_back(make_int4(b, (int)s0, (int)s1, 0));
       t.push_back(make_int4(g.nx, g.ny, g.nz, (int)g.off));
       t.push_back(inv);
+      s0 = s1;
     }
   }
   if ((int64_t)t.size() > 3 * c->L.max_tiles) return LBM_EINVAL;
