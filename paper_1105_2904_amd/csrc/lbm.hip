@@ -1550,10 +1550,12 @@ __global__ __launch_bounds__(kGridBlock) void k_prepare_grid(uint8_t* __restrict
   const double upx = P.u[3 * p], upy = P.u[3 * p + 1], upz = P.u[3 * p + 2];
   const double wx = P.om[3 * p], wy = P.om[3 * p + 1], wz = P.om[3 * p + 2];
   const C cupx = (C)upx, cupy = (C)upy, cupz = (C)upz, cwx = (C)wx, cwy = (C)wy, cwz = (C)wz;
-  const int e0 = P.ent0[p], ne = P.nbs[p] + P.nis[p] + P.nin[p];
   const bool jump = P.jump[p] != 0;
   const bool moved = P.moved[p] != 0;
   const bool flags = flags_all != 0 || moved;
+  // interior entries come last and only write flags: skipped when the flags
+  // stand as they are
+  const int e0 = P.ent0[p], ne = P.nbs[p] + P.nis[p] + (flags ? P.nin[p] : 0);
   const int nn = P.nbr_n[p];
   const int Rp = P.kgR[p];
   const uint8_t* kgp = P.kgrid + P.kg0[p];
