@@ -400,6 +400,101 @@ __device__ __forceinline__ C dot_c(int i, C vx, C vy, C vz) {
   return r;
 }
 
+// The 16-bit collision's arithmetic, which issue rate bounds more than the
+// FP32 sweep's (two sites per lane).  acc: s + v (sign > 0) or s - v into s,
+// the first term taken as it is -- 0 + v costs an addition the compiler must
+// keep (it is not v when v is -0); `any` is known at compile time wherever
+// the direction loops are unrolled.
+template <typename C>
+__device__ __forceinline__ void acc(C& s, bool& any, C v, int sign) {
+  if (sign > 0)
+    s = any ? s + v : v;
+  else
+    s = any ? s - v : -v;
+  any = true;
+}
+// c . v from the nonzero components only (0 for the rest direction).
+template <typename Lt, typename C>
+__device__ __forceinline__ C dot_c1(int i, C vx, C vy, C vz) {
+  C r = 0;
+  bool any = false;
+  if (Lt::cx(i) != 0) acc(r, any, vx, Lt::cx(i));
+  if (Lt::cy(i) != 0) acc(r, any, vy, Lt::cy(i));
+  if (Lt::cz(i) != 0) acc(r, any, vz, Lt::cz(i));
+  return r;
+}
+// Speed class |c_i|^2 of direction i (0, 1 or 2); D2Q9 and D3Q19 weigh every
+// direction of a class alike, class_w is that weight.
+template <typename Lt>
+__host__ __device__ constexpr int speed2(int i) {
+  return Lt::cx(i) * Lt::cx(i) + Lt::cy(i) * Lt::cy(i) + Lt::cz(i) * Lt::cz(i);
+}
+template <int Q>
+__host__ __device__ constexpr double class_w(int k) {
+  for (int i = 0; i < Q; i++)
+    if (speed2<Lattice<Q>>(i) == k) return Lattice<Q>::w(i);
+  return 0.0;
+}
+// The equilibrium (eq. 2) as the 16-bit number h_i^eq = e_i / sigma at
+// density deviation dr (rho = rho0 + dr) and velocity v with usq = 3/2 v.v,
+// e_i = dr + rho (3 cu + 9/2 cu^2) - rho usq: the weight cancels, so it is
+// kA + cu (kB + kC cu) with three constants per site, two multiply-adds per
+// moving direction and none for the rest direction.
+template <int Q, typename C>
+struct Feq16 {
+  C kA, kB, kC;
+  __device__ __forceinline__ Feq16(C dr, C rho, C usq, C inv_sig) {
+#pragma clang fp contract(off)
+    kA = inv_sig * fmac(-rho, usq, dr);
+    kB = inv_sig * C(3) * rho;
+    kC = inv_sig * C(4.5) * rho;
+  }
+  __device__ __forceinline__ C operator()(int i, C vx, C vy, C vz) const {
+#pragma clang fp contract(off)
+    using L = Lattice<Q>;
+    if (speed2<L>(i) == 0) return kA;
+    const C cu = dot_c1<L>(i, vx, vy, vz);
+    return fmac(fmac(kC, cu, kB), cu, kA);
+  }
+};
+// Sums of 16-bit stored numbers h_i per speed class -- the weight is one per
+// class, so g_i = h_i w_i sigma needs one product per class -- into the
+// density deviation and momentum of the compute type D.
+template <int Q, typename T, typename D, typename C>
+__device__ __forceinline__ void moments16(const C (&h)[Q], D& dr, D& jx, D& jy, D& jz) {
+#pragma clang fp contract(off)
+  using L = Lattice<Q>;
+  D sk[3] = {0, 0, 0}, jk[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  bool hs[3] = {false, false, false};
+  bool hj[3][3] = {{false, false, false}, {false, false, false}, {false, false, false}};
+#pragma unroll
+  for (int i = 0; i < Q; i++) {
+    const int k = speed2<L>(i);
+    const D v = (D)h[i];
+    acc(sk[k], hs[k], v, 1);
+    if (L::cx(i) != 0) acc(jk[k][0], hj[k][0], v, L::cx(i));
+    if (L::cy(i) != 0) acc(jk[k][1], hj[k][1], v, L::cy(i));
+    if (L::cz(i) != 0) acc(jk[k][2], hj[k][2], v, L::cz(i));
+  }
+  D* const out[3] = {&jx, &jy, &jz};
+  bool hd = false, hm[3] = {false, false, false};
+  dr = jx = jy = jz = 0;
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    const D uk = (D)pop_unit<T>(class_w<Q>(k));
+    if (hs[k]) {
+      dr = hd ? fmac(uk, sk[k], dr) : uk * sk[k];
+      hd = true;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      if (!hj[k][a]) continue;
+      *out[a] = hm[a] ? fmac(uk, jk[k][a], *out[a]) : uk * jk[k][a];
+      hm[a] = true;
+    }
+  }
+}
+
 // Collision of one site from the populations g it pulled, in place: BGK with
 // body force (eq. 1-3), the site's density deviation kept at ball sites, the
 // BS substep at an owned BS site (eq. 5-7; its post-collision moments to the
@@ -432,28 +527,32 @@ __device__ __forceinline__ void collide_site(typename Store<T>::C (&g)[Q],
   constexpr bool kRaw = std::is_same<T, _Float16>::value || std::is_same<T, bf16s>::value;
   const C inv_sig = (C)(1.0 / pop_unit<T>(1.0));
   C drho = 0, jx = 0, jy = 0, jz = 0;
+  if constexpr (kRaw) {
+    moments16<Q, T>(g, drho, jx, jy, jz);
+  } else {
 #pragma unroll
-  for (int i = 0; i < Q; i++) {
-    const C v = kRaw ? g[i] * (C)pop_unit<T>(L::w(i)) : g[i];
-    drho += v;
-    if (L::cx(i) > 0) jx += v;
-    if (L::cx(i) < 0) jx -= v;
-    if (L::cy(i) > 0) jy += v;
-    if (L::cy(i) < 0) jy -= v;
-    if (L::cz(i) > 0) jz += v;
-    if (L::cz(i) < 0) jz -= v;
+    for (int i = 0; i < Q; i++) {
+      const C v = g[i];
+      drho += v;
+      if (L::cx(i) > 0) jx += v;
+      if (L::cx(i) < 0) jx -= v;
+      if (L::cy(i) > 0) jy += v;
+      if (L::cy(i) < 0) jy -= v;
+      if (L::cz(i) > 0) jz += v;
+      if (L::cz(i) < 0) jz -= v;
+    }
   }
   const C rho = a.rho0 + drho;
   const C inv = recip(rho);
   const C ux = jx * inv, uy = jy * inv, uz = jz * inv;
   const C usq = C(1.5) * fmac(ux, ux, fmac(uy, uy, uz * uz));
   if constexpr (kRaw) {
-    const C kA = inv_sig * fmac(-rho, usq, drho), kB = inv_sig * C(3) * rho, kC = inv_sig * C(4.5) * rho;
+    const Feq16<Q, C> fe(drho, rho, usq, inv_sig);
 #pragma unroll
     for (int i = 0; i < Q; i++) {
-      const C cu = dot_c<L>(i, ux, uy, uz);
-      const C he = fmac(fmac(kC, cu, kB), cu, kA);
-      g[i] = fmac(fbt[i], (C)(1.0 / pop_unit<T>(L::w(i))), fmac(a.omega, he - g[i], g[i]));
+      const C r = fmac(a.omega, fe(i, ux, uy, uz) - g[i], g[i]);
+      // the body-force term 3 w_i c_i . f_b, in stored units (0 at rest)
+      g[i] = speed2<L>(i) == 0 ? r : fmac(fbt[i], (C)(1.0 / pop_unit<T>(L::w(i))), r);
     }
   } else {
 #pragma unroll
@@ -472,16 +571,20 @@ __device__ __forceinline__ void collide_site(typename Store<T>::C (&g)[Q],
       const C vx = rec.x, vy = rec.y, vz = rec.z;
       const int bs = as_idx<C>(rec.w);
       double dr = 0, bx = 0, by = 0, bz = 0;
+      if constexpr (kRaw) {
+        moments16<Q, T>(g, dr, bx, by, bz);
+      } else {
 #pragma unroll
-      for (int i = 0; i < Q; i++) {
-        const double v = kRaw ? (double)g[i] * pop_unit<T>(L::w(i)) : (double)g[i];
-        dr += v;
-        if (L::cx(i) > 0) bx += v;
-        if (L::cx(i) < 0) bx -= v;
-        if (L::cy(i) > 0) by += v;
-        if (L::cy(i) < 0) by -= v;
-        if (L::cz(i) > 0) bz += v;
-        if (L::cz(i) < 0) bz -= v;
+        for (int i = 0; i < Q; i++) {
+          const double v = (double)g[i];
+          dr += v;
+          if (L::cx(i) > 0) bx += v;
+          if (L::cx(i) < 0) bx -= v;
+          if (L::cy(i) > 0) by += v;
+          if (L::cy(i) < 0) by -= v;
+          if (L::cz(i) > 0) bz += v;
+          if (L::cz(i) < 0) bz -= v;
+        }
       }
       if ((unsigned)bs < (unsigned)sa.nent) {
         double* sl = sa.slot + 4 * (size_t)bs;
@@ -497,11 +600,16 @@ __device__ __forceinline__ void collide_site(typename Store<T>::C (&g)[Q],
       const C drB = (C)dr;
       const C rhoB = a.rho0 + drB;
       const C usqB = C(1.5) * fmac(vx, vx, fmac(vy, vy, vz * vz));
+      if constexpr (kRaw) {
+        const Feq16<Q, C> fe(drB, rhoB, usqB, inv_sig);
 #pragma unroll
-      for (int i = 0; i < Q; i++) {
-        const C cu = dot_c<L>(i, vx, vy, vz);
-        const C e = fmac(rhoB, fmac(C(4.5) * cu, cu, fmac(C(3), cu, -usqB)), drB);
-        g[i] = kRaw ? inv_sig * e : C(L::w(i)) * e;
+        for (int i = 0; i < Q; i++) g[i] = fe(i, vx, vy, vz);
+      } else {
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+          const C cu = dot_c<L>(i, vx, vy, vz);
+          g[i] = C(L::w(i)) * fmac(rhoB, fmac(C(4.5) * cu, cu, fmac(C(3), cu, -usqB)), drB);
+        }
       }
     }
   }
@@ -511,11 +619,16 @@ __device__ __forceinline__ void collide_site(typename Store<T>::C (&g)[Q],
     C vx, vy, vz;
     if (wall_velocity(a, x, y, z, nx, ny, nz, vx, vy, vz)) {
       const C usqW = C(1.5) * fmac(vx, vx, fmac(vy, vy, vz * vz));
+      if constexpr (kRaw) {
+        const Feq16<Q, C> fe(drho, rho, usqW, inv_sig);
 #pragma unroll
-      for (int i = 0; i < Q; i++) {
-        const C cu = dot_c<L>(i, vx, vy, vz);
-        const C e = fmac(rho, fmac(C(4.5) * cu, cu, fmac(C(3), cu, -usqW)), drho);
-        g[i] = kRaw ? inv_sig * e : C(L::w(i)) * e;
+        for (int i = 0; i < Q; i++) g[i] = fe(i, vx, vy, vz);
+      } else {
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+          const C cu = dot_c<L>(i, vx, vy, vz);
+          g[i] = C(L::w(i)) * fmac(rho, fmac(C(4.5) * cu, cu, fmac(C(3), cu, -usqW)), drho);
+        }
       }
     }
   }
@@ -1426,14 +1539,20 @@ __device__ __forceinline__ void impose_is(T* __restrict__ S, int lay, const Geo&
   const C dc = (C)dr;
   const C rho = (C)rho0 + dc;
   const C usq = C(1.5) * fmac(vx, vx, fmac(vy, vy, vz * vz));
+  [[maybe_unused]] const Feq16<Q, C> fe(dc, rho, usq, inv_sig);
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     // f^eq_i - w_i rho0 as the sweep's BS substep writes it: for 16-bit
     // storage the stored number directly (the weight cancels), so the
     // encoding is one rounding of a compute-type value
-    const C cu = dot_c<L>(i, vx, vy, vz);
-    const C e = fmac(rho, fmac(C(4.5) * cu, cu, fmac(C(3), cu, -usq)), dc);
-    const T v = store_enc<T>(kRaw ? inv_sig * e : C(L::w(i)) * e);
+    C e;
+    if constexpr (kRaw) {
+      e = fe(i, vx, vy, vz);
+    } else {
+      const C cu = dot_c<L>(i, vx, vy, vz);
+      e = C(L::w(i)) * fmac(rho, fmac(C(4.5) * cu, cu, fmac(C(3), cu, -usq)), dc);
+    }
+    const T v = store_enc<T>(e);
     T* const dst = S + coll_index<Q>(lay, i, G, x, y, z);
     // NTS (the AA pattern, whose next sweep reads and rewrites these lines in
     // place): streaming stores keep the partly written lines out of the
