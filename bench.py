@@ -391,7 +391,7 @@ def main():
         timed region."""
         sim_.step(warmup)
         if not args.no_autotune:
-            sim_.autotune_steps(steps=4)
+            sim_.autotune_steps(steps=16)
             sim_.step(2)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()

@@ -129,6 +129,10 @@ __host__ __device__ inline uint16_t f32_to_bf16_bits(float f) {
   u += 0x7fffu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
 }
+// The same rounding on the device, where gfx950 converts in one instruction
+// (v_cvt_pk_bf16_f32, round to nearest even); the two agree on every finite
+// value.
+__device__ __forceinline__ uint16_t bf16_rne(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __host__ __device__ inline float bf16_bits_to_f32(uint16_t h) {
   const uint32_t u = (uint32_t)h << 16;
   float f;
@@ -143,7 +147,7 @@ struct Store<bf16s> {
     return bf16_bits_to_f32(__builtin_nontemporal_load(&p->v));
   }
   static __device__ __forceinline__ void st(bf16s* p, float v) {
-    __builtin_nontemporal_store(f32_to_bf16_bits(v), (uint16_t*)p);
+    __builtin_nontemporal_store(bf16_rne(v), (uint16_t*)p);
   }
 };
 
@@ -170,7 +174,7 @@ __device__ __forceinline__ void pop_st(T* p, int i, typename Store<T>::C v) {
 template <typename T>
 __device__ __forceinline__ T store_enc(typename Store<T>::C h) {
   if constexpr (std::is_same<T, bf16s>::value)
-    return bf16s{f32_to_bf16_bits(h)};
+    return bf16s{bf16_rne(h)};
   else
     return (T)h;
 }
@@ -413,15 +417,20 @@ __device__ __forceinline__ void acc(C& s, bool& any, C v, int sign) {
     s = any ? s - v : -v;
   any = true;
 }
-// c . v from the nonzero components only (0 for the rest direction).
+// c . v from the nonzero components only (0 for the rest direction).  A
+// direction whose first nonzero component is negative takes minus its
+// opposite's value, the same number ((-a) - b = -(a + b)), which the compiler
+// then computes once per opposite pair.
 template <typename Lt, typename C>
 __device__ __forceinline__ C dot_c1(int i, C vx, C vy, C vz) {
+  const int lead = Lt::cx(i) != 0 ? Lt::cx(i) : (Lt::cy(i) != 0 ? Lt::cy(i) : Lt::cz(i));
+  const int sg = lead < 0 ? -1 : 1;
   C r = 0;
   bool any = false;
-  if (Lt::cx(i) != 0) acc(r, any, vx, Lt::cx(i));
-  if (Lt::cy(i) != 0) acc(r, any, vy, Lt::cy(i));
-  if (Lt::cz(i) != 0) acc(r, any, vz, Lt::cz(i));
-  return r;
+  if (Lt::cx(i) != 0) acc(r, any, vx, sg * Lt::cx(i));
+  if (Lt::cy(i) != 0) acc(r, any, vy, sg * Lt::cy(i));
+  if (Lt::cz(i) != 0) acc(r, any, vz, sg * Lt::cz(i));
+  return sg < 0 ? -r : r;
 }
 // Speed class |c_i|^2 of direction i (0, 1 or 2); D2Q9 and D3Q19 weigh every
 // direction of a class alike, class_w is that weight.
@@ -459,7 +468,12 @@ struct Feq16 {
 };
 // Sums of 16-bit stored numbers h_i per speed class -- the weight is one per
 // class, so g_i = h_i w_i sigma needs one product per class -- into the
-// density deviation and momentum of the compute type D.
+// density deviation and momentum of the compute type D.  Each opposite pair
+// (i, -i) enters as h_i + h_-i (the density) and h_i - h_-i (the momentum).
+template <typename Lt>
+__host__ __device__ constexpr bool lead_positive(int i) {
+  return Lt::cx(i) != 0 ? Lt::cx(i) > 0 : (Lt::cy(i) != 0 ? Lt::cy(i) > 0 : Lt::cz(i) > 0);
+}
 template <int Q, typename T, typename D, typename C>
 __device__ __forceinline__ void moments16(const C (&h)[Q], D& dr, D& jx, D& jy, D& jz) {
 #pragma clang fp contract(off)
@@ -470,11 +484,17 @@ __device__ __forceinline__ void moments16(const C (&h)[Q], D& dr, D& jx, D& jy, 
 #pragma unroll
   for (int i = 0; i < Q; i++) {
     const int k = speed2<L>(i);
-    const D v = (D)h[i];
-    acc(sk[k], hs[k], v, 1);
-    if (L::cx(i) != 0) acc(jk[k][0], hj[k][0], v, L::cx(i));
-    if (L::cy(i) != 0) acc(jk[k][1], hj[k][1], v, L::cy(i));
-    if (L::cz(i) != 0) acc(jk[k][2], hj[k][2], v, L::cz(i));
+    if (k == 0) {
+      acc(sk[0], hs[0], (D)h[i], 1);
+      continue;
+    }
+    if (!lead_positive<L>(i)) continue;  // taken with its opposite
+    const D a = (D)h[i], b = (D)h[opposite<Q>(i)];
+    const D ps = a + b, ms = a - b;
+    acc(sk[k], hs[k], ps, 1);
+    if (L::cx(i) != 0) acc(jk[k][0], hj[k][0], ms, L::cx(i));
+    if (L::cy(i) != 0) acc(jk[k][1], hj[k][1], ms, L::cy(i));
+    if (L::cz(i) != 0) acc(jk[k][2], hj[k][2], ms, L::cz(i));
   }
   D* const out[3] = {&jx, &jy, &jz};
   bool hd = false, hm[3] = {false, false, false};
@@ -717,12 +737,19 @@ __device__ __forceinline__ float half_lo(uint32_t v) {
   else
     return bf16_bits_to_f32((uint16_t)(v & 0xffffu));
 }
+// Two compute-type values rounded to the storage type (nearest even) and
+// packed, lo in the low half: one conversion instruction for both.
 template <typename T>
-__device__ __forceinline__ uint32_t half_bits(float v) {
-  if constexpr (std::is_same<T, _Float16>::value)
-    return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)v);
-  else
-    return (uint32_t)f32_to_bf16_bits(v);
+__device__ __forceinline__ uint32_t pack_halves(float lo, float hi) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  const f2 v = {lo, hi};
+  if constexpr (std::is_same<T, _Float16>::value) {
+    typedef _Float16 t2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, t2));
+  } else {
+    typedef __bf16 t2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, t2));
+  }
 }
 constexpr int kPairRow = 128;  // sites of a row per wave of k_sweep_pairs
 // Index of population i among those with c_x != 0 (and their count, i = Q).
@@ -817,7 +844,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep_pairs(const T* __restrict
   if (act) {
 #pragma unroll
     for (int i = 0; i < Q; i++)
-      __builtin_nontemporal_store(half_bits<T>(ga[i]) | (half_bits<T>(gb[i]) << 16), (uint32_t*)pop_at<Q, T>(B, i, s));
+      __builtin_nontemporal_store(pack_halves<T>(ga[i], gb[i]), (uint32_t*)pop_at<Q, T>(B, i, s));
   }
 }
 
