@@ -267,10 +267,11 @@ class Simulation:
                                   ctypes.byref(ms)), "lbm_autotune")
         return w.value, g.value, k.value, ms.value
 
-    def autotune_steps(self, steps=4):
-        """Picks and sets the fastest sweep launch timed inside whole steps;
-        returns (width, grid, blocks_per_cu, ms per step, steps it advanced the
-        simulation by)."""
+    def autotune_steps(self, steps=16):
+        """Picks and sets the fastest sweep launch timed inside whole steps
+        (`steps` per candidate: launches a percent apart need about 16 to rank
+        reliably); returns (width, grid, blocks_per_cu, ms per step, steps it
+        advanced the simulation by)."""
         w, g, k, ms, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double(), ctypes.c_int64()
         _check(lib().lbm_autotune_steps(self.ctx, int(steps), ctypes.byref(w), ctypes.byref(g), ctypes.byref(k),
                                         ctypes.byref(ms), ctypes.byref(n)), "lbm_autotune_steps")
