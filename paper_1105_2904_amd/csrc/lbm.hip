@@ -1762,7 +1762,9 @@ __global__ __launch_bounds__(kGridBlock) void k_prepare_grid(uint8_t* __restrict
       if (run0(mb + j) >= ne) break;
       const int pk = pkv[j];
       sv[j] = site_of(G, wrap1(ox0 + off_x(pk), G.nx), wrap1(oy0 + off_y(pk), G.ny), wrap1(oz0 + off_z(pk), G.nz));
-      dv[j] = drho[sv[j]];  // used only at an IS site the substep claims
+      // used only at an IS site the substep claims: runs of BS entries (the
+      // first of a particle's entries) load nothing
+      dv[j] = entry_kind(pk) == 2 ? drho[sv[j]] : C(0);
     }
 #pragma unroll 1
     for (int j = 0; j < kEnt; j++) {
